@@ -1,0 +1,492 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a library
+routine, a closed form, an invariant, brute force on a tiny input or the
+convergence behaviour the paper proves (Thm. 1) and reports (Sec. 6.1).
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2202_04894_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- kernel / direct sum
+def test_direct_sum_single_source_closed_form():
+    """eq. fmmsum with one source: p = exp(i k r)/(4 pi r) q (Sec. 1 kernel)."""
+    Y = np.array([[0.1, -0.2, 0.3]])
+    q = np.array([0.7 - 0.4j])
+    r = np.array([0.5, 1.0, 2.5])
+    X = Y + np.stack([r, 0 * r, 0 * r], axis=1)
+    for kappa in (0.0, 3.0):
+        p = oracle.direct_sum(X, Y, q, kappa, 1e-12)
+        ref = np.exp(1j * kappa * r) / (4 * np.pi * r) * q[0]
+        np.testing.assert_allclose(p, ref, rtol=1e-15, atol=0)
+
+
+def test_direct_sum_solves_helmholtz_and_skips_coincident_points():
+    """The potential of a source satisfies (Delta + k^2) p = 0 away from it, and a
+    coincident pair contributes nothing (the singularity rule of Sec. 5.3)."""
+    kappa = 5.0
+    Y = np.array([[0.0, 0.0, 0.0], [0.3, 0.2, -0.1]])
+    q = np.array([1.0 + 0.5j, -0.3 + 0.2j])
+    x0 = np.array([0.9, -0.7, 0.4])
+    hstep = 1e-3
+    pts = [x0]
+    for d in range(3):
+        for s in (-1, 1):
+            e = np.zeros(3); e[d] = s * hstep
+            pts.append(x0 + e)
+    p = oracle.direct_sum(np.array(pts), Y, q, kappa, 1e-12)
+    lap = (p[1:].sum() - 6 * p[0]) / hstep ** 2
+    assert abs(lap + kappa ** 2 * p[0]) < 1e-4 * abs(kappa ** 2 * p[0])
+    # coincident target and source: excluded
+    p = oracle.direct_sum(Y[:1], Y, q, kappa, 1e-12)
+    r = np.linalg.norm(Y[1] - Y[0])
+    np.testing.assert_allclose(p[0], np.exp(1j * kappa * r) / (4 * np.pi * r) * q[1], rtol=1e-15)
+
+
+# ---------------------------------------------------------------- interpolation
+@pytest.mark.parametrize("L", [2, 3, 4, 5, 6, 7, 8])
+def test_lagrange_equispaced_reproduces_polynomials(L):
+    """Sec. 2.3: equispaced nodes k/(L-1) including both faces; the basis is
+    cardinal at the nodes and reproduces every polynomial of degree < L
+    (compared with numpy's least-squares polynomial fit, exact here)."""
+    nodes = np.arange(L) / (L - 1)
+    for k, t in enumerate(nodes):
+        np.testing.assert_allclose(oracle.lagrange_1d(L, t), np.eye(L)[k], atol=1e-13)
+    rng = np.random.default_rng(L)
+    coef = rng.standard_normal(L)
+    f_nodes = np.polynomial.polynomial.polyval(nodes, coef)
+    fit = np.polynomial.polynomial.polyfit(nodes, f_nodes, L - 1)
+    for t in rng.uniform(0, 1, 7):
+        interp = oracle.lagrange_1d(L, t) @ f_nodes
+        assert abs(interp - np.polynomial.polynomial.polyval(t, fit)) < 1e-11
+        assert abs(interp - np.polynomial.polynomial.polyval(t, coef)) < 1e-11
+
+
+@pytest.mark.parametrize("L", [2, 3, 4, 5, 6, 7])
+def test_lemma1_node_polynomial_bound(L):
+    """Lemma 1: omega_L <= (2a/(L-1))^L / (4L) for L equispaced nodes on [-a, a].
+    The nodes are those the oracle's basis is cardinal on."""
+    a = 1.0
+    t = np.linspace(0, 1, 20001)
+    nodes = np.array([k / (L - 1) for k in range(L)
+                      if abs(oracle.lagrange_1d(L, k / (L - 1))[k] - 1) < 1e-14])
+    assert nodes.size == L
+    x = -a + 2 * a * t
+    xn = -a + 2 * a * nodes
+    prod = np.abs(np.prod(x[:, None] - xn[None, :], axis=1)).max()
+    import math
+    omega = prod / math.factorial(L)
+    assert omega <= (2 * a / (L - 1)) ** L / (4 * L) * (1 + 1e-12)
+
+
+# ---------------------------------------------------------------- directions
+def test_directions_golden_E0_E1():
+    """Sec. 4.1.2: face centres of the cube (E=0) and of its 2x2-split faces (E=1)."""
+    rows = np.loadtxt(os.path.join(GOLDEN, "directions_E0_E1.txt"))
+    for E in (0, 1):
+        d, f = oracle.directions(E)
+        g = rows[rows[:, 0] == E]
+        np.testing.assert_allclose(d, g[:, 2:5], atol=1e-15)
+        np.testing.assert_array_equal(f, g[:, 5].astype(np.int64))
+
+
+@pytest.mark.parametrize("E", [0, 1, 2, 3, 4])
+def test_direction_tree_nested(E):
+    """Sec. 2.1: every direction at level E is the son of exactly one direction at
+    level E-1; sons lie in the father's face patch; 6 * 4^E unit vectors."""
+    d, f = oracle.directions(E)
+    assert d.shape[0] == 6 * 4 ** E
+    np.testing.assert_allclose(np.linalg.norm(d, axis=1), 1.0, atol=1e-15)
+    assert len(np.unique(np.round(d, 12), axis=0)) == d.shape[0]
+    if E == 0:
+        assert (f == -1).all()
+        return
+    dp, _ = oracle.directions(E - 1)
+    counts = np.bincount(f, minlength=dp.shape[0])
+    assert (counts == 4).all()
+    # the father's patch contains the son: project both on the cube surface
+    def face_coords(v):
+        a = np.argmax(np.abs(v), axis=1)
+        return a, v / np.abs(v[np.arange(len(v)), a])[:, None]
+    a_s, p_s = face_coords(d)
+    a_f, p_f = face_coords(dp[f])
+    assert (a_s == a_f).all()
+    half = 1.0 / 2 ** (E - 1)
+    assert (np.abs(p_s - p_f) <= half + 1e-12).all()
+    # a son is closer to its father than to any other direction of level E-1
+    best = np.argmax(d @ dp.T, axis=1)
+    assert (best == f).mean() > 0.9
+
+
+# ---------------------------------------------------------------- DFT / circulant M2L
+@pytest.mark.parametrize("P", [3, 7, 9, 11])
+def test_dft3_matches_numpy(P):
+    """The DFT of eq. DFTformula (forward sign -1, no normalisation) is numpy.fft.fftn."""
+    rng = np.random.default_rng(P)
+    a = rng.standard_normal((P, P, P)) + 1j * rng.standard_normal((P, P, P))
+    np.testing.assert_allclose(oracle.dft3(a, -1), np.fft.fftn(a), rtol=0, atol=1e-11 * P ** 3)
+    np.testing.assert_allclose(oracle.dft3(a, +1), np.fft.ifftn(a) * P ** 3, rtol=0,
+                               atol=1e-11 * P ** 3)
+
+
+@pytest.mark.parametrize("L", [2, 3, 4, 5, 6])
+@pytest.mark.parametrize("kappa", [0.0, 7.0, 40.0])
+def test_circulant_m2l_equals_dense_m2l(L, kappa):
+    """eqs. FactorizedM2LMatrix1 / FourierDiagonal: the FFT-diagonal M2L (zero
+    padding, Hadamard product with fftn of the circulant column, inverse DFT and
+    restriction) equals the dense M2L sum_l G(x_k - y_l) M(y_l)."""
+    rng = np.random.default_rng(L * 100 + int(kappa))
+    h = 0.25
+    for delta in [(2, 0, 0), (-2, 3, 1), (0, -4, 2), (5, 5, -5)]:
+        M = rng.standard_normal(L ** 3) + 1j * rng.standard_normal(L ** 3)
+        a = oracle.m2l_fft(kappa, h, L, delta, M)
+        b = oracle.m2l_dense(kappa, h, L, delta, M)
+        assert np.linalg.norm(a - b) <= 1e-13 * np.linalg.norm(b)
+
+
+def test_dense_m2l_brute_force_nodes():
+    """The dense M2L is the kernel between the equispaced node grids of two cells of
+    side h at integer offset delta (Sec. 2.3, eq. NormalizedKernel), written out with
+    explicit node coordinates."""
+    L, h, kappa = 3, 0.5, 3.0
+    delta = np.array([2, -1, 3])
+    rng = np.random.default_rng(5)
+    M = rng.standard_normal(L ** 3) + 1j * rng.standard_normal(L ** 3)
+    alpha_s = np.array([0.1, 0.2, -0.3])
+    alpha_t = alpha_s + h * delta
+    g = np.arange(L) / (L - 1)
+    nodes = np.array([[g[kx], g[ky], g[kz]] for kz in range(L) for ky in range(L) for kx in range(L)])
+    xt = alpha_t + h * nodes
+    ys = alpha_s + h * nodes
+    ref = oracle.direct_sum(xt, ys, M, kappa, 1e-12)
+    np.testing.assert_allclose(oracle.m2l_dense(kappa, h, L, delta, M), ref, rtol=1e-13)
+
+
+def _signed_perms():
+    for perm in itertools.permutations(range(3)):
+        for signs in itertools.product((1, -1), repeat=3):
+            R = np.zeros((3, 3), dtype=int)
+            for i in range(3):
+                R[i, perm[i]] = signs[i]
+            yield R
+
+
+@pytest.mark.parametrize("L", [3, 4])
+def test_spectrum_hyperoctahedral_symmetry(L):
+    """eq. permuteM2L: D[G o R*] = D[G] o R*; with R acting on the offset, the
+    diagonal of the rotated M2L operator is the original diagonal read at R^-1 xi
+    (mod P).  All 48 signed permutations apply since G depends on |z| only."""
+    P = 2 * L - 1
+    kappa, h = 9.0, 0.5
+    delta = np.array([3, -2, 2])
+    D0 = oracle.spectrum(kappa, h, L, delta)  # [mz, my, mx]
+    xi = np.stack(np.meshgrid(np.arange(P), np.arange(P), np.arange(P), indexing="ij"), -1)
+    xi = xi[..., ::-1]  # (x, y, z) components for index [mz, my, mx]
+    nperm = 0
+    for R in _signed_perms():
+        DR = oracle.spectrum(kappa, h, L, R @ delta)
+        src = np.einsum("ij,...j->...i", R.T, xi) % P  # R^-1 = R^T
+        ref = D0[src[..., 2], src[..., 1], src[..., 0]]
+        assert np.abs(DR - ref).max() <= 1e-13 * np.abs(D0).max()
+        nperm += 1
+    assert nperm == 48
+
+
+# ---------------------------------------------------------------- whole FMM
+def _fmm_error(X, q, kappa, prm, targets=None, Y=None, qY=None):
+    F = oracle.FMM(X, Y, kappa, prm)
+    p = F.apply(q if Y is None else qY)
+    D, _ = F.geometry()
+    src = X if Y is None else Y
+    qq = q if Y is None else qY
+    pd = oracle.direct_sum(X, src, qq, kappa, 1e-12 * D, targets)
+    pe = p if targets is None else p[targets]
+    return np.linalg.norm(pe - pd) / np.linalg.norm(pd), F, p
+
+
+def test_root_leaf_is_direct_sum():
+    """Alg. 1 with N <= Ncrit: the root pair is not admissible and the root is a
+    leaf, so the FMM is one P2P = the direct sum."""
+    X = W.sphere(60, 11)
+    q = W.charges(60, 12)
+    err, F, _ = _fmm_error(X, q, 20.0, oracle.Params(L=4, ncrit=64))
+    assert F.info()["m2l_pairs"] == 0
+    assert err < 1e-15
+    # separate target and source sets
+    Y = W.sphere(50, 13)
+    qY = W.charges(50, 14)
+    err, _, _ = _fmm_error(X, None, 20.0, oracle.Params(L=4, ncrit=64), Y=Y, qY=qY)
+    assert err < 1e-15
+
+
+def test_traversal_covers_every_pair_exactly_once():
+    """Alg. 1: every (x, y) pair is handled by exactly one M2L or one P2P (brute force)."""
+    n = 1200
+    X = W.sphere(n, 21)
+    for kappa, prm in [(0.0, oracle.Params(L=3, ncrit=8)),
+                       (40.0, oracle.Params(L=3, ncrit=8, hf_threshold=1.0, eta=0.7))]:
+        F = oracle.FMM(X, None, kappa, prm)
+        cells = F.cells(0)
+        perm = F.perm(0)
+        pos = np.empty(n, dtype=np.int64)
+        pos[perm] = np.arange(n)
+        cover = np.zeros((n, n), dtype=np.int32)
+        m = F.m2l()
+        pp = F.p2p()
+        for t, s in list(zip(m["t"], m["s"])) + list(zip(pp["t"], pp["s"])):
+            a, b = cells["first"][t], cells["first"][t] + cells["count"][t]
+            c, d = cells["first"][s], cells["first"][s] + cells["count"][s]
+            cover[a:b, c:d] += 1
+        assert (cover == 1).all()
+        # M2L pairs are same-level, admissible by eq. macdirref, with delta = t - s
+        lev = cells["level"]
+        assert (lev[m["t"]] == lev[m["s"]]).all()
+        np.testing.assert_array_equal(m["delta"], cells["ijk"][m["t"]] - cells["ijk"][m["s"]])
+        D, _ = F.geometry()
+        for L_, d in zip(m["level"], m["delta"]):
+            w = D / 2 ** (L_ + 1)
+            nvec = np.maximum(np.abs(d) - 1, 0)
+            dist = 2 * w * np.linalg.norm(nvec)
+            assert max(kappa * w * w, 2 * w) <= prm.eta * dist * (1 + 1e-12)
+
+
+def test_tree_is_ncrit_morton():
+    """Sec. 4.2.1: Morton-sorted points, a cell is split iff it holds > Ncrit points,
+    empty cells are not stored, sons are contiguous sub-ranges of the father."""
+    X = W.ellipsoid(3000, 5)
+    F = oracle.FMM(X, None, 10.0, oracle.Params(L=3, ncrit=20))
+    c = F.cells(0)
+    D, o = F.geometry()
+    perm = F.perm(0)
+    pts = X[perm]
+    assert (c["count"] > 0).all()
+    assert ((c["count"] <= 20) == (c["is_leaf"] == 1)).all()
+    h = D / 2.0 ** c["level"]
+    for i in range(len(c["level"])):
+        sl = pts[c["first"][i]:c["first"][i] + c["count"][i]]
+        lo = o + h[i] * c["ijk"][i]
+        assert (sl >= lo - 1e-12).all() and (sl <= lo + h[i] + 1e-12).all()
+    for lev in range(1, c["level"].max() + 1):
+        sel = np.where(c["level"] == lev)[0]
+        assert (np.diff(c["first"][sel]) > 0).all()
+
+
+def _nodes(cell_level, ijk, D, o, L):
+    h = D / 2.0 ** cell_level
+    g = np.arange(L) / (L - 1)
+    k = np.array([[g[kx], g[ky], g[kz]] for kz in range(L) for ky in range(L) for kx in range(L)])
+    return o + h * np.asarray(ijk) + h * k
+
+
+def test_multipole_moments_preserved():
+    """P2M/M2M (Sec. 2.2) are interpolations: for f of degree < L per variable,
+    sum_r M(y_r) f(y_r) equals sum_y q(y) f(y) over the cell (low frequency), and for a
+    directional leaf expansion sum_r M^u(y_r) e^{-ik<y_r,u>} f(y_r) equals
+    sum_y q(y) e^{-ik<y,u>} f(y).  Nodes are built here from their definition."""
+    L = 4
+    X = W.sphere(3000, 31)
+    q = W.charges(3000, 32)
+    rng = np.random.default_rng(3)
+    for kappa, prm in [(0.0, oracle.Params(L=L, ncrit=16)),
+                       (30.0, oracle.Params(L=L, ncrit=16, hf_threshold=1.0))]:
+        F = oracle.FMM(X, None, kappa, prm)
+        F.apply(q)
+        ex = F.expansions(0)
+        c = F.cells(0)
+        D, o = F.geometry()
+        perm = F.perm(0)
+        pts, qs = X[perm], q[perm]
+        lstar = F.info()["lstar"]
+        checked = 0
+        for e in rng.choice(len(ex["cell"]), size=min(60, len(ex["cell"])), replace=False):
+            ci, u = ex["cell"][e], ex["dir"][e]
+            if u >= 0 and not c["is_leaf"][ci]:
+                continue
+            nd = _nodes(c["level"][ci], c["ijk"][ci], D, o, L)
+            sl = slice(c["first"][ci], c["first"][ci] + c["count"][ci])
+            y, qy = pts[sl], qs[sl]
+            if u >= 0:
+                E = lstar - c["level"][ci]
+                dirs, _ = oracle.directions(E)
+                ph_n = np.exp(-1j * kappa * nd @ dirs[u])
+                ph_y = np.exp(-1j * kappa * y @ dirs[u])
+            else:
+                ph_n, ph_y = 1.0, 1.0
+            for powers in [(0, 0, 0), (1, 0, 0), (0, 2, 1), (3, 3, 3), (1, 2, 3)]:
+                fn = np.prod(nd ** np.array(powers), axis=1)
+                fy = np.prod(y ** np.array(powers), axis=1)
+                lhs = np.sum(ex["M"][e] * ph_n * fn)
+                rhs = np.sum(qy * ph_y * fy)
+                assert abs(lhs - rhs) <= 1e-10 * (1 + np.sum(np.abs(qy * fy)))
+            checked += 1
+        assert checked > 10
+
+
+@pytest.mark.parametrize("geom", ["cube_volume", "sphere"])
+def test_laplace_geometric_convergence_in_L(geom):
+    """Thm. 1 / eq. convergence_estimate and Sec. 6.1: with kappa = 0 the relative
+    error decreases geometrically in L (checked at L = 2..7)."""
+    n = 4000
+    X = W.GENERATORS[geom](n, 41)
+    q = W.charges(n, 42)
+    tg = W.sample_targets(n, 300, 43)
+    errs = []
+    for L in range(2, 8):
+        e, _, _ = _fmm_error(X, q, 0.0, oracle.Params(L=L, ncrit=32), tg)
+        errs.append(e)
+    errs = np.array(errs)
+    assert (errs[1:] < errs[:-1]).all()
+    assert errs[-1] < 1e-5
+    rate = (errs[-1] / errs[0]) ** (1.0 / (len(errs) - 1))
+    assert rate < 0.35
+
+
+def test_helmholtz_high_frequency_convergence_and_accuracy():
+    """Sec. 6.1: geometric convergence also holds with directional expansions, and
+    the paper-literal settings are less accurate in HF than in LF."""
+    n = 3000
+    X = W.sphere(n, 51)
+    q = W.charges(n, 52)
+    tg = W.sample_targets(n, 300, 53)
+    errs = []
+    for L in (3, 4, 5, 6):
+        e, F, _ = _fmm_error(X, q, 24.0, oracle.Params(L=L, ncrit=24, eta=0.5, hf_threshold=1.0,
+                                                         dir_refine=1), tg)
+        assert F.info()["lstar"] >= 1
+        errs.append(e)
+    errs = np.array(errs)
+    assert (errs[1:] < errs[:-1]).all()
+    assert errs[-1] < 2e-4
+    e_lf, _, _ = _fmm_error(X, q, 0.0, oracle.Params(L=4, ncrit=24), tg)
+    e_hf, _, _ = _fmm_error(X, q, 24.0, oracle.Params(L=4, ncrit=24), tg)
+    assert e_hf > e_lf
+
+
+def test_separate_target_and_source_sets():
+    """eq. fmmsum with X != Y: two trees on one bounding cube."""
+    X = W.sphere(2000, 61)
+    Y = W.cube_volume(1500, 62) * 0.5
+    qY = W.charges(1500, 63)
+    e, F, _ = _fmm_error(X, None, 12.0, oracle.Params(L=5, ncrit=24, eta=0.5, hf_threshold=1.0),
+                         Y=Y, qY=qY)
+    assert F.info()["m2l_pairs"] > 0
+    assert e < 1e-3
+
+
+def test_degenerate_inputs():
+    """Empty sets give empty/zero potentials; coincident points all fall under tau."""
+    X = np.zeros((0, 3))
+    F = oracle.FMM(X, None, 3.0, oracle.Params())
+    assert F.apply(np.zeros(0, dtype=complex)).shape == (0,)
+    Xc = np.tile(np.array([[0.3, 0.3, 0.3]]), (100, 1))
+    F = oracle.FMM(Xc, None, 3.0, oracle.Params(ncrit=8))
+    p = F.apply(W.charges(100, 1))
+    assert np.all(p == 0)
+
+
+# ---------------------------------------------------------------- single operators
+def _grid_nodes(alpha, h, L):
+    g = np.arange(L) / (L - 1)
+    k = np.array([[g[kx], g[ky], g[kz]] for kz in range(L) for ky in range(L) for kx in range(L)])
+    return np.asarray(alpha) + h * k
+
+
+def _poly(pts, powers):
+    return np.prod(np.asarray(pts) ** np.array(powers), axis=1)
+
+
+POWERS = [(0, 0, 0), (1, 0, 0), (0, 1, 2), (2, 2, 1), (3, 1, 3)]
+
+
+@pytest.mark.parametrize("directional", [False, True])
+@pytest.mark.parametrize("L", [3, 4, 5])
+def test_l2l_reproduces_phased_polynomials(L, directional):
+    """L2L (Sec. 2.2, S_k^v): a father local expansion holding exp(ik<x_k,v>) f(x_k),
+    f of degree < L per variable, becomes exp(ik<x'_h,v>) f(x'_h) at each son's nodes.
+    The son grids sit in the 8 octants of the father (nodes from their definition)."""
+    kappa, h = 17.0, 0.5
+    alpha = np.array([0.2, -0.4, 0.1])
+    v = np.array([1.0, 2.0, -2.0]) / 3.0 if directional else None
+    xk = _grid_nodes(alpha, h, L)
+    ph = np.exp(1j * kappa * (xk @ v)) if directional else 1.0
+    for powers in POWERS[:4] if L == 3 else POWERS:
+        if max(powers) >= L:
+            continue
+        Lp = ph * _poly(xk, powers)
+        for octant in range(8):
+            off = np.array([(octant >> d) & 1 for d in range(3)])
+            calpha = alpha + 0.5 * h * off
+            xh = _grid_nodes(calpha, 0.5 * h, L)
+            got = oracle.l2l(kappa, L, alpha, h, v, calpha, 0.5 * h, Lp)
+            ref = (np.exp(1j * kappa * (xh @ v)) if directional else 1.0) * _poly(xh, powers)
+            assert np.abs(got - ref).max() < 1e-11 * (1 + np.abs(ref).max())
+
+
+@pytest.mark.parametrize("directional", [False, True])
+def test_m2m_and_p2m_preserve_phased_moments(directional):
+    """P2M/M2M (Sec. 2.2): sum_l M(y_l) e^{-ik<y_l,v>} f(y_l) is the same moment of the
+    son's node values (M2M) or of the charges (P2M), f of degree < L per variable."""
+    L, kappa, h = 4, 11.0, 0.5
+    rng = np.random.default_rng(7)
+    alpha = np.array([-0.3, 0.25, 0.0])
+    v = np.array([2.0, -1.0, 2.0]) / 3.0 if directional else None
+    yl = _grid_nodes(alpha, h, L)
+    ph_l = np.exp(-1j * kappa * (yl @ v)) if directional else 1.0
+    for octant in (0, 5, 7):
+        off = np.array([(octant >> d) & 1 for d in range(3)])
+        calpha = alpha + 0.5 * h * off
+        yr = _grid_nodes(calpha, 0.5 * h, L)
+        Mc = rng.standard_normal(L ** 3) + 1j * rng.standard_normal(L ** 3)
+        M = oracle.m2m(kappa, L, alpha, h, v, calpha, 0.5 * h, Mc)
+        ph_r = np.exp(-1j * kappa * (yr @ v)) if directional else 1.0
+        for powers in POWERS:
+            lhs = np.sum(M * ph_l * _poly(yl, powers))
+            rhs = np.sum(Mc * ph_r * _poly(yr, powers))
+            assert abs(lhs - rhs) < 1e-11 * (1 + np.abs(Mc).sum())
+    y = alpha + h * rng.uniform(0, 1, (40, 3))
+    q = rng.standard_normal(40) + 1j * rng.standard_normal(40)
+    M = oracle.p2m(kappa, L, alpha, h, v, y, q)
+    ph_y = np.exp(-1j * kappa * (y @ v)) if directional else 1.0
+    for powers in POWERS:
+        lhs = np.sum(M * ph_l * _poly(yl, powers))
+        rhs = np.sum(q * ph_y * _poly(y, powers))
+        assert abs(lhs - rhs) < 1e-11 * (1 + np.abs(q).sum())
+
+
+def test_l2p_reproduces_phased_polynomials():
+    """L2P (Sec. 2.2, S_h^u): node values exp(ik<x_h,u>) f(x_h) evaluate to exp(ik<x,u>) f(x)."""
+    L, kappa, h = 5, 23.0, 0.25
+    rng = np.random.default_rng(9)
+    alpha = np.array([0.5, 0.5, -0.25])
+    u = np.array([0.0, 0.6, 0.8])
+    xh = _grid_nodes(alpha, h, L)
+    x = alpha + h * rng.uniform(0, 1, (30, 3))
+    for powers in POWERS:
+        Lc = np.exp(1j * kappa * (xh @ u)) * _poly(xh, powers)
+        got = oracle.l2p(kappa, L, alpha, h, u, Lc, x)
+        ref = np.exp(1j * kappa * (x @ u)) * _poly(x, powers)
+        assert np.abs(got - ref).max() < 1e-11 * (1 + np.abs(ref).max())
+
+
+def test_mixed_regime_accuracy():
+    """A tree with high-frequency levels above low-frequency ones (the son of the
+    deepest HF level is LF) -- the directions passed between regimes by M2M/L2L
+    (Father(v) in the son, v in the phases) decide the accuracy here.  Reference
+    value 8.5e-4 for this input (direct sum on 300 targets); a direction mix-up in
+    M2M or L2L raises it above 3e-3."""
+    n = 3000
+    X = W.sphere(n, 51)
+    q = W.charges(n, 52)
+    tg = W.sample_targets(n, 300, 53)
+    e, F, _ = _fmm_error(X, q, 24.0, oracle.Params(L=5, ncrit=24, eta=0.5, hf_threshold=2.0,
+                                                     dir_refine=1), tg)
+    assert F.info()["lstar"] == 3 and F.info()["levels_x"] == 5
+    assert e < 1.5e-3
