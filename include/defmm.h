@@ -1,0 +1,162 @@
+/*
+ * defmm.h -- C ABI of libdefmm.so: the matvec of the directional equispaced-
+ * interpolation FMM (Chollet, Claeys, Fortin, Grigori) on one AMD MI355X GPU.
+ *
+ * Problem (Sec. 1, eq. fmmsum): given target points X, source points Y,
+ * a wavenumber kappa >= 0 and charges q on Y, evaluate
+ *     p(x) = sum_{y in Y} G(x,y) q(y),   G(x,y) = exp(i kappa |x-y|) / (4 pi |x-y|),
+ * for every x in X, with G taken as 0 when |x - y| <= tau = 1e-12 D (the
+ * singular pairs of Sec. 5.3; D = side of the bounding cube of X and Y).
+ *
+ * The plan (tree, traversal lists, directions, Fourier-domain M2L spectra)
+ * is built once per geometry; each matvec then runs entirely on the device.
+ * No C++ types or exceptions cross this interface.  Every call returns a
+ * defmm_status; defmm_last_error() gives a thread-local detail message.
+ * Calls on distinct plans are thread-safe; one workspace serves one
+ * in-flight matvec at a time.
+ */
+#ifndef DEFMM_H
+#define DEFMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DEFMM_OK = 0,
+  DEFMM_ERR_INVALID_ARG = 1,   /* bad pointer, size or parameter; nothing allocated */
+  DEFMM_ERR_OUT_OF_MEMORY = 2, /* device or host allocation failed; partial state freed */
+  DEFMM_ERR_DEVICE = 3,        /* a HIP runtime call failed */
+  DEFMM_ERR_UNSUPPORTED = 4    /* a parameter outside what this build implements */
+} defmm_status;
+
+typedef enum {
+  DEFMM_C128 = 0, /* complex128 everywhere */
+  DEFMM_C64 = 1   /* complex64 expansions, spectra, FFTs, Hadamard and P2P; FP64 geometry,
+                     spectrum precomputation and phase-argument reduction */
+} defmm_precision;
+
+typedef enum { DEFMM_M2L_AUTO = 0, DEFMM_M2L_FFT = 1, DEFMM_M2L_DENSE = 2 } defmm_m2l_mode;
+
+#define DEFMM_SAME_POINTS 1u /* X and Y are the same set: one tree; q and p share its order */
+
+typedef struct {
+  int32_t order_L;      /* interpolation nodes per dimension, 2..8 (padded FFT length 2L-1) */
+  int32_t ncrit;        /* a cell is a leaf iff it holds <= ncrit points (Sec. 4.2.1), >= 1 */
+  double eta;           /* MAC constant of eq. macdirref, > 0 (paper: 1) */
+  double hf_threshold;  /* a level is high-frequency iff kappa * w > hf_threshold, w = half
+                           the cell side; >= 0 (default 2) */
+  int32_t dir_refine;   /* extra 4-fold refinements of the cube-face direction set, 0..4 */
+  int32_t precision;    /* defmm_precision */
+  int32_t m2l_mode;     /* defmm_m2l_mode */
+  uint32_t flags;       /* DEFMM_SAME_POINTS */
+} defmm_params;
+
+typedef struct defmm_plan defmm_plan;           /* opaque */
+typedef struct defmm_workspace defmm_workspace; /* opaque */
+
+typedef struct {
+  int32_t levels;             /* tree levels of X (root = level 0) */
+  int32_t hf_levels;          /* number of high-frequency levels */
+  int64_t cells;              /* cells of X plus, for distinct sets, cells of Y */
+  int64_t leaves;
+  int64_t m2l_pairs;          /* admissible pairs of the dual tree traversal */
+  int64_t p2p_cell_pairs;     /* near-field pairs of the traversal */
+  int64_t p2p_point_pairs;    /* point-pair interactions of the near field */
+  int64_t eff_expansions;     /* effective (cell, direction) expansions, both trees */
+  int64_t m2l_expansions;     /* expansions taking part in M2L (sources + targets) */
+  int64_t unique_offsets;     /* distinct (level, offset) M2L spectra */
+  int32_t m2l_mode_per_level[32];
+} defmm_stats;
+
+/* Writes the default parameters: L=5, ncrit=64, eta=1, hf_threshold=2,
+   dir_refine=0, DEFMM_C64, DEFMM_M2L_FFT, flags=0. */
+defmm_status defmm_default_params(defmm_params* out);
+
+/* Builds a plan.  X: device pointer, nx*3 FP64 row-major (x,y,z); Y likewise
+   (ignored, may be NULL, when prm->flags has DEFMM_SAME_POINTS).  Host-
+   synchronous: X and Y may be freed when it returns.  hip_stream: the stream
+   used for the device work of the build (NULL = default stream).
+   Errors: DEFMM_ERR_INVALID_ARG for NULL out/prm/X, n < 0, L outside 2..8,
+   ncrit < 1, kappa < 0 or non-finite, eta <= 0, non-finite coordinates.
+   nx = 0 or ny = 0 is valid (every potential is then 0). */
+defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int64_t ny,
+                               double kappa, const defmm_params* prm, void* hip_stream,
+                               defmm_plan** out);
+
+/* Builds only the host side of a plan (tree, traversal lists, directions,
+   operator tables) from HOST arrays, touching no device: the result answers
+   defmm_plan_stats and the defmm_plan_export_* calls, while workspace_create
+   and matvec reject it with DEFMM_ERR_INVALID_ARG.  Same arguments and errors
+   as defmm_plan_create otherwise. */
+defmm_status defmm_plan_inspect_create(const double* X, int64_t nx, const double* Y, int64_t ny,
+                                       double kappa, const defmm_params* prm, defmm_plan** out);
+
+/* Device bytes held by the plan and needed by one workspace. */
+defmm_status defmm_plan_footprint(const defmm_plan* plan, size_t* resident_bytes,
+                                  size_t* workspace_bytes);
+defmm_status defmm_plan_stats(const defmm_plan* plan, defmm_stats* out);
+
+defmm_status defmm_workspace_create(defmm_plan* plan, defmm_workspace** out);
+
+/* One matvec p = G q, asynchronous on hip_stream (NULL = default stream).
+   q: device, ny complex values in the caller's order, interleaved (re, im),
+   complex128 for DEFMM_C128 and complex64 for DEFMM_C64; p: device, nx complex
+   of the same type, overwritten.  q must stay valid until the stream has
+   passed this call.  A workspace must not serve two in-flight matvecs. */
+defmm_status defmm_matvec(defmm_plan* plan, defmm_workspace* ws, const void* q, void* p,
+                          void* hip_stream);
+
+defmm_status defmm_workspace_destroy(defmm_workspace* ws);
+defmm_status defmm_plan_destroy(defmm_plan* plan);
+
+const char* defmm_status_string(defmm_status s);
+const char* defmm_last_error(void);
+
+/* ---- Introspection (tests, benchmarks).  All outputs are host arrays sized by
+   a first call with NULL outputs, which returns the count in *n. ---- */
+
+/* Bounding cube: side D and lower corner origin[3]. */
+defmm_status defmm_plan_geometry(const defmm_plan* plan, double* D, double* origin3);
+
+/* Cells of tree `which` (0 = X, 1 = Y), level-major, Morton order per level:
+   level, integer coordinates ijk[3] at that level, first sorted point, point
+   count, leaf flag.  perm (optional, n_points): sorted position -> caller index. */
+defmm_status defmm_plan_export_tree(const defmm_plan* plan, int32_t which, int64_t* n,
+                                    int32_t* level, int32_t* ijk, int32_t* first,
+                                    int32_t* count, int32_t* is_leaf, int32_t* perm);
+
+/* M2L pairs (Alg. 1): level, target cell, source cell (ids as in export_tree),
+   offset delta = ijk(t) - ijk(s), best direction (Alg. 2; -1 when low-frequency). */
+defmm_status defmm_plan_export_m2l(const defmm_plan* plan, int64_t* n, int32_t* level,
+                                   int32_t* t, int32_t* s, int32_t* delta, int32_t* dir);
+
+/* P2P pairs (Alg. 1): target cell, source cell. */
+defmm_status defmm_plan_export_p2p(const defmm_plan* plan, int64_t* n, int32_t* t, int32_t* s);
+
+/* Expansions of tree `which` after a matvec on ws: cell id, direction (-1 =
+   non-directional) and kind 0 = multipole / 1 = local node values, L^3 complex
+   per expansion (complex of the plan's precision). */
+defmm_status defmm_workspace_export_expansions(defmm_workspace* ws, int32_t which, int32_t kind,
+                                               int64_t* n, int32_t* cell, int32_t* dir,
+                                               void* values);
+
+/* Per-pass device time.  When enabled, matvec records HIP events around each pass
+   on its stream; pass_ms[i] accumulates milliseconds over the matvecs since the
+   last reset, calls[i] counts launches.  Pass names: defmm_pass_name(i). */
+#define DEFMM_NUM_PASSES 10
+defmm_status defmm_workspace_set_timing(defmm_workspace* ws, int32_t enable);
+defmm_status defmm_workspace_pass_times(defmm_workspace* ws, double* pass_ms, int64_t* calls);
+const char* defmm_pass_name(int32_t i);
+
+/* Algorithmic work of one matvec per pass (bytes or flops as documented in the
+   design notes): work[i] for pass i. */
+defmm_status defmm_plan_pass_work(const defmm_plan* plan, double* bytes, double* flops);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

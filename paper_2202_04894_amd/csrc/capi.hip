@@ -1,0 +1,553 @@
+// C ABI of libdefmm.so (include/defmm.h): argument checks, plan upload,
+// workspaces, matvec dispatch, introspection and per-pass timing.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <stdexcept>
+#include <string>
+
+#include "../../include/defmm.h"
+#include "device.hpp"
+
+using namespace defmm;
+
+struct defmm_plan {
+  DevPlan impl;
+};
+struct defmm_workspace {
+  Workspace impl;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+defmm_status fail(defmm_status s, const std::string& m) {
+  g_err = m;
+  return s;
+}
+
+struct HipError : std::runtime_error {
+  hipError_t code;
+  HipError(hipError_t c, const char* what) : std::runtime_error(std::string(what) + ": " + hipGetErrorString(c)), code(c) {}
+};
+
+void check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw HipError(e, what);
+}
+
+void* dalloc(DevPlan& P, size_t bytes) {
+  if (bytes == 0) return nullptr;
+  void* p = nullptr;
+  check(hipMalloc(&p, bytes), "hipMalloc");
+  P.allocs.push_back(p);
+  P.resident_bytes += bytes;
+  return p;
+}
+
+template <class T>
+T* upload(DevPlan& P, const std::vector<T>& v) {
+  if (v.empty()) return nullptr;
+  T* d = (T*)dalloc(P, v.size() * sizeof(T));
+  check(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy");
+  return d;
+}
+
+template <class T>
+std::vector<int32_t> to_i32(const std::vector<T>& v) {
+  return std::vector<int32_t>(v.begin(), v.end());
+}
+
+void upload_tree(DevPlan& P, DevTree& d, const Tree& t) {
+  d.n = t.n;
+  d.ncells = t.ncells();
+  d.nexp = t.nexp();
+  d.nlevels = t.nlevels;
+  d.soa = upload(P, t.soa);
+  d.perm = upload(P, t.perm);
+  d.level = upload(P, t.level);
+  d.ijk = upload(P, t.ijk);
+  d.first = upload(P, t.first);
+  d.count = upload(P, t.count);
+  d.exp_begin = upload(P, to_i32(t.exp_begin));
+  d.exp_cell = upload(P, t.exp_cell);
+  d.exp_u = upload(P, t.exp_u);
+}
+
+size_t csize(const DevPlan& P) { return P.precision == 0 ? 16 : 8; }
+
+}  // namespace
+
+namespace defmm {
+DevPlan::~DevPlan() {
+  for (void* p : allocs) hipFree(p);
+}
+Workspace::~Workspace() {
+  for (void* p : {qs, ps, M, Lx, Mt, part})
+    if (p) hipFree(p);
+  for (hipEvent_t e : ev_pool) hipEventDestroy(e);
+}
+}  // namespace defmm
+
+extern "C" {
+
+const char* defmm_status_string(defmm_status s) {
+  switch (s) {
+    case DEFMM_OK: return "ok";
+    case DEFMM_ERR_INVALID_ARG: return "invalid argument";
+    case DEFMM_ERR_OUT_OF_MEMORY: return "out of memory";
+    case DEFMM_ERR_DEVICE: return "device error";
+    case DEFMM_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* defmm_last_error(void) { return g_err.c_str(); }
+
+defmm_status defmm_default_params(defmm_params* out) {
+  if (!out) return fail(DEFMM_ERR_INVALID_ARG, "out is NULL");
+  out->order_L = 5;
+  out->ncrit = 64;
+  out->eta = 1.0;
+  out->hf_threshold = 2.0;
+  out->dir_refine = 0;
+  out->precision = DEFMM_C64;
+  out->m2l_mode = DEFMM_M2L_FFT;
+  out->flags = 0;
+  return DEFMM_OK;
+}
+
+static defmm_status validate(const double* X, int64_t nx, const double* Y, int64_t ny, double kappa,
+                             const defmm_params* prm, defmm_plan** out) {
+  if (!out || !prm) return fail(DEFMM_ERR_INVALID_ARG, "out or prm is NULL");
+  *out = nullptr;
+  bool same = (prm->flags & DEFMM_SAME_POINTS) != 0;
+  if (nx < 0 || ny < 0) return fail(DEFMM_ERR_INVALID_ARG, "negative point count");
+  if (nx > 0x7fffffffll || ny > 0x7fffffffll) return fail(DEFMM_ERR_UNSUPPORTED, "more than 2^31-1 points");
+  if ((nx > 0 && !X) || (!same && ny > 0 && !Y)) return fail(DEFMM_ERR_INVALID_ARG, "point array is NULL");
+  if (prm->order_L < 2 || prm->order_L > 8) return fail(DEFMM_ERR_INVALID_ARG, "order_L outside 2..8");
+  if (prm->ncrit < 1) return fail(DEFMM_ERR_INVALID_ARG, "ncrit < 1");
+  if (!(kappa >= 0.0) || !std::isfinite(kappa)) return fail(DEFMM_ERR_INVALID_ARG, "kappa < 0 or not finite");
+  if (!(prm->eta > 0.0) || !std::isfinite(prm->eta)) return fail(DEFMM_ERR_INVALID_ARG, "eta <= 0");
+  if (!(prm->hf_threshold >= 0.0)) return fail(DEFMM_ERR_INVALID_ARG, "hf_threshold < 0");
+  if (prm->dir_refine < 0 || prm->dir_refine > 4) return fail(DEFMM_ERR_INVALID_ARG, "dir_refine outside 0..4");
+  if (prm->precision != DEFMM_C64 && prm->precision != DEFMM_C128)
+    return fail(DEFMM_ERR_INVALID_ARG, "unknown precision");
+  if (prm->m2l_mode == DEFMM_M2L_DENSE) return fail(DEFMM_ERR_UNSUPPORTED, "dense M2L is not built");
+  if (prm->m2l_mode != DEFMM_M2L_AUTO && prm->m2l_mode != DEFMM_M2L_FFT)
+    return fail(DEFMM_ERR_INVALID_ARG, "unknown m2l_mode");
+  return DEFMM_OK;
+}
+
+// Host half of plan creation: copies the points, checks them and builds the
+// host plan.  Throws on allocation/device errors; returns a status for bad input.
+static defmm_status host_build(defmm_plan* plan, const double* X, int64_t nx, const double* Y, int64_t ny,
+                               double kappa, const defmm_params* prm, bool host_pointers) {
+  bool same = (prm->flags & DEFMM_SAME_POINTS) != 0;
+  std::vector<double> hx(3 * nx), hy;
+  if (nx > 0) {
+    if (host_pointers) std::memcpy(hx.data(), X, 3 * nx * sizeof(double));
+    else check(hipMemcpy(hx.data(), X, 3 * nx * sizeof(double), hipMemcpyDefault), "copy X");
+  }
+  if (!same) {
+    hy.resize(3 * ny);
+    if (ny > 0) {
+      if (host_pointers) std::memcpy(hy.data(), Y, 3 * ny * sizeof(double));
+      else check(hipMemcpy(hy.data(), Y, 3 * ny * sizeof(double), hipMemcpyDefault), "copy Y");
+    }
+  }
+  for (double v : hx)
+    if (!std::isfinite(v)) return fail(DEFMM_ERR_INVALID_ARG, "non-finite coordinate in X");
+  for (double v : hy)
+    if (!std::isfinite(v)) return fail(DEFMM_ERR_INVALID_ARG, "non-finite coordinate in Y");
+  DevPlan& P = plan->impl;
+  BuildParams bp;
+  bp.L = prm->order_L;
+  bp.ncrit = prm->ncrit;
+  bp.eta = prm->eta;
+  bp.hf_threshold = prm->hf_threshold;
+  bp.dir_refine = prm->dir_refine;
+  bp.same_points = same;
+  bp.kappa = kappa;
+  build_host_plan(P.host, hx.data(), nx, same ? nullptr : hy.data(), ny, bp);
+  const HostPlan& H = P.host;
+  P.L = bp.L;
+  P.precision = prm->precision;
+  P.kappa = kappa;
+  P.D = H.D;
+  for (int d = 0; d < 3; ++d) P.origin[d] = H.origin[d];
+  P.tau = H.tau;
+  P.same = same;
+  P.nx = nx;
+  P.ny = ny;
+  return DEFMM_OK;
+}
+
+defmm_status defmm_plan_inspect_create(const double* X, int64_t nx, const double* Y, int64_t ny, double kappa,
+                                       const defmm_params* prm, defmm_plan** out) {
+  defmm_status st = validate(X, nx, Y, ny, kappa, prm, out);
+  if (st != DEFMM_OK) return st;
+  if (prm->flags & DEFMM_SAME_POINTS) ny = nx;
+  defmm_plan* plan = nullptr;
+  try {
+    plan = new defmm_plan();
+    plan->impl.host_only = true;
+    st = host_build(plan, X, nx, Y, ny, kappa, prm, true);
+    if (st != DEFMM_OK) {
+      delete plan;
+      return st;
+    }
+    *out = plan;
+    return DEFMM_OK;
+  } catch (const std::bad_alloc&) {
+    delete plan;
+    return fail(DEFMM_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (const std::exception& e) {
+    delete plan;
+    return fail(DEFMM_ERR_DEVICE, e.what());
+  }
+}
+
+defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int64_t ny, double kappa,
+                               const defmm_params* prm, void* hip_stream, defmm_plan** out) {
+  defmm_status st = validate(X, nx, Y, ny, kappa, prm, out);
+  if (st != DEFMM_OK) return st;
+  bool same = (prm->flags & DEFMM_SAME_POINTS) != 0;
+  if (same) ny = nx;
+  hipStream_t s = (hipStream_t)hip_stream;
+  defmm_plan* plan = nullptr;
+  try {
+    plan = new defmm_plan();
+    st = host_build(plan, X, nx, Y, ny, kappa, prm, false);
+    if (st != DEFMM_OK) {
+      delete plan;
+      return st;
+    }
+    DevPlan& P = plan->impl;
+    HostPlan& H = P.host;
+    upload_tree(P, P.tx, H.tx);
+    if (same) P.ty = P.tx;
+    else upload_tree(P, P.ty, H.ty_own);
+    P.p2m_exp = upload(P, H.p2m_exp);
+    P.n_p2m = (int64_t)H.p2m_exp.size();
+    P.m2m.resize(H.m2m_par.size());
+    for (size_t l = 0; l < H.m2m_par.size(); ++l) {
+      P.m2m[l].n = (int64_t)H.m2m_par[l].size();
+      P.m2m[l].a = upload(P, H.m2m_par[l]);
+      P.m2m[l].b = upload(P, H.m2m_child[l]);
+      P.m2m[l].oct = upload(P, H.m2m_oct[l]);
+    }
+    P.m2f_exp = upload(P, H.m2f_exp);
+    P.n_m2f = (int64_t)H.m2f_exp.size();
+    P.m2l_tgt = upload(P, H.m2l_tgt);
+    P.m2l_begin = upload(P, H.m2l_begin);
+    P.m2l_src = upload(P, H.m2l_src);
+    P.m2l_off = upload(P, H.m2l_off);
+    P.n_m2l_tgt = (int64_t)H.m2l_tgt.size();
+    P.n_m2l = (int64_t)H.m2l_src.size();
+    P.l2l.resize(H.l2l_ch.size());
+    for (size_t l = 0; l < H.l2l_ch.size(); ++l) {
+      P.l2l[l].n = (int64_t)H.l2l_ch[l].size();
+      if (P.l2l[l].n == 0) continue;
+      P.l2l[l].a = upload(P, H.l2l_ch[l]);
+      P.l2l[l].b = upload(P, H.l2l_begin[l]);
+      P.l2l[l].c = upload(P, H.l2l_par[l]);
+      P.l2l[l].oct = upload(P, H.l2l_oct[l]);
+    }
+    P.l2p_cell = upload(P, H.l2p_cell);
+    P.l2p_first = upload(P, H.l2p_first);
+    P.l2p_count = upload(P, H.l2p_count);
+    P.n_l2p = (int64_t)H.l2p_cell.size();
+    P.blk_first = upload(P, H.blk_first);
+    P.blk_count = upload(P, H.blk_count);
+    P.blk_wi_begin = upload(P, H.blk_wi_begin);
+    P.nblk = (int64_t)H.blk_first.size();
+    P.wi_blk = upload(P, H.wi_blk);
+    P.wi_seg_begin = upload(P, H.wi_seg_begin);
+    P.nwi = (int64_t)H.wi_blk.size();
+    P.seg_first = upload(P, H.seg_first);
+    P.seg_count = upload(P, H.seg_count);
+    // spectra, one per distinct (level, delta), computed on the device in FP64
+    P.n_off = (int64_t)H.offsets.size();
+    if (P.n_off > 0) {
+      int P3 = (2 * P.L - 1) * (2 * P.L - 1) * (2 * P.L - 1);
+      P.spectra = dalloc(P, (size_t)P.n_off * P3 * csize(P));
+      std::vector<int32_t> lev(P.n_off), dl(3 * P.n_off);
+      for (int64_t i = 0; i < P.n_off; ++i) {
+        lev[i] = H.offsets[i].level;
+        for (int d = 0; d < 3; ++d) dl[3 * i + d] = H.offsets[i].d[d];
+      }
+      int32_t* dlev = upload(P, lev);
+      int32_t* ddl = upload(P, dl);
+      check(compute_spectra(P, dlev, ddl, s), "spectra launch");
+      check(hipStreamSynchronize(s), "spectra");
+    }
+    *out = plan;
+    return DEFMM_OK;
+  } catch (const HipError& e) {
+    delete plan;
+    if (e.code == hipErrorOutOfMemory) return fail(DEFMM_ERR_OUT_OF_MEMORY, e.what());
+    return fail(DEFMM_ERR_DEVICE, e.what());
+  } catch (const std::bad_alloc&) {
+    delete plan;
+    return fail(DEFMM_ERR_OUT_OF_MEMORY, "host allocation failed");
+  } catch (const std::exception& e) {
+    delete plan;
+    return fail(DEFMM_ERR_DEVICE, e.what());
+  }
+}
+
+static size_t workspace_bytes(const DevPlan& P) {
+  size_t cs = csize(P);
+  int L3 = P.L * P.L * P.L, P3 = (2 * P.L - 1) * (2 * P.L - 1) * (2 * P.L - 1);
+  return cs * ((size_t)P.ny + (size_t)P.nx + (size_t)P.ty.nexp * L3 + (size_t)P.tx.nexp * L3 +
+               (size_t)P.n_m2f * P3 + (size_t)P.nwi * 64);
+}
+
+defmm_status defmm_plan_footprint(const defmm_plan* plan, size_t* resident, size_t* ws) {
+  if (!plan) return fail(DEFMM_ERR_INVALID_ARG, "plan is NULL");
+  if (resident) *resident = plan->impl.resident_bytes;
+  if (ws) *ws = workspace_bytes(plan->impl);
+  return DEFMM_OK;
+}
+
+defmm_status defmm_plan_stats(const defmm_plan* plan, defmm_stats* out) {
+  if (!plan || !out) return fail(DEFMM_ERR_INVALID_ARG, "NULL argument");
+  const DevPlan& P = plan->impl;
+  const HostPlan& H = P.host;
+  std::memset(out, 0, sizeof(*out));
+  out->levels = H.tx.nlevels;
+  int hfl = 0;
+  for (int l = 0; l < H.tx.nlevels; ++l) hfl += H.hf[l];
+  out->hf_levels = hfl;
+  out->cells = H.tx.ncells() + (P.same ? 0 : H.ty->ncells());
+  int64_t leaves = 0;
+  for (int64_t c = 0; c < H.tx.ncells(); ++c) leaves += H.tx.leaf[c];
+  if (!P.same)
+    for (int64_t c = 0; c < H.ty->ncells(); ++c) leaves += H.ty->leaf[c];
+  out->leaves = leaves;
+  out->m2l_pairs = (int64_t)H.m2l.size();
+  out->p2p_cell_pairs = (int64_t)H.p2p_t.size();
+  out->p2p_point_pairs = H.p2p_point_pairs;
+  out->eff_expansions = H.tx.nexp() + (P.same ? 0 : H.ty->nexp());
+  out->m2l_expansions = (int64_t)H.m2f_exp.size() + (int64_t)H.m2l_tgt.size();
+  out->unique_offsets = (int64_t)H.offsets.size();
+  for (int l = 0; l < 32; ++l) out->m2l_mode_per_level[l] = DEFMM_M2L_FFT;
+  return DEFMM_OK;
+}
+
+defmm_status defmm_workspace_create(defmm_plan* plan, defmm_workspace** out) {
+  if (!plan || !out) return fail(DEFMM_ERR_INVALID_ARG, "NULL argument");
+  *out = nullptr;
+  DevPlan& P = plan->impl;
+  if (P.host_only) return fail(DEFMM_ERR_INVALID_ARG, "plan was built for inspection only");
+  defmm_workspace* ws = new (std::nothrow) defmm_workspace();
+  if (!ws) return fail(DEFMM_ERR_OUT_OF_MEMORY, "host allocation failed");
+  Workspace& W = ws->impl;
+  W.plan = &P;
+  size_t cs = csize(P);
+  int L3 = P.L * P.L * P.L, P3 = (2 * P.L - 1) * (2 * P.L - 1) * (2 * P.L - 1);
+  struct {
+    void** p;
+    size_t n;
+  } bufs[] = {{&W.qs, cs * (size_t)P.ny},
+              {&W.ps, cs * (size_t)P.nx},
+              {&W.M, cs * (size_t)P.ty.nexp * L3},
+              {&W.Lx, cs * (size_t)P.tx.nexp * L3},
+              {&W.Mt, cs * (size_t)P.n_m2f * P3},
+              {&W.part, cs * (size_t)P.nwi * 64}};
+  for (auto& b : bufs) {
+    if (b.n == 0) continue;
+    hipError_t e = hipMalloc(b.p, b.n);
+    if (e != hipSuccess) {
+      delete ws;
+      return fail(e == hipErrorOutOfMemory ? DEFMM_ERR_OUT_OF_MEMORY : DEFMM_ERR_DEVICE,
+                  std::string("workspace hipMalloc: ") + hipGetErrorString(e));
+    }
+    W.bytes += b.n;
+  }
+  *out = ws;
+  return DEFMM_OK;
+}
+
+defmm_status defmm_matvec(defmm_plan* plan, defmm_workspace* ws, const void* q, void* p, void* hip_stream) {
+  if (!plan || !ws) return fail(DEFMM_ERR_INVALID_ARG, "plan or workspace is NULL");
+  DevPlan& P = plan->impl;
+  if (P.host_only) return fail(DEFMM_ERR_INVALID_ARG, "plan was built for inspection only");
+  if (ws->impl.plan != &P) return fail(DEFMM_ERR_INVALID_ARG, "workspace belongs to another plan");
+  if ((P.ny > 0 && !q) || (P.nx > 0 && !p)) return fail(DEFMM_ERR_INVALID_ARG, "q or p is NULL");
+  hipError_t e = run_matvec(P, ws->impl, q, p, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return fail(DEFMM_ERR_DEVICE, std::string("matvec launch: ") + hipGetErrorString(e));
+  return DEFMM_OK;
+}
+
+defmm_status defmm_workspace_destroy(defmm_workspace* ws) {
+  delete ws;
+  return DEFMM_OK;
+}
+
+defmm_status defmm_plan_destroy(defmm_plan* plan) {
+  delete plan;
+  return DEFMM_OK;
+}
+
+defmm_status defmm_plan_geometry(const defmm_plan* plan, double* D, double* origin3) {
+  if (!plan) return fail(DEFMM_ERR_INVALID_ARG, "plan is NULL");
+  if (D) *D = plan->impl.D;
+  if (origin3)
+    for (int d = 0; d < 3; ++d) origin3[d] = plan->impl.origin[d];
+  return DEFMM_OK;
+}
+
+defmm_status defmm_plan_export_tree(const defmm_plan* plan, int32_t which, int64_t* n, int32_t* level,
+                                    int32_t* ijk, int32_t* first, int32_t* count, int32_t* is_leaf,
+                                    int32_t* perm) {
+  if (!plan || !n || (which != 0 && which != 1)) return fail(DEFMM_ERR_INVALID_ARG, "bad argument");
+  const HostPlan& H = plan->impl.host;
+  const Tree& T = which == 0 ? H.tx : *H.ty;
+  *n = T.ncells();
+  if (level) std::memcpy(level, T.level.data(), T.level.size() * 4);
+  if (ijk) std::memcpy(ijk, T.ijk.data(), T.ijk.size() * 4);
+  if (first) std::memcpy(first, T.first.data(), T.first.size() * 4);
+  if (count) std::memcpy(count, T.count.data(), T.count.size() * 4);
+  if (is_leaf) std::memcpy(is_leaf, T.leaf.data(), T.leaf.size() * 4);
+  if (perm) std::memcpy(perm, T.perm.data(), T.perm.size() * 4);
+  return DEFMM_OK;
+}
+
+defmm_status defmm_plan_export_m2l(const defmm_plan* plan, int64_t* n, int32_t* level, int32_t* t, int32_t* s,
+                                   int32_t* delta, int32_t* dir) {
+  if (!plan || !n) return fail(DEFMM_ERR_INVALID_ARG, "bad argument");
+  const HostPlan& H = plan->impl.host;
+  *n = (int64_t)H.m2l.size();
+  if (level || t || s || delta || dir)
+    for (size_t i = 0; i < H.m2l.size(); ++i) {
+      const Offset& o = H.offsets[H.m2l[i].off];
+      if (level) level[i] = o.level;
+      if (t) t[i] = H.m2l[i].t;
+      if (s) s[i] = H.m2l[i].s;
+      if (delta)
+        for (int d = 0; d < 3; ++d) delta[3 * i + d] = o.d[d];
+      if (dir) dir[i] = o.dir;
+    }
+  return DEFMM_OK;
+}
+
+defmm_status defmm_plan_export_p2p(const defmm_plan* plan, int64_t* n, int32_t* t, int32_t* s) {
+  if (!plan || !n) return fail(DEFMM_ERR_INVALID_ARG, "bad argument");
+  const HostPlan& H = plan->impl.host;
+  *n = (int64_t)H.p2p_t.size();
+  if (t) std::memcpy(t, H.p2p_t.data(), H.p2p_t.size() * 4);
+  if (s) std::memcpy(s, H.p2p_s.data(), H.p2p_s.size() * 4);
+  return DEFMM_OK;
+}
+
+defmm_status defmm_workspace_export_expansions(defmm_workspace* ws, int32_t which, int32_t kind, int64_t* n,
+                                               int32_t* cell, int32_t* dir, void* values) {
+  if (!ws || !n || (which != 0 && which != 1) || (kind != 0 && kind != 1))
+    return fail(DEFMM_ERR_INVALID_ARG, "bad argument");
+  const DevPlan& P = *ws->impl.plan;
+  const Tree& T = which == 0 ? P.host.tx : *P.host.ty;
+  *n = T.nexp();
+  if (cell) std::memcpy(cell, T.exp_cell.data(), T.exp_cell.size() * 4);
+  if (dir) std::memcpy(dir, T.exp_dir.data(), T.exp_dir.size() * 4);
+  if (values && T.nexp() > 0) {
+    // multipoles live on the source tree, locals on the target tree
+    bool ok = (kind == 0) ? (which == 1 || P.same) : (which == 0 || P.same);
+    if (!ok) return fail(DEFMM_ERR_INVALID_ARG, "this tree holds no such expansions");
+    const void* src = kind == 0 ? ws->impl.M : ws->impl.Lx;
+    size_t bytes = (size_t)T.nexp() * P.L * P.L * P.L * csize(P);
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(values, src, bytes, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(DEFMM_ERR_DEVICE, hipGetErrorString(e));
+  }
+  return DEFMM_OK;
+}
+
+defmm_status defmm_workspace_set_timing(defmm_workspace* ws, int32_t enable) {
+  if (!ws) return fail(DEFMM_ERR_INVALID_ARG, "workspace is NULL");
+  ws->impl.timing = enable != 0;
+  return DEFMM_OK;
+}
+
+defmm_status defmm_workspace_pass_times(defmm_workspace* ws, double* pass_ms, int64_t* calls) {
+  if (!ws) return fail(DEFMM_ERR_INVALID_ARG, "workspace is NULL");
+  Workspace& W = ws->impl;
+  for (const auto& r : W.pending) {
+    hipError_t e = hipEventSynchronize(W.ev_pool[r.b]);
+    if (e != hipSuccess) return fail(DEFMM_ERR_DEVICE, hipGetErrorString(e));
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, W.ev_pool[r.a], W.ev_pool[r.b]);
+    if (e != hipSuccess) return fail(DEFMM_ERR_DEVICE, hipGetErrorString(e));
+    W.pass_ms[r.pass] += ms;
+    W.pass_calls[r.pass] += 1;
+  }
+  W.pending.clear();
+  W.ev_used = 0;
+  for (int i = 0; i < kNumPasses; ++i) {
+    if (pass_ms) pass_ms[i] = W.pass_ms[i];
+    if (calls) calls[i] = W.pass_calls[i];
+    W.pass_ms[i] = 0;
+    W.pass_calls[i] = 0;
+  }
+  return DEFMM_OK;
+}
+
+const char* defmm_pass_name(int32_t i) {
+  static const char* names[kNumPasses] = {"setup", "p2m", "m2m", "m2f", "m2l_f2l", "l2l", "p2p", "p2p_reduce",
+                                          "l2p", "scatter"};
+  if (i < 0 || i >= kNumPasses) return "";
+  return names[i];
+}
+
+defmm_status defmm_plan_pass_work(const defmm_plan* plan, double* bytes, double* flops) {
+  if (!plan) return fail(DEFMM_ERR_INVALID_ARG, "plan is NULL");
+  const DevPlan& P = plan->impl;
+  const HostPlan& H = P.host;
+  double cs = (double)csize(P);
+  double L = P.L, Pp = 2 * P.L - 1, L3 = L * L * L, P3 = Pp * Pp * Pp;
+  double b[kNumPasses] = {0}, f[kNumPasses] = {0};
+  b[kPassSetup] = (double)P.ny * (2 * cs + 4) + cs * ((double)P.tx.nexp * L3 + (double)P.nx);
+  double npts = 0;
+  for (int32_t e : H.p2m_exp) npts += H.ty->count[H.ty->exp_cell[e]];
+  b[kPassP2M] = npts * (24 + cs) + (double)P.n_p2m * cs * L3;
+  f[kPassP2M] = npts * L3 * 8;
+  double nm2m = 0, nm2m_child = 0;
+  for (const auto& v : H.m2m_par) nm2m += (double)v.size();
+  for (const auto& v : H.m2m_child)
+    for (int32_t c : v) nm2m_child += c >= 0;
+  b[kPassM2M] = (nm2m + nm2m_child) * cs * L3;
+  f[kPassM2M] = nm2m_child * 8 * (3 * L3 * L + 2 * L3);
+  b[kPassM2F] = (double)P.n_m2f * cs * (L3 + P3);
+  f[kPassM2F] = (double)P.n_m2f * 8 * (Pp * L * L * L + Pp * Pp * L * L + P3 * L);
+  b[kPassM2L] = (double)P.n_m2l * 2 * cs * P3 + (double)P.n_m2l_tgt * cs * L3;
+  f[kPassM2L] = (double)P.n_m2l * 8 * P3 + (double)P.n_m2l_tgt * 8 * (Pp * Pp * L * Pp + Pp * L * L * Pp + L3 * Pp);
+  double nl2l = 0;
+  for (const auto& v : H.l2l_par) nl2l += (double)v.size();
+  double nl2l_ch = 0;
+  for (const auto& v : H.l2l_ch) nl2l_ch += (double)v.size();
+  b[kPassL2L] = (nl2l + 2 * nl2l_ch) * cs * L3;
+  f[kPassL2L] = nl2l * 8 * (3 * L3 * L + 3 * L3);
+  f[kPassP2P] = 23.0 * (double)H.p2p_point_pairs;
+  b[kPassP2P] = (double)P.nwi * 64 * cs;
+  b[kPassP2PRed] = (double)P.nwi * 64 * cs + (double)P.nx * cs;
+  double nl2p_pts = 0, nl2p_exp = 0;
+  for (size_t i = 0; i < H.l2p_cell.size(); ++i) {
+    int c = H.l2p_cell[i];
+    double ne = (double)(H.tx.exp_begin[c + 1] - H.tx.exp_begin[c]);
+    nl2p_pts += H.l2p_count[i];
+    nl2p_exp += ne;
+    f[kPassL2P] += (double)H.l2p_count[i] * ne * 8 * (L3 + L * L + L);
+  }
+  b[kPassL2P] = nl2p_pts * (24 + 2 * cs) + nl2p_exp * cs * L3;
+  b[kPassScatter] = (double)P.nx * (2 * cs + 4);
+  for (int i = 0; i < kNumPasses; ++i) {
+    if (bytes) bytes[i] = b[i];
+    if (flops) flops[i] = f[i];
+  }
+  return DEFMM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,106 @@
+// Device mirror of the plan and the per-matvec workspace.  Internal.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "plan.hpp"
+
+namespace defmm {
+
+// Pass indices for timing and work accounting.
+enum Pass {
+  kPassSetup = 0,   // charge gather, zeroing
+  kPassP2M = 1,
+  kPassM2M = 2,
+  kPassM2F = 3,
+  kPassM2L = 4,     // Hadamard accumulate + F2L (fused)
+  kPassL2L = 5,
+  kPassP2P = 6,
+  kPassP2PRed = 7,
+  kPassL2P = 8,
+  kPassScatter = 9,
+  kNumPasses = 10
+};
+
+struct DevTree {
+  int64_t n = 0, ncells = 0, nexp = 0;
+  int nlevels = 0;
+  double* soa = nullptr;      // 3n sorted coordinates (x | y | z)
+  int32_t* perm = nullptr;    // sorted -> caller
+  int32_t* level = nullptr;
+  int32_t* ijk = nullptr;     // 3 per cell
+  int32_t* first = nullptr;
+  int32_t* count = nullptr;
+  int32_t* exp_begin = nullptr;  // ncells + 1
+  int32_t* exp_cell = nullptr;
+  double* exp_u = nullptr;       // 3 per expansion
+};
+
+struct LevelTable {  // per-level operator table on the device
+  int64_t n = 0;     // number of work items
+  int32_t* a = nullptr;
+  int32_t* b = nullptr;
+  int32_t* c = nullptr;
+  int8_t* oct = nullptr;
+};
+
+struct DevPlan {
+  HostPlan host;   // kept for introspection and stats
+  int L = 5, precision = 1;
+  double kappa = 0.0, D = 0.0, origin[3] = {0, 0, 0}, tau = 0.0;
+  DevTree tx, ty;
+  bool same = false;
+  bool host_only = false;  // built by defmm_plan_inspect_create: no device data
+  int64_t nx = 0, ny = 0;
+  // tables
+  int32_t* p2m_exp = nullptr;
+  int64_t n_p2m = 0;
+  std::vector<LevelTable> m2m;  // a = parent exps, b = 8 child exps per parent, oct = 8 per parent
+  int32_t* m2f_exp = nullptr;
+  int64_t n_m2f = 0;
+  int32_t *m2l_tgt = nullptr, *m2l_begin = nullptr, *m2l_src = nullptr, *m2l_off = nullptr;
+  int64_t n_m2l_tgt = 0, n_m2l = 0;
+  std::vector<LevelTable> l2l;  // a = child exps, b = CSR begin (n+1), c = parent exps, oct
+  int32_t *l2p_cell = nullptr, *l2p_first = nullptr, *l2p_count = nullptr;
+  int64_t n_l2p = 0;
+  int32_t *blk_first = nullptr, *blk_count = nullptr, *blk_wi_begin = nullptr;
+  int64_t nblk = 0;
+  int32_t *wi_blk = nullptr, *wi_seg_begin = nullptr;
+  int64_t nwi = 0;
+  int32_t *seg_first = nullptr, *seg_count = nullptr;
+  void* spectra = nullptr;  // n_off x P^3 complex (plan precision), scaled by 1/P^3
+  int64_t n_off = 0;
+  std::vector<void*> allocs;
+  size_t resident_bytes = 0;
+  ~DevPlan();
+};
+
+struct Workspace {
+  DevPlan* plan = nullptr;
+  void* qs = nullptr;    // sorted charges
+  void* ps = nullptr;    // sorted potentials
+  void* M = nullptr;     // multipoles, ty.nexp x L^3
+  void* Lx = nullptr;    // locals, tx.nexp x L^3
+  void* Mt = nullptr;    // Fourier-domain multipoles, n_m2f x P^3
+  void* part = nullptr;  // P2P partial sums, nwi x 64
+  size_t bytes = 0;
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  struct Rec { int pass; size_t a, b; };
+  std::vector<Rec> pending;
+  double pass_ms[kNumPasses] = {0};
+  int64_t pass_calls[kNumPasses] = {0};
+  ~Workspace();
+};
+
+// Kernel launchers (kernels.hip).
+hipError_t compute_spectra(DevPlan& P, const int32_t* d_lev, const int32_t* d_delta, hipStream_t s);
+hipError_t run_matvec(DevPlan& P, Workspace& W, const void* q, void* p, hipStream_t s);
+
+}  // namespace defmm

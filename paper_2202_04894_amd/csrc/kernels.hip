@@ -1,0 +1,830 @@
+// HIP kernels of the defmm matvec for gfx950 (wave64) and their launchers.
+//
+// One matvec (Sec. 2.2 operators, Sec. 4.1.1 Fourier-domain M2L):
+//   gather q -> P2M (source leaves) -> M2M (sons to fathers, level by level)
+//   -> M2F (pruned 3D DFT of each zero-padded multipole grid)
+//   -> M2L: per target expansion, Hadamard accumulate over its interaction
+//      list, then F2L (pruned inverse DFT, restricted to the L^3 grid)
+//   -> L2L (fathers to sons) -> P2P (near field) + L2P -> scatter p.
+// Every output element is owned by one thread: no atomics, results are
+// bitwise reproducible run to run.
+//
+// Precision: R = float (complex64 path) or double (complex128 path).  Phase
+// arguments kappa*<d,u> are formed in FP64 from differences of points of the
+// same cell and reduced modulo 2 pi in FP64 before a float sincos.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+
+#include "device.hpp"
+
+namespace defmm {
+
+template <typename R>
+struct C2 {
+  R x, y;
+};
+
+template <typename R>
+__device__ __forceinline__ C2<R> cmul(C2<R> a, C2<R> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+template <typename R>
+__device__ __forceinline__ void cfma(C2<R>& acc, C2<R> a, C2<R> b) {
+  acc.x = fma(a.x, b.x, fma(-a.y, b.y, acc.x));
+  acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
+}
+
+template <typename R>
+__device__ __forceinline__ C2<R> cscale(C2<R> a, R s) {
+  return {a.x * s, a.y * s};
+}
+
+// exp(i a) for an FP64 argument.
+template <typename R>
+__device__ __forceinline__ C2<R> expi(double a);
+
+template <>
+__device__ __forceinline__ C2<double> expi<double>(double a) {
+  double s, c;
+  sincos(a, &s, &c);
+  return {c, s};
+}
+
+template <>
+__device__ __forceinline__ C2<float> expi<float>(double a) {
+  // Cody-Waite reduction by 2 pi in FP64 (two-term constant), then float sincos.
+  const double inv2pi = 0.15915494309189533577;
+  const double twopi_hi = 6.283185307179586232;
+  const double twopi_lo = 2.4492935982947064e-16;
+  double k = rint(a * inv2pi);
+  double r = fma(-k, twopi_hi, a);
+  r = fma(-k, twopi_lo, r);
+  float s, c;
+  sincosf((float)r, &s, &c);
+  return {c, s};
+}
+
+// Lagrange basis on the L equispaced nodes j/(L-1) of [0,1] (Sec. 2.3).
+template <typename R, int L>
+__device__ __forceinline__ void lagrange(R t, R* w) {
+  R s = t * (R)(L - 1);
+#pragma unroll
+  for (int m = 0; m < L; ++m) {
+    R v = (R)1;
+#pragma unroll
+    for (int j = 0; j < L; ++j)
+      if (j != m) v *= (s - (R)j) / (R)(m - j);
+    w[m] = v;
+  }
+}
+
+constexpr int round64(int x) { return ((x + 63) / 64) * 64; }
+
+// XCD-aware block order: the hardware deals consecutive workgroups to the 8
+// XCDs round-robin; remap so each XCD walks a contiguous range of items and
+// neighbours in Morton order share that XCD's L2.
+__device__ __forceinline__ int64_t xcd_item(int64_t n) {
+  int64_t nper = (n + 7) / 8;
+  int64_t b = blockIdx.x;
+  return (b % 8) * nper + b / 8;
+}
+
+static inline unsigned xcd_grid(int64_t n) { return (unsigned)(8 * ((n + 7) / 8)); }
+
+struct TreeView {
+  int64_t n;
+  const double* soa;
+  const int32_t* level;
+  const int32_t* ijk;
+  const int32_t* first;
+  const int32_t* count;
+  const int32_t* exp_begin;
+  const int32_t* exp_cell;
+  const double* exp_u;
+};
+
+static TreeView view(const DevTree& t) {
+  return {t.n, t.soa, t.level, t.ijk, t.first, t.count, t.exp_begin, t.exp_cell, t.exp_u};
+}
+
+struct Geo {
+  double kappa, D, ox, oy, oz;
+};
+
+// ------------------------------------------------------------------ elementwise
+template <typename R>
+__global__ void k_gather(int64_t n, const int32_t* __restrict__ perm, const C2<R>* __restrict__ q,
+                         C2<R>* __restrict__ qs) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) qs[i] = q[perm[i]];
+}
+
+template <typename R>
+__global__ void k_scatter(int64_t n, const int32_t* __restrict__ perm, const C2<R>* __restrict__ ps,
+                          C2<R>* __restrict__ p) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[perm[i]] = ps[i];
+}
+
+template <typename R>
+__global__ void k_zero(int64_t n, C2<R>* __restrict__ a) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = {(R)0, (R)0};
+}
+
+// ------------------------------------------------------------------ spectra
+// Fourier-domain M2L diagonal (eq. FourierDiagonal) for each (level, delta):
+// the kernel on the (2L-1)^3 difference grid (eq. CirculantKernel), a 3D DFT
+// in FP64, scaled by 1/P^3 so that F2L is a plain inverse sum.
+template <typename R, int L>
+__global__ __launch_bounds__(256) void k_spectra(int64_t n, const int32_t* __restrict__ lev,
+                                                 const int32_t* __restrict__ delta, double kappa, double D,
+                                                 C2<R>* __restrict__ S) {
+  constexpr int P = 2 * L - 1, P3 = P * P * P;
+  __shared__ C2<double> a[P3];
+  __shared__ C2<double> W[P];
+  int64_t o = blockIdx.x;
+  if (o >= n) return;
+  int tid = threadIdx.x;
+  double h = ldexp(D, -lev[o]);
+  double dx = delta[3 * o], dy = delta[3 * o + 1], dz = delta[3 * o + 2];
+  if (tid < P) {
+    double s, c;
+    sincospi(-2.0 * (double)tid / (double)P, &s, &c);
+    W[tid] = {c, s};
+  }
+  for (int i = tid; i < P3; i += blockDim.x) {
+    int m0 = i % P, m1 = (i / P) % P, m2 = i / (P * P);
+    int j0 = m0 <= L - 1 ? m0 : m0 - P;
+    int j1 = m1 <= L - 1 ? m1 : m1 - P;
+    int j2 = m2 <= L - 1 ? m2 : m2 - P;
+    double z0 = h * dx + (h / (double)(L - 1)) * (double)j0;
+    double z1 = h * dy + (h / (double)(L - 1)) * (double)j1;
+    double z2 = h * dz + (h / (double)(L - 1)) * (double)j2;
+    double r = sqrt(z0 * z0 + z1 * z1 + z2 * z2);
+    double s, c;
+    sincos(kappa * r, &s, &c);
+    double g = 1.0 / (4.0 * M_PI * r);
+    a[i] = {c * g, s * g};
+  }
+  __syncthreads();
+  const int stride[3] = {1, P, P * P};
+#pragma unroll 1
+  for (int d = 0; d < 3; ++d) {
+    for (int line = tid; line < P * P; line += blockDim.x) {
+      int base;
+      if (d == 0) base = line * P;
+      else if (d == 1) base = (line % P) + (line / P) * P * P;
+      else base = line;
+      C2<double> in[P];
+#pragma unroll
+      for (int m = 0; m < P; ++m) in[m] = a[base + m * stride[d]];
+#pragma unroll
+      for (int k = 0; k < P; ++k) {
+        C2<double> acc = {0.0, 0.0};
+#pragma unroll
+        for (int m = 0; m < P; ++m) cfma(acc, in[m], W[(k * m) % P]);
+        a[base + k * stride[d]] = acc;
+      }
+    }
+    __syncthreads();
+  }
+  const double scale = 1.0 / (double)P3;
+  for (int i = tid; i < P3; i += blockDim.x)
+    S[o * P3 + i] = {(R)(a[i].x * scale), (R)(a[i].y * scale)};
+}
+
+// ------------------------------------------------------------------ P2M
+// M^u(y_r) = exp(ik<y_r - a, u>) sum_y S_r(y) exp(-ik<y - a, u>) q(y): the
+// phases split at the cell corner a, one thread per node r.
+template <typename R, int L>
+__global__ __launch_bounds__(round64(L* L* L)) void k_p2m(int64_t n, const int32_t* __restrict__ exps,
+                                                         TreeView T, Geo g, const C2<R>* __restrict__ qs,
+                                                         C2<R>* __restrict__ M) {
+  constexpr int L3 = L * L * L, PT = 64;
+  __shared__ R w[PT][3][L];
+  __shared__ C2<R> qq[PT];
+  int64_t item = blockIdx.x;
+  if (item >= n) return;
+  int e = exps[item];
+  int c = T.exp_cell[e];
+  double h = ldexp(g.D, -T.level[c]);
+  double ax = g.ox + h * T.ijk[3 * c], ay = g.oy + h * T.ijk[3 * c + 1], az = g.oz + h * T.ijk[3 * c + 2];
+  double ux = T.exp_u[3 * e], uy = T.exp_u[3 * e + 1], uz = T.exp_u[3 * e + 2];
+  int first = T.first[c], cnt = T.count[c];
+  int tid = threadIdx.x;
+  int rx = tid % L, ry = (tid / L) % L, rz = tid / (L * L);
+  C2<R> acc = {(R)0, (R)0};
+  for (int base = 0; base < cnt; base += PT) {
+    int j = base + tid;
+    if (tid < PT && j < cnt) {
+      int64_t pi = first + j;
+      double d0 = T.soa[pi] - ax, d1 = T.soa[T.n + pi] - ay, d2 = T.soa[2 * T.n + pi] - az;
+      lagrange<R, L>((R)(d0 / h), w[tid][0]);
+      lagrange<R, L>((R)(d1 / h), w[tid][1]);
+      lagrange<R, L>((R)(d2 / h), w[tid][2]);
+      qq[tid] = cmul(qs[pi], expi<R>(-g.kappa * (ux * d0 + uy * d1 + uz * d2)));
+    }
+    __syncthreads();
+    int m = min(PT, cnt - base);
+    if (tid < L3)
+      for (int k = 0; k < m; ++k) cfma(acc, qq[k], {w[k][0][rx] * w[k][1][ry] * w[k][2][rz], (R)0});
+    __syncthreads();
+  }
+  if (tid < L3) {
+    double arg = g.kappa * h / (double)(L - 1) * (ux * rx + uy * ry + uz * rz);
+    M[(int64_t)e * L3 + tid] = cmul(acc, expi<R>(arg));
+  }
+}
+
+// Interpolation matrices between a cell and its sons (Sec. 5.2, tensorised
+// M2M/L2L): A[b][l][r] = l_l((b + r/(L-1))/2), b = son half along an axis.
+template <typename R, int L>
+__device__ __forceinline__ void son_matrices(R (*A)[L][L]) {
+  int tid = threadIdx.x;
+  if (tid < 2 * L) {
+    int b = tid / L, r = tid % L;
+    R w[L];
+    lagrange<R, L>(((R)b + (R)r / (R)(L - 1)) * (R)0.5, w);
+#pragma unroll
+    for (int l = 0; l < L; ++l) A[b][l][r] = w[l];
+  }
+}
+
+// ------------------------------------------------------------------ M2M
+// M_s^v(y_l) = D0 (x)A_b (D1 M_{s'}) summed over sons (eq. dlefturight):
+// D1 = exp(-ik<y'_r - a_s, v>), three mode products with the real son
+// matrices (Sec. 5.2.3), D0 = exp(ik<y_l - a_s, v>).  One thread per node.
+template <typename R, int L>
+__global__ __launch_bounds__(round64(L* L* L)) void k_m2m(int64_t n, const int32_t* __restrict__ par,
+                                                         const int32_t* __restrict__ child,
+                                                         const int8_t* __restrict__ oct, TreeView T, Geo g,
+                                                         C2<R>* __restrict__ M) {
+  constexpr int L3 = L * L * L;
+  __shared__ R A[2][L][L];
+  __shared__ C2<R> ph[3][L];
+  __shared__ C2<R> b0[L3], b1[L3];
+  int64_t item = blockIdx.x;
+  if (item >= n) return;
+  int pe = par[item];
+  int c = T.exp_cell[pe];
+  double h = ldexp(g.D, -T.level[c]), hc = 0.5 * h;
+  double v[3] = {T.exp_u[3 * pe], T.exp_u[3 * pe + 1], T.exp_u[3 * pe + 2]};
+  int tid = threadIdx.x;
+  int lx = tid % L, ly = (tid / L) % L, lz = tid / (L * L);
+  son_matrices<R, L>(A);
+  C2<R> acc = {(R)0, (R)0};
+  for (int k = 0; k < 8; ++k) {
+    int ce = child[item * 8 + k];
+    if (ce < 0) break;
+    int o = oct[item * 8 + k];
+    int b[3] = {o & 1, (o >> 1) & 1, (o >> 2) & 1};
+    __syncthreads();
+    if (tid < 3 * L) {
+      int d = tid / L, r = tid % L;
+      ph[d][r] = expi<R>(-g.kappa * hc * v[d] * ((double)b[d] + (double)r / (double)(L - 1)));
+    }
+    __syncthreads();
+    if (tid < L3) b0[tid] = cmul(cmul(M[(int64_t)ce * L3 + tid], ph[0][lx]), cmul(ph[1][ly], ph[2][lz]));
+    __syncthreads();
+    if (tid < L3) {
+      C2<R> s = {(R)0, (R)0};
+#pragma unroll
+      for (int r = 0; r < L; ++r) cfma(s, b0[r + L * ly + L * L * lz], {A[b[0]][lx][r], (R)0});
+      b1[tid] = s;
+    }
+    __syncthreads();
+    if (tid < L3) {
+      C2<R> s = {(R)0, (R)0};
+#pragma unroll
+      for (int r = 0; r < L; ++r) cfma(s, b1[lx + L * r + L * L * lz], {A[b[1]][ly][r], (R)0});
+      b0[tid] = s;
+    }
+    __syncthreads();
+    if (tid < L3) {
+#pragma unroll
+      for (int r = 0; r < L; ++r) cfma(acc, b0[lx + L * ly + L * L * r], {A[b[2]][lz][r], (R)0});
+    }
+  }
+  if (tid < L3) {
+    double arg = g.kappa * h / (double)(L - 1) * (v[0] * lx + v[1] * ly + v[2] * lz);
+    M[(int64_t)pe * L3 + tid] = cmul(acc, expi<R>(arg));
+  }
+}
+
+// ------------------------------------------------------------------ M2F
+// M~ = DFT_P(pad(M)): three pruned 1D DFT passes (x, y, z) in LDS; only the
+// L nonzero inputs of each line enter the sums.
+template <typename R, int L>
+__global__ __launch_bounds__(256) void k_m2f(int64_t n, const int32_t* __restrict__ src,
+                                             const C2<R>* __restrict__ M, C2<R>* __restrict__ Mt) {
+  constexpr int P = 2 * L - 1, P3 = P * P * P, L3 = L * L * L;
+  __shared__ C2<R> W[P];
+  __shared__ C2<R> a[L3];
+  __shared__ C2<R> b[P * L * L];
+  __shared__ C2<R> c[P * P * L];
+  int64_t item = blockIdx.x;
+  if (item >= n) return;
+  int e = src[item];
+  int tid = threadIdx.x;
+  if (tid < P) W[tid] = expi<R>(-2.0 * M_PI * (double)tid / (double)P);
+  for (int i = tid; i < L3; i += 256) a[i] = M[(int64_t)e * L3 + i];
+  __syncthreads();
+  for (int i = tid; i < P * L * L; i += 256) {
+    int xi = i % P, rest = i / P;
+    C2<R> s = {(R)0, (R)0};
+#pragma unroll
+    for (int r = 0; r < L; ++r) cfma(s, a[r + L * rest], W[(xi * r) % P]);
+    b[i] = s;
+  }
+  __syncthreads();
+  for (int i = tid; i < P * P * L; i += 256) {
+    int xi = i % P, yi = (i / P) % P, rz = i / (P * P);
+    C2<R> s = {(R)0, (R)0};
+#pragma unroll
+    for (int r = 0; r < L; ++r) cfma(s, b[xi + P * (r + L * rz)], W[(yi * r) % P]);
+    c[i] = s;
+  }
+  __syncthreads();
+  for (int i = tid; i < P3; i += 256) {
+    int xy = i % (P * P), zi = i / (P * P);
+    C2<R> s = {(R)0, (R)0};
+#pragma unroll
+    for (int r = 0; r < L; ++r) cfma(s, c[xy + P * P * r], W[(zi * r) % P]);
+    Mt[item * P3 + i] = s;
+  }
+}
+
+// ------------------------------------------------------------------ M2L + F2L
+// For one target expansion: L~ = sum over its list of D_{l,delta} (.) M~_s
+// (Hadamard products, Sec. 2.3), then F2L = pruned inverse DFT restricted to
+// [0,L)^3 (the 1/P^3 is folded into the spectra).  Each thread owns NF
+// frequencies; operand loads are contiguous across the workgroup.
+template <typename R, int L>
+__global__ __launch_bounds__(256) void k_m2l(int64_t ntgt, const int32_t* __restrict__ tgt,
+                                             const int32_t* __restrict__ begin, const int32_t* __restrict__ src,
+                                             const int32_t* __restrict__ off, const C2<R>* __restrict__ Mt,
+                                             const C2<R>* __restrict__ S, C2<R>* __restrict__ Lx) {
+  constexpr int P = 2 * L - 1, P3 = P * P * P, L3 = L * L * L;
+  constexpr int NT = 256, NF = (P3 + NT - 1) / NT;
+  __shared__ C2<R> A[P3];
+  __shared__ C2<R> B1[P * P * L];
+  __shared__ C2<R> B2[P * L * L];
+  __shared__ C2<R> W[P];
+  int64_t i = xcd_item(ntgt);
+  if (i >= ntgt) return;
+  int tid = threadIdx.x;
+  C2<R> acc[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) acc[f] = {(R)0, (R)0};
+  int kb = begin[i], ke = begin[i + 1];
+  for (int k = kb; k < ke; ++k) {
+    const C2<R>* ms = Mt + (int64_t)src[k] * P3;
+    const C2<R>* ds = S + (int64_t)off[k] * P3;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      int xi = tid + f * NT;
+      if (xi < P3) cfma(acc[f], ds[xi], ms[xi]);
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    int xi = tid + f * NT;
+    if (xi < P3) A[xi] = acc[f];
+  }
+  if (tid < P) W[tid] = expi<R>(2.0 * M_PI * (double)tid / (double)P);
+  __syncthreads();
+  for (int j = tid; j < P * P * L; j += NT) {  // z: (xi, yi, kz)
+    int xy = j % (P * P), kz = j / (P * P);
+    C2<R> s = {(R)0, (R)0};
+#pragma unroll
+    for (int m = 0; m < P; ++m) cfma(s, A[xy + P * P * m], W[(m * kz) % P]);
+    B1[j] = s;
+  }
+  __syncthreads();
+  for (int j = tid; j < P * L * L; j += NT) {  // y: (xi, ky, kz)
+    int xi = j % P, ky = (j / P) % L, kz = j / (P * L);
+    C2<R> s = {(R)0, (R)0};
+#pragma unroll
+    for (int m = 0; m < P; ++m) cfma(s, B1[xi + P * m + P * P * kz], W[(m * ky) % P]);
+    B2[j] = s;
+  }
+  __syncthreads();
+  for (int j = tid; j < L3; j += NT) {  // x: (kx, ky, kz)
+    int kx = j % L, kyz = j / L;
+    C2<R> s = {(R)0, (R)0};
+#pragma unroll
+    for (int m = 0; m < P; ++m) cfma(s, B2[m + P * kyz], W[(m * kx) % P]);
+    Lx[(int64_t)tgt[i] * L3 + j] = s;
+  }
+}
+
+// ------------------------------------------------------------------ L2L
+// L_{t'}^u(x'_h) += sum over father expansions v with Father(v) = u of
+// exp(ik<x'_h - a_t, v>) (x)A_b^T (exp(-ik<x_k - a_t, v>) L_t^v).
+template <typename R, int L>
+__global__ __launch_bounds__(round64(L* L* L)) void k_l2l(int64_t n, const int32_t* __restrict__ ch,
+                                                         const int32_t* __restrict__ begin,
+                                                         const int32_t* __restrict__ par,
+                                                         const int8_t* __restrict__ oct, TreeView T, Geo g,
+                                                         C2<R>* __restrict__ Lx) {
+  constexpr int L3 = L * L * L;
+  __shared__ R A[2][L][L];
+  __shared__ C2<R> phi[3][L], pho[3][L];
+  __shared__ C2<R> b0[L3], b1[L3];
+  int64_t item = blockIdx.x;
+  if (item >= n) return;
+  int ce = ch[item];
+  int c = T.exp_cell[ce];
+  double hc = ldexp(g.D, -T.level[c]), hp = 2.0 * hc;
+  int tid = threadIdx.x;
+  int hx = tid % L, hy = (tid / L) % L, hz = tid / (L * L);
+  son_matrices<R, L>(A);
+  C2<R> acc = {(R)0, (R)0};
+  for (int k = begin[item]; k < begin[item + 1]; ++k) {
+    int pe = par[k];
+    int o = oct[k];
+    int b[3] = {o & 1, (o >> 1) & 1, (o >> 2) & 1};
+    double v[3] = {T.exp_u[3 * pe], T.exp_u[3 * pe + 1], T.exp_u[3 * pe + 2]};
+    __syncthreads();
+    if (tid < 3 * L) {
+      int d = tid / L, r = tid % L;
+      phi[d][r] = expi<R>(-g.kappa * hp * v[d] * ((double)r / (double)(L - 1)));
+      pho[d][r] = expi<R>(g.kappa * hc * v[d] * ((double)b[d] + (double)r / (double)(L - 1)));
+    }
+    __syncthreads();
+    if (tid < L3) b0[tid] = cmul(cmul(Lx[(int64_t)pe * L3 + tid], phi[0][hx]), cmul(phi[1][hy], phi[2][hz]));
+    __syncthreads();
+    if (tid < L3) {  // (hx, ky, kz)
+      C2<R> s = {(R)0, (R)0};
+#pragma unroll
+      for (int kk = 0; kk < L; ++kk) cfma(s, b0[kk + L * hy + L * L * hz], {A[b[0]][kk][hx], (R)0});
+      b1[tid] = s;
+    }
+    __syncthreads();
+    if (tid < L3) {  // (hx, hy, kz)
+      C2<R> s = {(R)0, (R)0};
+#pragma unroll
+      for (int kk = 0; kk < L; ++kk) cfma(s, b1[hx + L * kk + L * L * hz], {A[b[1]][kk][hy], (R)0});
+      b0[tid] = s;
+    }
+    __syncthreads();
+    if (tid < L3) {
+      C2<R> s = {(R)0, (R)0};
+#pragma unroll
+      for (int kk = 0; kk < L; ++kk) cfma(s, b0[hx + L * hy + L * L * kk], {A[b[2]][kk][hz], (R)0});
+      C2<R> t = cmul(cmul(s, pho[0][hx]), cmul(pho[1][hy], pho[2][hz]));
+      acc.x += t.x;
+      acc.y += t.y;
+    }
+  }
+  if (tid < L3) {
+    C2<R> cur = Lx[(int64_t)ce * L3 + tid];
+    Lx[(int64_t)ce * L3 + tid] = {cur.x + acc.x, cur.y + acc.y};
+  }
+}
+
+// ------------------------------------------------------------------ L2P
+// p(x) += sum_u exp(ik<x - a, u>) sum_h S_h(x) exp(-ik<x_h - a, u>) L^u(x_h).
+template <typename R, int L>
+__global__ __launch_bounds__(64) void k_l2p(int64_t n, const int32_t* __restrict__ cell,
+                                            const int32_t* __restrict__ pfirst, const int32_t* __restrict__ pcount,
+                                            TreeView T, Geo g, const C2<R>* __restrict__ Lx,
+                                            C2<R>* __restrict__ ps) {
+  constexpr int L3 = L * L * L, PER = 4;  // up to 256 points per item
+  __shared__ C2<R> Lp[L3];
+  int64_t item = blockIdx.x;
+  if (item >= n) return;
+  int c = cell[item];
+  double h = ldexp(g.D, -T.level[c]);
+  double ax = g.ox + h * T.ijk[3 * c], ay = g.oy + h * T.ijk[3 * c + 1], az = g.oz + h * T.ijk[3 * c + 2];
+  int first = pfirst[item], cnt = pcount[item];
+  int tid = threadIdx.x;
+  C2<R> acc[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) acc[q] = {(R)0, (R)0};
+  for (int e = T.exp_begin[c]; e < T.exp_begin[c + 1]; ++e) {
+    double ux = T.exp_u[3 * e], uy = T.exp_u[3 * e + 1], uz = T.exp_u[3 * e + 2];
+    __syncthreads();
+    for (int i = tid; i < L3; i += 64) {
+      int kx = i % L, ky = (i / L) % L, kz = i / (L * L);
+      double arg = -g.kappa * h / (double)(L - 1) * (ux * kx + uy * ky + uz * kz);
+      Lp[i] = cmul(Lx[(int64_t)e * L3 + i], expi<R>(arg));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      int j = tid + 64 * q;
+      if (j < cnt) {
+        int64_t pi = first + j;
+        double d0 = T.soa[pi] - ax, d1 = T.soa[T.n + pi] - ay, d2 = T.soa[2 * T.n + pi] - az;
+        R wx[L], wy[L], wz[L];
+        lagrange<R, L>((R)(d0 / h), wx);
+        lagrange<R, L>((R)(d1 / h), wy);
+        lagrange<R, L>((R)(d2 / h), wz);
+        C2<R> sz = {(R)0, (R)0};
+#pragma unroll
+        for (int kz = 0; kz < L; ++kz) {
+          C2<R> sy = {(R)0, (R)0};
+#pragma unroll
+          for (int ky = 0; ky < L; ++ky) {
+            C2<R> sx = {(R)0, (R)0};
+#pragma unroll
+            for (int kx = 0; kx < L; ++kx) cfma(sx, Lp[kx + L * ky + L * L * kz], {wx[kx], (R)0});
+            cfma(sy, sx, {wy[ky], (R)0});
+          }
+          cfma(sz, sy, {wz[kz], (R)0});
+        }
+        cfma(acc[q], sz, expi<R>(g.kappa * (ux * d0 + uy * d1 + uz * d2)));
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    int j = tid + 64 * q;
+    if (j < cnt) {
+      C2<R> cur = ps[first + j];
+      ps[first + j] = {cur.x + acc[q].x, cur.y + acc[q].y};
+    }
+  }
+}
+
+// ------------------------------------------------------------------ P2P
+// Near field (Sec. 2.2 P2P, Sec. 5.3 singular pairs): one work item = one
+// block of <= 64 target points of a leaf and a chunk of its source ranges.
+// Lanes are (target, sub-stream) pairs; sources are staged through LDS in
+// tiles of 256; differences are formed in FP64 (coordinates are FP64), the
+// rest in R.  Partial sums per work item are reduced in a fixed order.
+template <typename R>
+__device__ __forceinline__ void p2p_pair(C2<R>& acc, double x0, double x1, double x2, double y0, double y1,
+                                         double y2, C2<R> q, R kap2pi, R kappa, R tau2);
+
+template <>
+__device__ __forceinline__ void p2p_pair<float>(C2<float>& acc, double x0, double x1, double x2, double y0,
+                                                double y1, double y2, C2<float> q, float kap2pi, float,
+                                                float tau2) {
+  float dx = (float)(x0 - y0), dy = (float)(x1 - y1), dz = (float)(x2 - y2);
+  float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+  float rinv = __builtin_amdgcn_rsqf(r2);
+  rinv = r2 > tau2 ? rinv : 0.0f;
+  float r = r2 * rinv;
+  float f = __builtin_amdgcn_fractf(r * kap2pi);  // revolutions of kappa r
+  float sn = __builtin_amdgcn_sinf(f);             // sin(2 pi f)
+  float cs = __builtin_amdgcn_cosf(f);
+  float gr = cs * rinv, gi = sn * rinv;
+  acc.x = fmaf(gr, q.x, fmaf(-gi, q.y, acc.x));
+  acc.y = fmaf(gr, q.y, fmaf(gi, q.x, acc.y));
+}
+
+template <>
+__device__ __forceinline__ void p2p_pair<double>(C2<double>& acc, double x0, double x1, double x2, double y0,
+                                                 double y1, double y2, C2<double> q, double, double kappa,
+                                                 double tau2) {
+  double dx = x0 - y0, dy = x1 - y1, dz = x2 - y2;
+  double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+  if (r2 > tau2) {
+    double r = sqrt(r2);
+    double rinv = 1.0 / r;
+    double s, c;
+    sincos(kappa * r, &s, &c);
+    double gr = c * rinv, gi = s * rinv;
+    acc.x = fma(gr, q.x, fma(-gi, q.y, acc.x));
+    acc.y = fma(gr, q.y, fma(gi, q.x, acc.y));
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_p2p(int64_t nwi, const int32_t* __restrict__ wi_blk,
+                                             const int32_t* __restrict__ wi_seg, const int32_t* __restrict__ seg_first,
+                                             const int32_t* __restrict__ seg_count, const int32_t* __restrict__ blk_first,
+                                             const int32_t* __restrict__ blk_count, const double* __restrict__ X,
+                                             int64_t nx, const double* __restrict__ Y, int64_t ny,
+                                             const C2<R>* __restrict__ qs, C2<R>* __restrict__ part, double kappa,
+                                             double tau2) {
+  constexpr int NT = 256;
+  __shared__ double sx[NT], sy[NT], sz[NT];
+  __shared__ C2<R> sq[NT];
+  __shared__ C2<R> red[NT];
+  int64_t w = xcd_item(nwi);
+  if (w >= nwi) return;
+  int blk = wi_blk[w];
+  int tf = blk_first[blk], tc = blk_count[blk];
+  int S = NT / tc;
+  int tid = threadIdx.x;
+  int ti = tid % tc, sub = tid / tc;
+  bool active = sub < S;
+  double x0 = 0, x1 = 0, x2 = 0;
+  if (active) {
+    x0 = X[tf + ti];
+    x1 = X[nx + tf + ti];
+    x2 = X[2 * nx + tf + ti];
+  }
+  const R inv4pi = (R)(1.0 / (4.0 * M_PI));
+  const R kap2pi = (R)(kappa / (2.0 * M_PI));
+  C2<R> acc = {(R)0, (R)0};
+  for (int sg = wi_seg[w]; sg < wi_seg[w + 1]; ++sg) {
+    int f = seg_first[sg], cnt = seg_count[sg];
+    for (int base = 0; base < cnt; base += NT) {
+      int j = base + tid;
+      if (j < cnt) {
+        sx[tid] = Y[f + j];
+        sy[tid] = Y[ny + f + j];
+        sz[tid] = Y[2 * ny + f + j];
+        sq[tid] = cscale(qs[f + j], inv4pi);
+      }
+      __syncthreads();
+      int m = min(NT, cnt - base);
+      if (active)
+        for (int k = sub; k < m; k += S)
+          p2p_pair<R>(acc, x0, x1, x2, sx[k], sy[k], sz[k], sq[k], kap2pi, (R)kappa, (R)tau2);
+      __syncthreads();
+    }
+  }
+  red[tid] = acc;
+  __syncthreads();
+  if (tid < tc) {
+    C2<R> s = {(R)0, (R)0};
+    for (int u = 0; u < S; ++u) {
+      s.x += red[u * tc + tid].x;
+      s.y += red[u * tc + tid].y;
+    }
+    part[w * 64 + tid] = s;
+  }
+}
+
+template <typename R>
+__global__ void k_p2p_reduce(int64_t nblk, const int32_t* __restrict__ blk_first,
+                             const int32_t* __restrict__ blk_count, const int32_t* __restrict__ blk_wi,
+                             const C2<R>* __restrict__ part, C2<R>* __restrict__ ps) {
+  int64_t b = blockIdx.x;
+  int tid = threadIdx.x;
+  if (b >= nblk || tid >= blk_count[b]) return;
+  C2<R> s = {(R)0, (R)0};
+  for (int w = blk_wi[b]; w < blk_wi[b + 1]; ++w) {
+    C2<R> v = part[(int64_t)w * 64 + tid];
+    s.x += v.x;
+    s.y += v.y;
+  }
+  ps[blk_first[b] + tid] = s;
+}
+
+// ------------------------------------------------------------------ launchers
+#define DEFMM_L_SWITCH(Lval, ...)                          \
+  switch (Lval) {                                          \
+    case 2: { constexpr int LL = 2; __VA_ARGS__; } break;  \
+    case 3: { constexpr int LL = 3; __VA_ARGS__; } break;  \
+    case 4: { constexpr int LL = 4; __VA_ARGS__; } break;  \
+    case 5: { constexpr int LL = 5; __VA_ARGS__; } break;  \
+    case 6: { constexpr int LL = 6; __VA_ARGS__; } break;  \
+    case 7: { constexpr int LL = 7; __VA_ARGS__; } break;  \
+    case 8: { constexpr int LL = 8; __VA_ARGS__; } break;  \
+    default: return hipErrorInvalidValue;                  \
+  }
+
+template <typename R>
+static hipError_t spectra_impl(DevPlan& P, const int32_t* lev, const int32_t* delta, hipStream_t s) {
+  if (P.n_off == 0) return hipSuccess;
+  DEFMM_L_SWITCH(P.L, hipLaunchKernelGGL((k_spectra<R, LL>), dim3((unsigned)P.n_off), dim3(256), 0, s, P.n_off,
+                                         lev, delta, P.kappa, P.D, (C2<R>*)P.spectra));
+  return hipGetLastError();
+}
+
+hipError_t compute_spectra(DevPlan& P, const int32_t* lev, const int32_t* delta, hipStream_t s) {
+  return P.precision == 0 ? spectra_impl<double>(P, lev, delta, s) : spectra_impl<float>(P, lev, delta, s);
+}
+
+namespace {
+
+struct PassTimer {
+  Workspace& W;
+  hipStream_t s;
+  int pass = -1;
+  size_t a = 0;
+  PassTimer(Workspace& w, hipStream_t st) : W(w), s(st) {}
+  hipEvent_t next() {
+    if (W.ev_used == W.ev_pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      W.ev_pool.push_back(e);
+    }
+    return W.ev_pool[W.ev_used++];
+  }
+  void begin(int p) {
+    if (!W.timing) return;
+    pass = p;
+    a = W.ev_used;
+    hipEvent_t e = next();
+    if (e) (void)hipEventRecord(e, s);
+  }
+  void end() {
+    if (!W.timing || pass < 0) return;
+    size_t b = W.ev_used;
+    hipEvent_t e = next();
+    if (e) {
+      (void)hipEventRecord(e, s);
+      W.pending.push_back({pass, a, b});
+    }
+    pass = -1;
+  }
+};
+
+inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+template <typename R>
+static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, hipStream_t s) {
+  const int L = P.L;
+  const int L3 = L * L * L;
+  Geo g{P.kappa, P.D, P.origin[0], P.origin[1], P.origin[2]};
+  TreeView TX = view(P.tx), TY = view(P.ty);
+  C2<R>* qs = (C2<R>*)W.qs;
+  C2<R>* ps = (C2<R>*)W.ps;
+  C2<R>* M = (C2<R>*)W.M;
+  C2<R>* Lx = (C2<R>*)W.Lx;
+  C2<R>* Mt = (C2<R>*)W.Mt;
+  C2<R>* part = (C2<R>*)W.part;
+  const C2<R>* S = (const C2<R>*)P.spectra;
+  PassTimer tm(W, s);
+
+  tm.begin(kPassSetup);
+  if (P.ny > 0)
+    hipLaunchKernelGGL((k_gather<R>), dim3(blocks_for(P.ny, 256)), dim3(256), 0, s, P.ny, P.ty.perm,
+                       (const C2<R>*)q, qs);
+  if (P.tx.nexp > 0)
+    hipLaunchKernelGGL((k_zero<R>), dim3(blocks_for(P.tx.nexp * L3, 256)), dim3(256), 0, s, P.tx.nexp * L3, Lx);
+  if (P.nx > 0) hipLaunchKernelGGL((k_zero<R>), dim3(blocks_for(P.nx, 256)), dim3(256), 0, s, P.nx, ps);
+  tm.end();
+
+  tm.begin(kPassP2M);
+  if (P.n_p2m > 0)
+    DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_p2m<R, LL>), dim3((unsigned)P.n_p2m), dim3(round64(LL * LL * LL)), 0,
+                                          s, P.n_p2m, P.p2m_exp, TY, g, (const C2<R>*)qs, M));
+  tm.end();
+
+  tm.begin(kPassM2M);
+  for (int l = (int)P.m2m.size() - 1; l >= 0; --l) {
+    const LevelTable& t = P.m2m[l];
+    if (t.n == 0) continue;
+    DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2m<R, LL>), dim3((unsigned)t.n), dim3(round64(LL * LL * LL)), 0, s,
+                                          t.n, t.a, t.b, t.oct, TY, g, M));
+  }
+  tm.end();
+
+  tm.begin(kPassM2F);
+  if (P.n_m2f > 0)
+    DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2f<R, LL>), dim3((unsigned)P.n_m2f), dim3(256), 0, s, P.n_m2f,
+                                          P.m2f_exp, (const C2<R>*)M, Mt));
+  tm.end();
+
+  tm.begin(kPassM2L);
+  if (P.n_m2l_tgt > 0)
+    DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l<R, LL>), dim3(xcd_grid(P.n_m2l_tgt)), dim3(256), 0, s,
+                                          P.n_m2l_tgt, P.m2l_tgt, P.m2l_begin, P.m2l_src, P.m2l_off,
+                                          (const C2<R>*)Mt, S, Lx));
+  tm.end();
+
+  tm.begin(kPassL2L);
+  for (size_t l = 0; l < P.l2l.size(); ++l) {
+    const LevelTable& t = P.l2l[l];
+    if (t.n == 0) continue;
+    DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_l2l<R, LL>), dim3((unsigned)t.n), dim3(round64(LL * LL * LL)), 0, s,
+                                          t.n, t.a, t.b, t.c, t.oct, TX, g, Lx));
+  }
+  tm.end();
+
+  tm.begin(kPassP2P);
+  if (P.nwi > 0)
+    hipLaunchKernelGGL((k_p2p<R>), dim3(xcd_grid(P.nwi)), dim3(256), 0, s, P.nwi, P.wi_blk, P.wi_seg_begin,
+                       P.seg_first, P.seg_count, P.blk_first, P.blk_count, P.tx.soa, P.tx.n, P.ty.soa, P.ty.n,
+                       (const C2<R>*)qs, part, P.kappa, P.tau * P.tau);
+  tm.end();
+
+  tm.begin(kPassP2PRed);
+  if (P.nblk > 0)
+    hipLaunchKernelGGL((k_p2p_reduce<R>), dim3((unsigned)P.nblk), dim3(64), 0, s, P.nblk, P.blk_first,
+                       P.blk_count, P.blk_wi_begin, (const C2<R>*)part, ps);
+  tm.end();
+
+  tm.begin(kPassL2P);
+  if (P.n_l2p > 0)
+    DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_l2p<R, LL>), dim3((unsigned)P.n_l2p), dim3(64), 0, s, P.n_l2p,
+                                          P.l2p_cell, P.l2p_first, P.l2p_count, TX, g, (const C2<R>*)Lx, ps));
+  tm.end();
+
+  tm.begin(kPassScatter);
+  if (P.nx > 0)
+    hipLaunchKernelGGL((k_scatter<R>), dim3(blocks_for(P.nx, 256)), dim3(256), 0, s, P.nx, P.tx.perm,
+                       (const C2<R>*)ps, (C2<R>*)p);
+  tm.end();
+  return hipGetLastError();
+}
+
+hipError_t run_matvec(DevPlan& P, Workspace& W, const void* q, void* p, hipStream_t s) {
+  return P.precision == 0 ? matvec_impl<double>(P, W, q, p, s) : matvec_impl<float>(P, W, q, p, s);
+}
+
+}  // namespace defmm

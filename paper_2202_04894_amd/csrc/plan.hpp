@@ -1,0 +1,100 @@
+// Internal plan structures of libdefmm: the host-side build of the tree,
+// traversal lists, marks and operator tables, and the device mirror the
+// matvec kernels read.  Not part of the C ABI.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace defmm {
+
+constexpr int kKeyBits = 21;   // Morton key bits per dimension
+constexpr int kMaxLevel = 21;  // cells at this level are always leaves
+constexpr int kP2PBlock = 64;  // target points per P2P block
+constexpr int kP2PChunk = 4096;  // source points per P2P work item (balance)
+constexpr int kL2PChunk = 256;   // target points per L2P work item
+
+struct BuildParams {
+  int L = 5;
+  int ncrit = 64;
+  double eta = 1.0;
+  double hf_threshold = 2.0;
+  int dir_refine = 0;
+  bool same_points = false;
+  double kappa = 0.0;
+};
+
+// One 2^d-tree over a point set, level-major, Morton order inside a level.
+struct Tree {
+  int64_t n = 0;
+  std::vector<int32_t> perm;   // sorted position -> caller index
+  std::vector<double> soa;     // sorted coordinates, x[n] y[n] z[n]
+  std::vector<uint64_t> key;   // sorted Morton keys
+  int nlevels = 0;
+  std::vector<int64_t> lev_start;  // nlevels + 1
+  std::vector<int32_t> level, first, count, leaf, child0, nchild, parent;
+  std::vector<int32_t> ijk;        // 3 per cell
+  // marks = effective expansions (cell, direction), sorted per cell; -1 = none
+  std::vector<int64_t> exp_begin;  // ncells + 1
+  std::vector<int32_t> exp_dir, exp_cell;
+  std::vector<double> exp_u;       // 3 per expansion, zero vector for -1
+  int64_t ncells() const { return (int64_t)level.size(); }
+  int64_t nexp() const { return (int64_t)exp_dir.size(); }
+  int64_t find_exp(int32_t c, int32_t u) const;
+};
+
+struct Offset {  // one distinct (level, delta) M2L spectrum
+  int32_t level, d[3], dir;
+};
+
+// Everything the matvec needs, built on the host.
+struct HostPlan {
+  BuildParams prm;
+  double D = 0.0, origin[3] = {0, 0, 0}, tau = 0.0;
+  Tree tx, ty_own;
+  Tree* ty = nullptr;
+  int lstar = -1;
+  int hf[kMaxLevel + 2] = {0};
+  double thr[kMaxLevel + 2] = {0};
+  // direction sets per direction level, flattened
+  std::vector<double> dirs;
+  std::vector<int64_t> dir_off;  // per direction level E: offset (in directions), -1 if absent
+  std::vector<int64_t> father_flat;  // per direction (flattened): father index at E-1
+  // traversal output
+  struct M2L { int32_t t, s, off; };
+  std::vector<M2L> m2l;
+  std::vector<Offset> offsets;
+  std::vector<int32_t> p2p_t, p2p_s;
+  int64_t p2p_point_pairs = 0;
+
+  // ---- operator tables (device mirror in DevicePlan) ----
+  // P2M: source-leaf expansions
+  std::vector<int32_t> p2m_exp;
+  // M2M per level l (parents at l): parent expansions and 8 (child exp, octant) slots
+  std::vector<std::vector<int32_t>> m2m_par, m2m_child;  // child: 8 per parent, -1 empty
+  std::vector<std::vector<int8_t>> m2m_oct;
+  // M2F: source expansions used by M2L, mapped to rows of the Fourier table
+  std::vector<int32_t> m2f_exp;
+  // M2L: target expansions with interactions, CSR of (Fourier row, offset id)
+  std::vector<int32_t> m2l_tgt, m2l_begin;  // begin: ntgt + 1
+  std::vector<int32_t> m2l_src, m2l_off;
+  // L2L per level l (children at l+1): child expansions, CSR of (parent exp, octant)
+  std::vector<std::vector<int32_t>> l2l_ch, l2l_begin, l2l_par;
+  std::vector<std::vector<int8_t>> l2l_oct;
+  // L2P work items: (leaf, first point, count <= kL2PChunk)
+  std::vector<int32_t> l2p_cell, l2p_first, l2p_count;
+  // P2P: target blocks, work items with source segments
+  std::vector<int32_t> blk_first, blk_count, blk_wi_begin;  // blocks; wi CSR (nblk + 1)
+  std::vector<int32_t> wi_blk, wi_seg_begin;                 // work items; seg CSR (nwi + 1)
+  std::vector<int32_t> seg_first, seg_count;
+};
+
+// Builds the whole host plan; throws std::runtime_error / std::bad_alloc.
+void build_host_plan(HostPlan& hp, const double* X, int64_t nx, const double* Y, int64_t ny,
+                     const BuildParams& prm);
+
+int64_t num_directions(int E);
+void make_directions(int E, double* dirs, int64_t* father);
+
+}  // namespace defmm

@@ -1,0 +1,624 @@
+// Host-side plan builder: bounding cube, Morton sort, Ncrit tree (Sec. 4.2.1),
+// level-synchronous dual tree traversal (Alg. 1 with the MAC of
+// eq. macdirref), best directions and blank passes (Alg. 2, Alg. 3), and the
+// flat operator tables the device kernels read.
+//
+// Floating-point decisions (MAC thresholds, regime tests, direction choice)
+// are written with the same operations in the same order as the paper's
+// definitions so that the lists are reproducible bit for bit; this file must
+// be compiled without floating-point contraction.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <stdexcept>
+#include <thread>
+#include <unordered_map>
+
+#include "plan.hpp"
+
+namespace defmm {
+
+namespace {
+
+template <class F>
+void parallel_chunks(int64_t n, int64_t min_chunk, F&& f) {
+  unsigned hw = std::thread::hardware_concurrency();
+  int64_t nt = std::max<int64_t>(1, std::min<int64_t>(hw ? hw : 4, 32));
+  nt = std::min<int64_t>(nt, std::max<int64_t>(1, n / std::max<int64_t>(1, min_chunk)));
+  if (nt <= 1) {
+    f(0, n, 0);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int64_t t = 0; t < nt; ++t) {
+    int64_t b = n * t / nt, e = n * (t + 1) / nt;
+    th.emplace_back([&, b, e, t] { f(b, e, (int)t); });
+  }
+  for (auto& x : th) x.join();
+}
+
+uint64_t spread_bits(uint64_t v) {
+  // bit b of v -> bit 3b
+  v &= 0x1fffffull;
+  v = (v | (v << 32)) & 0x1f00000000ffffull;
+  v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+  v = (v | (v << 8)) & 0x100f00f00f00f00full;
+  v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+  v = (v | (v << 2)) & 0x1249249249249249ull;
+  return v;
+}
+
+int64_t quantise(double x, double o, double D) {
+  if (!(D > 0.0)) return 0;
+  double s = std::floor((x - o) / D * (double)(1 << kKeyBits));
+  if (s < 0.0) s = 0.0;
+  if (s > (double)((1 << kKeyBits) - 1)) s = (double)((1 << kKeyBits) - 1);
+  return (int64_t)s;
+}
+
+// Stable LSD radix sort of (key, index) by key; indices start in caller order.
+void radix_sort(std::vector<uint64_t>& key, std::vector<int32_t>& idx) {
+  size_t n = key.size();
+  std::vector<uint64_t> k2(n);
+  std::vector<int32_t> i2(n);
+  for (int pass = 0; pass < 8; ++pass) {
+    int sh = 8 * pass;
+    size_t cnt[257] = {0};
+    for (size_t i = 0; i < n; ++i) cnt[((key[i] >> sh) & 255) + 1]++;
+    if (cnt[1] == n) continue;  // all digits zero in this pass
+    bool skip = false;
+    for (int d = 0; d < 256; ++d)
+      if (cnt[d + 1] == n) skip = true;
+    if (skip) continue;
+    for (int d = 0; d < 256; ++d) cnt[d + 1] += cnt[d];
+    for (size_t i = 0; i < n; ++i) {
+      size_t pos = cnt[(key[i] >> sh) & 255]++;
+      k2[pos] = key[i];
+      i2[pos] = idx[i];
+    }
+    key.swap(k2);
+    idx.swap(i2);
+  }
+}
+
+void build_tree(Tree& T, const double* pts, int64_t n, const double* origin, double D, int ncrit) {
+  T.n = n;
+  std::vector<uint64_t> key(n);
+  std::vector<int32_t> idx(n);
+  parallel_chunks(n, 1 << 16, [&](int64_t b, int64_t e, int) {
+    for (int64_t i = b; i < e; ++i) {
+      uint64_t qx = (uint64_t)quantise(pts[3 * i + 0], origin[0], D);
+      uint64_t qy = (uint64_t)quantise(pts[3 * i + 1], origin[1], D);
+      uint64_t qz = (uint64_t)quantise(pts[3 * i + 2], origin[2], D);
+      key[i] = spread_bits(qx) | (spread_bits(qy) << 1) | (spread_bits(qz) << 2);
+      idx[i] = (int32_t)i;
+    }
+  });
+  radix_sort(key, idx);
+  T.key = std::move(key);
+  T.perm = std::move(idx);
+  T.soa.resize(3 * n);
+  for (int64_t i = 0; i < n; ++i)
+    for (int d = 0; d < 3; ++d) T.soa[d * n + i] = pts[3 * (int64_t)T.perm[i] + d];
+  // level 0: the root
+  T.level = {0};
+  T.first = {0};
+  T.count = {(int32_t)n};
+  T.parent = {-1};
+  T.ijk = {0, 0, 0};
+  T.leaf = {0};
+  T.child0 = {0};
+  T.nchild = {0};
+  T.lev_start = {0, 1};
+  for (int lev = 0;; ++lev) {
+    int64_t b = T.lev_start[lev], e = T.lev_start[lev + 1];
+    for (int64_t c = b; c < e; ++c) {
+      if (T.count[c] > ncrit && lev < kMaxLevel) {
+        T.leaf[c] = 0;
+        T.child0[c] = (int32_t)T.level.size();
+        int sh = 3 * (kKeyBits - lev - 1);
+        int64_t i = T.first[c], end = (int64_t)T.first[c] + T.count[c];
+        while (i < end) {
+          uint64_t dg = (T.key[i] >> sh) & 7ull;
+          int64_t j = i;
+          while (j < end && ((T.key[j] >> sh) & 7ull) == dg) ++j;
+          T.level.push_back(lev + 1);
+          T.first.push_back((int32_t)i);
+          T.count.push_back((int32_t)(j - i));
+          T.parent.push_back((int32_t)c);
+          T.ijk.push_back(2 * T.ijk[3 * c + 0] + (int32_t)(dg & 1));
+          T.ijk.push_back(2 * T.ijk[3 * c + 1] + (int32_t)((dg >> 1) & 1));
+          T.ijk.push_back(2 * T.ijk[3 * c + 2] + (int32_t)((dg >> 2) & 1));
+          T.leaf.push_back(0);
+          T.child0.push_back(0);
+          T.nchild.push_back(0);
+          T.nchild[c]++;
+          i = j;
+        }
+      } else {
+        T.leaf[c] = 1;
+      }
+    }
+    T.lev_start.push_back((int64_t)T.level.size());
+    if (T.lev_start[lev + 2] == T.lev_start[lev + 1]) {
+      T.nlevels = lev + 1;
+      T.lev_start.pop_back();
+      break;
+    }
+  }
+}
+
+// Flat open-addressing map (level, delta) -> offset id.
+struct OffsetMap {
+  std::vector<int32_t> slot;
+  std::vector<Offset>* offs;
+  uint64_t mask = 0;
+  explicit OffsetMap(std::vector<Offset>* o) : offs(o) { rehash(1 << 12); }
+  static uint64_t hash(int32_t l, const int32_t* d) {
+    uint64_t h = 0x9e3779b97f4a7c15ull * (uint64_t)(uint32_t)l;
+    for (int k = 0; k < 3; ++k) h = (h ^ (uint64_t)(uint32_t)d[k]) * 0xff51afd7ed558ccdull;
+    return h ^ (h >> 31);
+  }
+  void rehash(size_t cap) {
+    slot.assign(cap, -1);
+    mask = cap - 1;
+    for (size_t i = 0; i < offs->size(); ++i) {
+      uint64_t h = hash((*offs)[i].level, (*offs)[i].d) & mask;
+      while (slot[h] >= 0) h = (h + 1) & mask;
+      slot[h] = (int32_t)i;
+    }
+  }
+  int32_t get(int32_t l, const int32_t* d) {
+    if (offs->size() * 2 >= slot.size()) rehash(slot.size() * 2);
+    uint64_t h = hash(l, d) & mask;
+    while (slot[h] >= 0) {
+      const Offset& o = (*offs)[slot[h]];
+      if (o.level == l && o.d[0] == d[0] && o.d[1] == d[1] && o.d[2] == d[2]) return slot[h];
+      h = (h + 1) & mask;
+    }
+    Offset o;
+    o.level = l;
+    o.d[0] = d[0];
+    o.d[1] = d[1];
+    o.d[2] = d[2];
+    o.dir = -1;
+    offs->push_back(o);
+    slot[h] = (int32_t)(offs->size() - 1);
+    return slot[h];
+  }
+};
+
+}  // namespace
+
+int64_t num_directions(int E) { return 6ll << (2 * E); }
+
+// Projected face-patch centres of the cube (Sec. 4.1.2), index
+// face*4^E + i*2^E + j, father = enclosing patch at E-1.
+void make_directions(int E, double* dirs, int64_t* father) {
+  int64_t side = 1ll << E;
+  for (int f = 0; f < 6; ++f) {
+    int a = f / 2;
+    double sg = (f % 2 == 0) ? 1.0 : -1.0;
+    int b = (a == 0) ? 1 : 0;
+    int c = (a == 2) ? 1 : 2;
+    for (int64_t i = 0; i < side; ++i)
+      for (int64_t j = 0; j < side; ++j) {
+        double p[3];
+        p[a] = sg;
+        p[b] = -1.0 + (double)(2 * i + 1) / (double)side;
+        p[c] = -1.0 + (double)(2 * j + 1) / (double)side;
+        double nr = std::sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+        int64_t u = (int64_t)f * side * side + i * side + j;
+        for (int d = 0; d < 3; ++d) dirs[3 * u + d] = p[d] / nr;
+        father[u] = (E == 0) ? -1 : (int64_t)f * (side / 2) * (side / 2) + (i >> 1) * (side / 2) + (j >> 1);
+      }
+  }
+}
+
+int64_t Tree::find_exp(int32_t c, int32_t u) const {
+  const int32_t* b = exp_dir.data() + exp_begin[c];
+  const int32_t* e = exp_dir.data() + exp_begin[c + 1];
+  const int32_t* it = std::lower_bound(b, e, u);
+  if (it == e || *it != u) return -1;
+  return exp_begin[c] + (it - b);
+}
+
+namespace {
+
+int dir_level(const HostPlan& hp, int l) { return hp.lstar - l + hp.prm.dir_refine; }
+
+int32_t best_direction(const HostPlan& hp, int E, const int32_t* d) {
+  const double* V = hp.dirs.data() + 3 * hp.dir_off[E];
+  int64_t n = num_directions(E);
+  double dd[3] = {(double)d[0], (double)d[1], (double)d[2]};
+  double best = -1e300;
+  for (int64_t u = 0; u < n; ++u) {
+    double s = V[3 * u] * dd[0] + V[3 * u + 1] * dd[1] + V[3 * u + 2] * dd[2];
+    if (s > best) best = s;
+  }
+  double tol = 1e-12 * std::sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
+  for (int64_t u = 0; u < n; ++u) {
+    double s = V[3 * u] * dd[0] + V[3 * u + 1] * dd[1] + V[3 * u + 2] * dd[2];
+    if (s >= best - tol) return (int32_t)u;
+  }
+  return 0;
+}
+
+// Dual tree traversal, one level at a time: the frontier holds same-level
+// pairs; admissible -> M2L, else a leaf -> P2P, else all pairs of sons.
+void traverse(HostPlan& hp) {
+  const Tree& X = hp.tx;
+  const Tree& Y = *hp.ty;
+  std::vector<std::pair<int32_t, int32_t>> front = {{0, 0}};
+  OffsetMap omap(&hp.offsets);
+  for (int lev = 0; !front.empty(); ++lev) {
+    int64_t nf = (int64_t)front.size();
+    int64_t nchunk = std::min<int64_t>(64, std::max<int64_t>(1, nf / 4096));
+    struct Out {
+      std::vector<std::pair<int32_t, int32_t>> m2l, p2p, next;
+      std::vector<int32_t> dl;
+    };
+    std::vector<Out> out(nchunk);
+    parallel_chunks(nchunk, 1, [&](int64_t cb, int64_t ce, int) {
+      for (int64_t ch = cb; ch < ce; ++ch) {
+        Out& o = out[ch];
+        int64_t b = nf * ch / nchunk, e = nf * (ch + 1) / nchunk;
+        for (int64_t i = b; i < e; ++i) {
+          int32_t t = front[i].first, s = front[i].second;
+          int32_t d[3];
+          int64_t n2 = 0;
+          for (int k = 0; k < 3; ++k) {
+            d[k] = X.ijk[3 * t + k] - Y.ijk[3 * s + k];
+            int64_t a = d[k] < 0 ? -(int64_t)d[k] : (int64_t)d[k];
+            int64_t nk = a - 1 > 0 ? a - 1 : 0;
+            n2 += nk * nk;
+          }
+          if ((double)n2 >= hp.thr[lev]) {
+            o.m2l.push_back({t, s});
+            o.dl.insert(o.dl.end(), d, d + 3);
+          } else if (X.leaf[t] || Y.leaf[s]) {
+            o.p2p.push_back({t, s});
+          } else {
+            for (int a = 0; a < X.nchild[t]; ++a)
+              for (int c = 0; c < Y.nchild[s]; ++c) o.next.push_back({X.child0[t] + a, Y.child0[s] + c});
+          }
+        }
+      }
+    });
+    std::vector<std::pair<int32_t, int32_t>> next;
+    size_t nn = 0;
+    for (auto& o : out) nn += o.next.size();
+    next.reserve(nn);
+    for (auto& o : out) {
+      for (size_t i = 0; i < o.m2l.size(); ++i) {
+        HostPlan::M2L m;
+        m.t = o.m2l[i].first;
+        m.s = o.m2l[i].second;
+        m.off = omap.get(lev, &o.dl[3 * i]);
+        hp.m2l.push_back(m);
+      }
+      for (auto& pr : o.p2p) {
+        hp.p2p_t.push_back(pr.first);
+        hp.p2p_s.push_back(pr.second);
+      }
+      next.insert(next.end(), o.next.begin(), o.next.end());
+      o = Out();
+    }
+    front.swap(next);
+  }
+}
+
+// Marks of Alg. 2 on one tree, then the blank downward pass of Alg. 3
+// (a low-frequency son of a marked cell carries the non-directional mark).
+void mark_tree(HostPlan& hp, Tree& T, const std::vector<uint64_t>& own) {
+  int64_t nc = T.ncells();
+  std::vector<std::vector<int32_t>> marks(nc);
+  for (uint64_t m : own) marks[m >> 32].push_back((int32_t)(m & 0xffffffffu) - 1);
+  for (int l = 0; l < T.nlevels; ++l) {
+    for (int64_t c = T.lev_start[l]; c < T.lev_start[l + 1]; ++c) {
+      auto& mk = marks[c];
+      std::sort(mk.begin(), mk.end());
+      mk.erase(std::unique(mk.begin(), mk.end()), mk.end());
+      if (mk.empty() || T.leaf[c]) continue;
+      for (int a = 0; a < T.nchild[c]; ++a) {
+        auto& cm = marks[T.child0[c] + a];
+        if (hp.hf[l + 1]) {
+          const int64_t* fa = hp.father_flat.data() + hp.dir_off[dir_level(hp, l)];
+          for (int32_t u : mk) cm.push_back((int32_t)fa[u]);
+        } else {
+          cm.push_back(-1);
+        }
+      }
+    }
+  }
+  T.exp_begin.assign(nc + 1, 0);
+  for (int64_t c = 0; c < nc; ++c) T.exp_begin[c + 1] = T.exp_begin[c] + (int64_t)marks[c].size();
+  int64_t ne = T.exp_begin[nc];
+  T.exp_dir.resize(ne);
+  T.exp_cell.resize(ne);
+  T.exp_u.assign(3 * ne, 0.0);
+  for (int64_t c = 0; c < nc; ++c) {
+    for (size_t k = 0; k < marks[c].size(); ++k) {
+      int64_t e = T.exp_begin[c] + (int64_t)k;
+      int32_t u = marks[c][k];
+      T.exp_dir[e] = u;
+      T.exp_cell[e] = (int32_t)c;
+      if (u >= 0) {
+        const double* v = hp.dirs.data() + 3 * (hp.dir_off[dir_level(hp, T.level[c])] + u);
+        for (int d = 0; d < 3; ++d) T.exp_u[3 * e + d] = v[d];
+      }
+    }
+  }
+}
+
+void build_tables(HostPlan& hp) {
+  Tree& X = hp.tx;
+  Tree& Y = *hp.ty;
+  // P2M: every expansion of a source leaf
+  for (int64_t e = 0; e < Y.nexp(); ++e)
+    if (Y.leaf[Y.exp_cell[e]]) hp.p2m_exp.push_back((int32_t)e);
+  // M2M, fathers level by level
+  hp.m2m_par.assign(Y.nlevels, {});
+  hp.m2m_child.assign(Y.nlevels, {});
+  hp.m2m_oct.assign(Y.nlevels, {});
+  for (int l = 0; l + 1 < Y.nlevels; ++l) {
+    for (int64_t c = Y.lev_start[l]; c < Y.lev_start[l + 1]; ++c) {
+      if (Y.leaf[c]) continue;
+      for (int64_t e = Y.exp_begin[c]; e < Y.exp_begin[c + 1]; ++e) {
+        int32_t v = Y.exp_dir[e];
+        int32_t u = -1;
+        if (hp.hf[l + 1]) u = (int32_t)hp.father_flat[hp.dir_off[dir_level(hp, l)] + v];
+        hp.m2m_par[l].push_back((int32_t)e);
+        for (int k = 0; k < 8; ++k) {
+          if (k < Y.nchild[c]) {
+            int32_t cc = Y.child0[c] + k;
+            int64_t ce = Y.find_exp(cc, u);
+            if (ce < 0) throw std::runtime_error("internal: missing son expansion");
+            int oct = (Y.ijk[3 * cc] - 2 * Y.ijk[3 * c]) | ((Y.ijk[3 * cc + 1] - 2 * Y.ijk[3 * c + 1]) << 1) |
+                      ((Y.ijk[3 * cc + 2] - 2 * Y.ijk[3 * c + 2]) << 2);
+            hp.m2m_child[l].push_back((int32_t)ce);
+            hp.m2m_oct[l].push_back((int8_t)oct);
+          } else {
+            hp.m2m_child[l].push_back(-1);
+            hp.m2m_oct[l].push_back(0);
+          }
+        }
+      }
+    }
+  }
+  // M2L grouped by target expansion
+  int64_t nm = (int64_t)hp.m2l.size();
+  std::vector<int32_t> te(nm), se(nm);
+  parallel_chunks(nm, 1 << 14, [&](int64_t b, int64_t e, int) {
+    for (int64_t i = b; i < e; ++i) {
+      const auto& m = hp.m2l[i];
+      int32_t u = hp.offsets[m.off].dir;
+      int64_t a = X.find_exp(m.t, u), c = Y.find_exp(m.s, u);
+      if (a < 0 || c < 0) throw std::runtime_error("internal: missing M2L expansion");
+      te[i] = (int32_t)a;
+      se[i] = (int32_t)c;
+    }
+  });
+  std::vector<int32_t> row(Y.nexp(), -1);
+  for (int64_t i = 0; i < nm; ++i) row[se[i]] = 0;
+  for (int64_t e = 0; e < Y.nexp(); ++e)
+    if (row[e] == 0) {
+      row[e] = (int32_t)hp.m2f_exp.size();
+      hp.m2f_exp.push_back((int32_t)e);
+    }
+  std::vector<int64_t> order(nm);
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+    if (te[a] != te[b]) return te[a] < te[b];
+    return se[a] < se[b];
+  });
+  hp.m2l_src.resize(nm);
+  hp.m2l_off.resize(nm);
+  for (int64_t k = 0; k < nm; ++k) {
+    int64_t i = order[k];
+    if (k == 0 || te[i] != te[order[k - 1]]) {
+      hp.m2l_tgt.push_back(te[i]);
+      hp.m2l_begin.push_back((int32_t)k);
+    }
+    hp.m2l_src[k] = row[se[i]];
+    hp.m2l_off[k] = hp.m2l[i].off;
+  }
+  hp.m2l_begin.push_back((int32_t)nm);
+  // L2L, sons level by level
+  hp.l2l_ch.assign(X.nlevels, {});
+  hp.l2l_begin.assign(X.nlevels, {});
+  hp.l2l_par.assign(X.nlevels, {});
+  hp.l2l_oct.assign(X.nlevels, {});
+  for (int l = 0; l + 1 < X.nlevels; ++l) {
+    for (int64_t c = X.lev_start[l + 1]; c < X.lev_start[l + 2]; ++c) {
+      int32_t p = X.parent[c];
+      int oct = (X.ijk[3 * c] - 2 * X.ijk[3 * p]) | ((X.ijk[3 * c + 1] - 2 * X.ijk[3 * p + 1]) << 1) |
+                ((X.ijk[3 * c + 2] - 2 * X.ijk[3 * p + 2]) << 2);
+      for (int64_t e = X.exp_begin[c]; e < X.exp_begin[c + 1]; ++e) {
+        int32_t u = X.exp_dir[e];
+        size_t before = hp.l2l_par[l].size();
+        for (int64_t pe = X.exp_begin[p]; pe < X.exp_begin[p + 1]; ++pe) {
+          int32_t v = X.exp_dir[pe];
+          int32_t fv = -1;
+          if (hp.hf[l + 1]) fv = (int32_t)hp.father_flat[hp.dir_off[dir_level(hp, l)] + v];
+          if (fv != u) continue;
+          hp.l2l_par[l].push_back((int32_t)pe);
+          hp.l2l_oct[l].push_back((int8_t)oct);
+        }
+        if (hp.l2l_par[l].size() != before) {
+          hp.l2l_ch[l].push_back((int32_t)e);
+          hp.l2l_begin[l].push_back((int32_t)before);
+        }
+      }
+    }
+    hp.l2l_begin[l].push_back((int32_t)hp.l2l_par[l].size());
+  }
+  // L2P work items: target leaves holding expansions, in chunks of points
+  for (int64_t c = 0; c < X.ncells(); ++c) {
+    if (!X.leaf[c] || X.exp_begin[c + 1] == X.exp_begin[c]) continue;
+    for (int32_t f = 0; f < X.count[c]; f += kL2PChunk) {
+      hp.l2p_cell.push_back((int32_t)c);
+      hp.l2p_first.push_back(X.first[c] + f);
+      hp.l2p_count.push_back(std::min(kL2PChunk, X.count[c] - f));
+    }
+  }
+  // P2P: push pairs with a non-leaf target down to its leaves, then group by
+  // target leaf, split into blocks of points and balanced work items.
+  int64_t np = (int64_t)hp.p2p_t.size();
+  std::vector<std::pair<int32_t, int32_t>> lp;
+  lp.reserve(np);
+  std::vector<int32_t> stack;
+  for (int64_t i = 0; i < np; ++i) {
+    int32_t t = hp.p2p_t[i], s = hp.p2p_s[i];
+    if (X.leaf[t]) {
+      lp.push_back({t, s});
+      continue;
+    }
+    stack.assign(1, t);
+    while (!stack.empty()) {
+      int32_t c = stack.back();
+      stack.pop_back();
+      if (X.leaf[c]) {
+        lp.push_back({c, s});
+      } else {
+        for (int a = X.nchild[c] - 1; a >= 0; --a) stack.push_back(X.child0[c] + a);
+      }
+    }
+  }
+  std::sort(lp.begin(), lp.end(), [&](const auto& a, const auto& b) {
+    if (a.first != b.first) return a.first < b.first;
+    return Y.first[a.second] < Y.first[b.second];
+  });
+  hp.p2p_point_pairs = 0;
+  for (size_t i = 0; i < lp.size();) {
+    size_t j = i;
+    while (j < lp.size() && lp[j].first == lp[i].first) ++j;
+    int32_t t = lp[i].first;
+    // merge adjacent source ranges
+    std::vector<std::pair<int32_t, int32_t>> ranges;
+    for (size_t k = i; k < j; ++k) {
+      int32_t f = Y.first[lp[k].second], n = Y.count[lp[k].second];
+      if (!ranges.empty() && ranges.back().first + ranges.back().second == f)
+        ranges.back().second += n;
+      else
+        ranges.push_back({f, n});
+    }
+    int64_t total = 0;
+    for (auto& r : ranges) total += r.second;
+    for (int32_t bf = 0; bf < X.count[t]; bf += kP2PBlock) {
+      int32_t bc = std::min(kP2PBlock, X.count[t] - bf);
+      hp.blk_first.push_back(X.first[t] + bf);
+      hp.blk_count.push_back(bc);
+      hp.blk_wi_begin.push_back((int32_t)hp.wi_blk.size());
+      hp.p2p_point_pairs += total * bc;
+      int32_t blk = (int32_t)hp.blk_first.size() - 1;
+      int64_t acc = kP2PChunk;  // forces a new work item first
+      for (auto& r : ranges) {
+        for (int32_t off = 0; off < r.second;) {
+          if (acc >= kP2PChunk) {
+            hp.wi_blk.push_back(blk);
+            hp.wi_seg_begin.push_back((int32_t)hp.seg_first.size());
+            acc = 0;
+          }
+          int32_t take = (int32_t)std::min<int64_t>(r.second - off, kP2PChunk - acc);
+          hp.seg_first.push_back(r.first + off);
+          hp.seg_count.push_back(take);
+          acc += take;
+          off += take;
+        }
+      }
+    }
+    i = j;
+  }
+  hp.blk_wi_begin.push_back((int32_t)hp.wi_blk.size());
+  hp.wi_seg_begin.push_back((int32_t)hp.seg_first.size());
+}
+
+}  // namespace
+
+void build_host_plan(HostPlan& hp, const double* X, int64_t nx, const double* Y, int64_t ny,
+                     const BuildParams& prm) {
+  hp.prm = prm;
+  const double* Yp = prm.same_points ? X : Y;
+  if (prm.same_points) ny = nx;
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t i = 0; i < nx; ++i)
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = std::fmin(lo[d], X[3 * i + d]);
+      hi[d] = std::fmax(hi[d], X[3 * i + d]);
+    }
+  if (!prm.same_points)
+    for (int64_t i = 0; i < ny; ++i)
+      for (int d = 0; d < 3; ++d) {
+        lo[d] = std::fmin(lo[d], Yp[3 * i + d]);
+        hi[d] = std::fmax(hi[d], Yp[3 * i + d]);
+      }
+  double D = 0.0;
+  if (nx + (prm.same_points ? 0 : ny) > 0) {
+    for (int d = 0; d < 3; ++d) D = std::fmax(D, hi[d] - lo[d]);
+    for (int d = 0; d < 3; ++d) hp.origin[d] = 0.5 * (lo[d] + hi[d]) - 0.5 * D;
+  }
+  hp.D = D;
+  hp.tau = 1e-12 * D;
+  build_tree(hp.tx, X, nx, hp.origin, D, prm.ncrit);
+  if (prm.same_points) {
+    hp.ty = &hp.tx;
+  } else {
+    build_tree(hp.ty_own, Yp, ny, hp.origin, D, prm.ncrit);
+    hp.ty = &hp.ty_own;
+  }
+  hp.lstar = -1;
+  for (int l = 0; l <= kMaxLevel; ++l) {
+    double w = std::ldexp(D, -(l + 1));
+    hp.hf[l] = (prm.kappa * w > prm.hf_threshold) ? 1 : 0;
+    if (hp.hf[l]) hp.lstar = l;
+    double a = std::fmax(prm.kappa * w, 2.0) / (2.0 * prm.eta);
+    hp.thr[l] = a * a;
+  }
+  if (nx > 0 && ny > 0) traverse(hp);
+  // directions up to the finest level any M2L needs
+  int Emax = -1;
+  for (const Offset& o : hp.offsets)
+    if (hp.hf[o.level]) Emax = std::max(Emax, dir_level(hp, o.level));
+  hp.dir_off.assign(std::max(Emax + 1, 1), -1);
+  int64_t tot = 0;
+  for (int E = 0; E <= Emax; ++E) {
+    hp.dir_off[E] = tot;
+    tot += num_directions(E);
+  }
+  hp.dirs.resize(3 * tot);
+  hp.father_flat.resize(tot);
+  for (int E = 0; E <= Emax; ++E)
+    make_directions(E, hp.dirs.data() + 3 * hp.dir_off[E], hp.father_flat.data() + hp.dir_off[E]);
+  parallel_chunks((int64_t)hp.offsets.size(), 64, [&](int64_t b, int64_t e, int) {
+    for (int64_t i = b; i < e; ++i) {
+      Offset& o = hp.offsets[i];
+      if (hp.hf[o.level]) o.dir = best_direction(hp, dir_level(hp, o.level), o.d);
+    }
+  });
+  // marks
+  std::vector<uint64_t> mx, my;
+  mx.reserve(hp.m2l.size());
+  my.reserve(hp.m2l.size());
+  for (const auto& m : hp.m2l) {
+    uint64_t u = (uint64_t)(uint32_t)(hp.offsets[m.off].dir + 1);
+    mx.push_back(((uint64_t)(uint32_t)m.t << 32) | u);
+    my.push_back(((uint64_t)(uint32_t)m.s << 32) | u);
+  }
+  if (prm.same_points) {
+    mx.insert(mx.end(), my.begin(), my.end());
+    my.clear();
+  }
+  std::sort(mx.begin(), mx.end());
+  mx.erase(std::unique(mx.begin(), mx.end()), mx.end());
+  mark_tree(hp, hp.tx, mx);
+  if (!prm.same_points) {
+    std::sort(my.begin(), my.end());
+    my.erase(std::unique(my.begin(), my.end()), my.end());
+    mark_tree(hp, hp.ty_own, my);
+  }
+  build_tables(hp);
+}
+
+}  // namespace defmm

@@ -1,0 +1,149 @@
+"""GPU path (through the C ABI) against the FP64 oracle.
+
+Tolerances: the complex128 path computes the same sums as the oracle in a
+different order, so it agrees to rounding (relative l2 <= 1e-11).  The
+complex64 path is compared at 2e-5 relative l2 against the oracle: complex64
+expansions carry ~6e-8 relative rounding per operation, amplified by the
+equispaced interpolation (Lebesgue constants ~10 at L <= 6) and by the
+number of M2L terms accumulated per target (~300), giving ~1e-6..1e-5.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2202_04894_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _defmm():
+    from paper_2202_04894_amd import defmm
+    return defmm
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def run_gpu(X, q, kappa, prm, Y=None, qY=None, repeat=1):
+    defmm = _defmm()
+    plan = defmm.Plan(X, Y, kappa, prm)
+    ws = defmm.Workspace(plan)
+    qq = q if Y is None else qY
+    qt = torch.as_tensor(qq, device="cuda").to(plan.cdtype)
+    outs = []
+    for _ in range(repeat):
+        p = ws.matvec(qt)
+        torch.cuda.synchronize()
+        outs.append(p.cpu().numpy().astype(np.complex128))
+    return outs if repeat > 1 else outs[0], plan, ws
+
+
+def oracle_params(prm):
+    return oracle.Params(L=prm.order_L, ncrit=prm.ncrit, eta=prm.eta, hf_threshold=prm.hf_threshold,
+                         dir_refine=prm.dir_refine)
+
+
+def test_root_leaf_equals_direct_sum():
+    defmm = _defmm()
+    X = W.sphere(50, 5)
+    q = W.charges(50, 6)
+    for prec, tol in ((defmm.C128, 1e-13), (defmm.C64, 2e-6)):
+        prm = defmm.Params(order_L=4, ncrit=64, precision=prec)
+        p, plan, _ = run_gpu(X, q, 17.0, prm)
+        D, _ = plan.geometry()
+        ref = oracle.direct_sum(X, X, q, 17.0, 1e-12 * D)
+        assert plan.stats()["m2l_pairs"] == 0
+        assert rel(p, ref) < tol, (prec, rel(p, ref))
+
+
+FMM_CASES = [
+    # geometry, n, kappa, params
+    ("sphere", 3000, 24.0, dict(order_L=5, ncrit=24, eta=0.5, hf_threshold=2.0, dir_refine=1)),
+    ("sphere", 4000, 0.0, dict(order_L=4, ncrit=32)),
+    ("ellipsoid", 5000, 48.0, dict(order_L=4, ncrit=20, hf_threshold=1.0)),
+    ("cube_surface", 4000, 30.0, dict(order_L=3, ncrit=40, eta=0.7, dir_refine=2)),
+    ("cube_volume", 3000, 12.0, dict(order_L=6, ncrit=50)),
+]
+
+
+@pytest.mark.parametrize("geom,n,kappa,kw", FMM_CASES)
+def test_c128_matches_oracle(geom, n, kappa, kw):
+    defmm = _defmm()
+    X = W.GENERATORS[geom](n, 101)
+    q = W.charges(n, 102)
+    prm = defmm.Params(precision=defmm.C128, **kw)
+    p, plan, ws = run_gpu(X, q, kappa, prm)
+    F = oracle.FMM(X, None, kappa, oracle_params(prm))
+    ref = F.apply(q)
+    assert plan.stats()["m2l_pairs"] > 0
+    assert rel(p, ref) < 1e-11, rel(p, ref)
+    # per-pass: multipole and local node values of every expansion
+    ex_o = F.expansions(0)
+    for kind, key in ((0, "M"), (1, "L")):
+        ex = ws.expansions(0, kind)
+        np.testing.assert_array_equal(ex["cell"], ex_o["cell"])
+        np.testing.assert_array_equal(ex["dir"], ex_o["dir"])
+        scale = np.abs(ex_o[key]).max()
+        assert np.abs(ex["values"] - ex_o[key]).max() <= 1e-11 * scale, key
+
+
+@pytest.mark.parametrize("geom,n,kappa,kw", FMM_CASES[:3])
+def test_c64_matches_oracle(geom, n, kappa, kw):
+    defmm = _defmm()
+    X = W.GENERATORS[geom](n, 101)
+    q = W.charges(n, 102)
+    prm = defmm.Params(precision=defmm.C64, **kw)
+    p, _, _ = run_gpu(X, q, kappa, prm)
+    ref = oracle.FMM(X, None, kappa, oracle_params(prm)).apply(q)
+    assert rel(p, ref) < 2e-5, rel(p, ref)
+
+
+def test_distinct_target_and_source_sets():
+    defmm = _defmm()
+    X = W.sphere(2500, 3)
+    Y = W.cube_volume(1800, 4) * 0.6
+    qY = W.charges(1800, 5)
+    kw = dict(order_L=4, ncrit=12, hf_threshold=1.0)
+    for prec, tol in ((defmm.C128, 1e-11), (defmm.C64, 2e-5)):
+        p, _, _ = run_gpu(X, None, 30.0, defmm.Params(precision=prec, **kw), Y=Y, qY=qY)
+        ref = oracle.FMM(X, Y, 30.0, oracle.Params(L=4, ncrit=12, hf_threshold=1.0)).apply(qY)
+        assert rel(p, ref) < tol
+
+
+def test_sphere8k_against_oracle_and_direct_sum():
+    """8,192 points on the unit sphere, kappa*D = 32, L = 4, leaves <= 32, complex128:
+    GPU vs the oracle FMM on every target, and both vs the direct sum."""
+    defmm = _defmm()
+    wl = W.WORKLOADS["sphere8k"]
+    X = wl.points()
+    q = wl.charges(0)
+    prm = defmm.Params(order_L=wl.L, ncrit=wl.ncrit, precision=defmm.C128)
+    p, plan, _ = run_gpu(X, q, wl.kappa, prm)
+    ref = oracle.FMM(X, None, wl.kappa, oracle_params(prm)).apply(q)
+    assert rel(p, ref) < 1e-11
+    D, _ = plan.geometry()
+    direct = oracle.direct_sum(X, X, q, wl.kappa, 1e-12 * D)
+    e = rel(p, direct)
+    assert abs(e - rel(ref, direct)) < 1e-9
+    assert e < 5e-2  # paper-literal knobs at L = 4 (method error, not a parity bound)
+
+
+def test_repeatable_bitwise():
+    defmm = _defmm()
+    X = W.ellipsoid(6000, 9)
+    q = W.charges(6000, 10)
+    outs, _, _ = run_gpu(X, q, 40.0, defmm.Params(order_L=5, ncrit=32, precision=defmm.C64), repeat=3)
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+def test_degenerate_inputs():
+    defmm = _defmm()
+    # coincident points: every pair falls under tau
+    Xc = np.tile([[0.3, -0.2, 0.1]], (300, 1))
+    p, _, _ = run_gpu(Xc, W.charges(300, 1), 5.0, defmm.Params(ncrit=16, precision=defmm.C128))
+    assert np.all(p == 0)
+    # a single point
+    p, _, _ = run_gpu(np.array([[0.1, 0.2, 0.3]]), np.array([1 + 1j]), 5.0, defmm.Params(precision=defmm.C128))
+    assert np.all(p == 0)
