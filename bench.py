@@ -1,0 +1,263 @@
+#!/usr/bin/env python3
+"""Benchmark: Mpoints/s per defmm matvec on one MI355X.
+
+Workload (default): 1,048,576 points uniform on the unit sphere (D = 2),
+kappa*D = 256, L = 5, leaves <= 64 points, complex N(0,1) charges; the
+complex64 path is timed (value), the complex128 path is timed beside it.
+A step is one matvec (P2M .. P2P, L2P, scatter) with fresh charges already
+resident in HBM.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpoints/s per FMM matvec at rel.err<=1e-4 (FP32 vs FP64 path); p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+HBM_PASSES = {"setup", "p2m", "m2m", "m2f", "m2l", "f2l", "l2l", "p2p_reduce", "l2p", "scatter"}
+KERNEL_OF_PASS = {"m2l": "k_m2l_slice", "f2l": "k_f2l", "p2p": "k_p2p", "m2f": "k_m2f", "m2m": "k_m2m",
+                  "l2l": "k_l2l", "p2m": "k_p2m", "l2p": "k_l2p"}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="sphere1m")
+    ap.add_argument("--eta", type=float, default=None)
+    ap.add_argument("--hf", type=float, default=None)
+    ap.add_argument("--e0", type=int, default=None)
+    ap.add_argument("--c128-steps", type=int, default=5)
+    ap.add_argument("--check-targets", type=int, default=2048)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=0, help="points in the oracle's sample (0: auto)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after timing, run one plain device copy of this size (HBM counter calibration)")
+    ap.add_argument("--c64-only", action="store_true", help="skip the complex128 path and the checks")
+    return ap.parse_args()
+
+
+# Knobs per workload: (eta, hf_threshold, dir_refine).
+KNOBS = {"sphere8k": (1.0, 2.0, 0), "sphere1m": (1.0, 2.0, 0), "ellipsoid2m": (1.0, 2.0, 0),
+         "cube8m": (1.0, 2.0, 0)}
+
+
+def direct_sum_sampled(X, q, kappa, tau, targets):
+    """FP64 direct sum on sampled targets (torch on the device, chunked over sources),
+    used only to report the method's error."""
+    import torch
+    Xt = torch.as_tensor(X, dtype=torch.float64, device="cuda")
+    qt = torch.as_tensor(q, dtype=torch.complex128, device="cuda")
+    xs = Xt[torch.as_tensor(targets, device="cuda")]
+    out = torch.zeros(len(targets), dtype=torch.complex128, device="cuda")
+    chunk = 1 << 12
+    for j in range(0, Xt.shape[0], chunk):
+        y = Xt[j:j + chunk]
+        r = torch.sqrt(((xs[:, None, :] - y[None, :, :]) ** 2).sum(-1))
+        mask = r > tau
+        rr = torch.where(mask, r, torch.ones_like(r))
+        g = torch.where(mask, torch.exp(1j * kappa * rr) / (4 * np.pi * rr), torch.zeros_like(rr, dtype=torch.complex128))
+        out += g @ qt[j:j + chunk]
+    return out.cpu().numpy()
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip",):
+        with open(os.path.join(ROOT, "paper_2202_04894_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel, workload):
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def time_matvecs(ws, charges, steps, warmup, timing):
+    import torch
+    p = None
+    for k in range(warmup):
+        p = ws.matvec(charges[k % len(charges)], p)
+    torch.cuda.synchronize()
+    ws.set_timing(timing)
+    if timing:
+        ws.pass_times()  # reset
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        starts[k].record()
+        p = ws.matvec(charges[(warmup + k) % len(charges)], p)
+        ends[k].record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    lat = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+    passes = ws.pass_times() if timing else None
+    ws.set_timing(False)
+    return (t1 - t0) * 1e3 / steps, lat, passes
+
+
+def cpu_baseline(wl, X, kappa, knobs, perm, n_sample):
+    """The FP64 oracle on a bounded sample: the first n_sample points in Morton order
+    (a contiguous patch of the same surface at the same density), same kappa/L/ncrit."""
+    import oracle
+    idx = np.sort(perm[:n_sample])
+    Xs = X[idx]
+    q = wl.charges(0)[idx]
+    eta, hf, e0 = knobs
+    F = oracle.FMM(Xs, None, kappa, oracle.Params(L=wl.L, ncrit=wl.ncrit, eta=eta, hf_threshold=hf,
+                                                  dir_refine=e0))
+    F.apply(q)
+    secs = F.last_seconds
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(n_sample / secs / 1e6, 6), "unit": "Mpoints/s", "cores": cores, "kind": "oracle",
+            "sample": f"first {n_sample} of {wl.n} points in Morton order (a patch of the {wl.geometry} at "
+                      f"full density), kappa*D={wl.kappa_d}, L={wl.L}, ncrit={wl.ncrit}; one FP64 matvec "
+                      f"(setup excluded) took {secs:.2f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is "
+              f"described in DESIGN.md and not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2202_04894_amd import defmm
+    from paper_2202_04894_amd import workloads as W
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    wl = W.WORKLOADS[args.workload]
+    eta, hf, e0 = KNOBS[args.workload]
+    if args.eta is not None:
+        eta = args.eta
+    if args.hf is not None:
+        hf = args.hf
+    if args.e0 is not None:
+        e0 = args.e0
+    X = wl.points()
+    nsteps = max(args.steps, 1)
+    nq = min(nsteps + args.warmup, 64)
+
+    def make(prec):
+        t0 = time.perf_counter()
+        plan = defmm.Plan(X, None, wl.kappa, defmm.Params(order_L=wl.L, ncrit=wl.ncrit, eta=eta,
+                                                            hf_threshold=hf, dir_refine=e0, precision=prec))
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        return plan, defmm.Workspace(plan), setup
+
+    plan64, ws64, setup64 = make(defmm.C64)
+    charges64 = [torch.as_tensor(wl.charges(k, np.complex64), device="cuda") for k in range(nq)]
+    ms64, lat64, passes = time_matvecs(ws64, charges64, nsteps, args.warmup, timing=True)
+    p64 = ws64.matvec(charges64[0]).cpu().numpy().astype(np.complex128)
+    del charges64
+
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    if args.c64_only:
+        print(json.dumps({"value": round(wl.n / (ms64 / 1e3) / 1e6, 3), "ms_per_step": round(ms64, 4),
+                          "passes_ms_per_step": {defmm.pass_name(i): round(float(v) / nsteps, 4)
+                                                 for i, v in enumerate(passes[0])}}), flush=True)
+        return
+
+    plan128, ws128, setup128 = make(defmm.C128)
+    charges128 = [torch.as_tensor(wl.charges(k), device="cuda") for k in range(min(nq, 8))]
+    ms128, lat128, _ = time_matvecs(ws128, charges128, max(args.c128_steps, 1), 2, timing=False)
+    p128 = ws128.matvec(charges128[0]).cpu().numpy()
+    del charges128
+    rel_prec = float(np.linalg.norm(p64 - p128) / np.linalg.norm(p128))
+
+    D, _ = plan64.geometry()
+    tg = W.sample_targets(wl.n, args.check_targets, 3000 + wl.seed)
+    pd = direct_sum_sampled(X, wl.charges(0), wl.kappa, 1e-12 * D, tg)
+    rel_direct = float(np.linalg.norm(p128[tg] - pd) / np.linalg.norm(pd))
+    rel_direct64 = float(np.linalg.norm(p64[tg] - pd) / np.linalg.norm(pd))
+
+    # roofline of the dominant kernel, from per-pass HIP events over the timed region
+    ms_pass, calls = passes
+    names = [defmm.pass_name(i) for i in range(defmm.NUM_PASSES)]
+    bytes_, flops = plan64.pass_work()
+    per_step = ms_pass / nsteps
+    dom = int(np.argmax(per_step))
+    dname = names[dom]
+    t_launch = per_step[dom] / 1e3  # s per matvec for this pass
+    kern = KERNEL_OF_PASS.get(dname, dname)
+    if dname in HBM_PASSES:
+        ach = bytes_[dom] / t_launch / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4)}
+    else:
+        ach = flops[dom] / t_launch / 1e12
+        roof = {"bound": "alu", "achieved": round(ach, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(ach / FP32_PEAK_TFLOPS, 4)}
+    roof["kernel"] = kern
+    roof["avg_launch_ms"] = round(t_launch * 1e3, 4)
+    roof["traffic"] = load_traffic(kern, wl.name)
+
+    st = plan64.stats()
+    out = {
+        "metric": METRIC,
+        "value": round(wl.n / (ms64 / 1e3) / 1e6, 3),
+        "unit": "Mpoints/s",
+        "n_gpus": 1,
+        "steps": nsteps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms64, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: {wl.n} points uniform on the unit {wl.geometry}, "
+                               f"kappa*D={wl.kappa_d}, L={wl.L}, leaf<={wl.ncrit}, complex N(0,1) charges",
+                   "eta": eta, "hf_threshold": hf, "dir_refine": e0},
+        "p50_ms": round(float(np.percentile(lat64, 50)), 4),
+        "p99_ms": round(float(np.percentile(lat64, 99)), 4),
+        "rel_l2_c64_vs_c128": rel_prec,
+        "rel_l2_vs_direct_c128": rel_direct,
+        "rel_l2_vs_direct_c64": rel_direct64,
+        "direct_check": f"FP64 direct sum on {len(tg)} sampled targets",
+        "c128": {"value": round(wl.n / (ms128 / 1e3) / 1e6, 3), "unit": "Mpoints/s",
+                 "ms_per_step": round(ms128, 4), "p50_ms": round(float(np.percentile(lat128, 50)), 4),
+                 "p99_ms": round(float(np.percentile(lat128, 99)), 4)},
+        "setup_s": {"c64": round(setup64, 3), "c128": round(setup128, 3)},
+        "passes_ms_per_step": {n: round(float(v), 4) for n, v in zip(names, per_step)},
+        "stats": st,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        n_s = args.cpu_sample or min(wl.n, 131072)
+        out["cpu_baseline"] = cpu_baseline(wl, X, wl.kappa, (eta, hf, e0), plan64.tree(0)["perm"], n_s)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

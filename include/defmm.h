@@ -147,7 +147,7 @@ defmm_status defmm_workspace_export_expansions(defmm_workspace* ws, int32_t whic
 /* Per-pass device time.  When enabled, matvec records HIP events around each pass
    on its stream; pass_ms[i] accumulates milliseconds over the matvecs since the
    last reset, calls[i] counts launches.  Pass names: defmm_pass_name(i). */
-#define DEFMM_NUM_PASSES 10
+#define DEFMM_NUM_PASSES 11
 defmm_status defmm_workspace_set_timing(defmm_workspace* ws, int32_t enable);
 defmm_status defmm_workspace_pass_times(defmm_workspace* ws, double* pass_ms, int64_t* calls);
 const char* defmm_pass_name(int32_t i);

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <stdexcept>
@@ -85,7 +86,7 @@ DevPlan::~DevPlan() {
   for (void* p : allocs) hipFree(p);
 }
 Workspace::~Workspace() {
-  for (void* p : {qs, ps, M, Lx, Mt, part})
+  for (void* p : {qs, ps, M, Lx, Mt, Lt, part})
     if (p) hipFree(p);
   for (hipEvent_t e : ev_pool) hipEventDestroy(e);
 }
@@ -243,9 +244,17 @@ defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int
     P.n_m2f = (int64_t)H.m2f_exp.size();
     P.m2l_tgt = upload(P, H.m2l_tgt);
     P.m2l_begin = upload(P, H.m2l_begin);
-    P.m2l_src = upload(P, H.m2l_src);
-    P.m2l_off = upload(P, H.m2l_off);
+    {
+      std::vector<int32_t> pr(2 * H.m2l_src.size());
+      for (size_t k = 0; k < H.m2l_src.size(); ++k) {
+        pr[2 * k] = H.m2l_src[k];
+        pr[2 * k + 1] = H.m2l_off[k];
+      }
+      P.m2l_pair = upload(P, pr);
+    }
     P.n_m2l_tgt = (int64_t)H.m2l_tgt.size();
+    P.m2l_level_tgt.assign(H.m2l_level_tgt.begin(), H.m2l_level_tgt.end());
+
     P.n_m2l = (int64_t)H.m2l_src.size();
     P.l2l.resize(H.l2l_ch.size());
     for (size_t l = 0; l < H.l2l_ch.size(); ++l) {
@@ -303,7 +312,7 @@ static size_t workspace_bytes(const DevPlan& P) {
   size_t cs = csize(P);
   int L3 = P.L * P.L * P.L, P3 = (2 * P.L - 1) * (2 * P.L - 1) * (2 * P.L - 1);
   return cs * ((size_t)P.ny + (size_t)P.nx + (size_t)P.ty.nexp * L3 + (size_t)P.tx.nexp * L3 +
-               (size_t)P.n_m2f * P3 + (size_t)P.nwi * 64);
+               (size_t)P.n_m2f * P3 + (size_t)P.nwi * 64 + (P.m2l_variant == 1 ? (size_t)P.n_m2l_tgt * P3 : 0));
 }
 
 defmm_status defmm_plan_footprint(const defmm_plan* plan, size_t* resident, size_t* ws) {
@@ -357,6 +366,7 @@ defmm_status defmm_workspace_create(defmm_plan* plan, defmm_workspace** out) {
               {&W.M, cs * (size_t)P.ty.nexp * L3},
               {&W.Lx, cs * (size_t)P.tx.nexp * L3},
               {&W.Mt, cs * (size_t)P.n_m2f * P3},
+              {&W.Lt, P.m2l_variant == 1 ? cs * (size_t)P.n_m2l_tgt * P3 : 0},
               {&W.part, cs * (size_t)P.nwi * 64}};
   for (auto& b : bufs) {
     if (b.n == 0) continue;
@@ -496,8 +506,8 @@ defmm_status defmm_workspace_pass_times(defmm_workspace* ws, double* pass_ms, in
 }
 
 const char* defmm_pass_name(int32_t i) {
-  static const char* names[kNumPasses] = {"setup", "p2m", "m2m", "m2f", "m2l_f2l", "l2l", "p2p", "p2p_reduce",
-                                          "l2p", "scatter"};
+  static const char* names[kNumPasses] = {"setup", "p2m", "m2m", "m2f", "m2l", "l2l", "p2p", "p2p_reduce",
+                                          "l2p", "scatter", "f2l"};
   if (i < 0 || i >= kNumPasses) return "";
   return names[i];
 }
@@ -509,7 +519,7 @@ defmm_status defmm_plan_pass_work(const defmm_plan* plan, double* bytes, double*
   double cs = (double)csize(P);
   double L = P.L, Pp = 2 * P.L - 1, L3 = L * L * L, P3 = Pp * Pp * Pp;
   double b[kNumPasses] = {0}, f[kNumPasses] = {0};
-  b[kPassSetup] = (double)P.ny * (2 * cs + 4) + cs * ((double)P.tx.nexp * L3 + (double)P.nx);
+  b[kPassSetup] = (double)P.ny * (2 * cs + 4) + cs * ((double)H.tx.nexp() * L3 + (double)P.nx);
   double npts = 0;
   for (int32_t e : H.p2m_exp) npts += H.ty->count[H.ty->exp_cell[e]];
   b[kPassP2M] = npts * (24 + cs) + (double)P.n_p2m * cs * L3;
@@ -520,10 +530,19 @@ defmm_status defmm_plan_pass_work(const defmm_plan* plan, double* bytes, double*
     for (int32_t c : v) nm2m_child += c >= 0;
   b[kPassM2M] = (nm2m + nm2m_child) * cs * L3;
   f[kPassM2M] = nm2m_child * 8 * (3 * L3 * L + 2 * L3);
-  b[kPassM2F] = (double)P.n_m2f * cs * (L3 + P3);
-  f[kPassM2F] = (double)P.n_m2f * 8 * (Pp * L * L * L + Pp * Pp * L * L + P3 * L);
-  b[kPassM2L] = (double)P.n_m2l * 2 * cs * P3 + (double)P.n_m2l_tgt * cs * L3;
-  f[kPassM2L] = (double)P.n_m2l * 8 * P3 + (double)P.n_m2l_tgt * 8 * (Pp * Pp * L * Pp + Pp * L * L * Pp + L3 * Pp);
+  double n_m2f = (double)H.m2f_exp.size(), n_m2l = (double)H.m2l_src.size(), n_tgt = (double)H.m2l_tgt.size();
+  b[kPassM2F] = n_m2f * cs * (L3 + P3);
+  f[kPassM2F] = n_m2f * 8 * (Pp * L * L * L + Pp * Pp * L * L + P3 * L);
+  double f2l_flops = n_tgt * 8 * (Pp * Pp * L * Pp + Pp * L * L * Pp + L3 * Pp);
+  if (P.m2l_variant == 0) {
+    b[kPassM2L] = n_m2l * 2 * cs * P3 + n_tgt * cs * L3;
+    f[kPassM2L] = n_m2l * 8 * P3 + f2l_flops;
+  } else {
+    b[kPassM2L] = n_m2l * 2 * cs * P3 + n_tgt * cs * P3;
+    f[kPassM2L] = n_m2l * 8 * P3;
+    b[kPassF2L] = n_tgt * cs * (P3 + L3);
+    f[kPassF2L] = f2l_flops;
+  }
   double nl2l = 0;
   for (const auto& v : H.l2l_par) nl2l += (double)v.size();
   double nl2l_ch = 0;
@@ -531,8 +550,9 @@ defmm_status defmm_plan_pass_work(const defmm_plan* plan, double* bytes, double*
   b[kPassL2L] = (nl2l + 2 * nl2l_ch) * cs * L3;
   f[kPassL2L] = nl2l * 8 * (3 * L3 * L + 3 * L3);
   f[kPassP2P] = 23.0 * (double)H.p2p_point_pairs;
-  b[kPassP2P] = (double)P.nwi * 64 * cs;
-  b[kPassP2PRed] = (double)P.nwi * 64 * cs + (double)P.nx * cs;
+  double nwi = (double)H.wi_blk.size();
+  b[kPassP2P] = nwi * 64 * cs;
+  b[kPassP2PRed] = nwi * 64 * cs + (double)P.nx * cs;
   double nl2p_pts = 0, nl2p_exp = 0;
   for (size_t i = 0; i < H.l2p_cell.size(); ++i) {
     int c = H.l2p_cell[i];

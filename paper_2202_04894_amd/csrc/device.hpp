@@ -18,13 +18,14 @@ enum Pass {
   kPassP2M = 1,
   kPassM2M = 2,
   kPassM2F = 3,
-  kPassM2L = 4,     // Hadamard accumulate + F2L (fused)
+  kPassM2L = 4,     // Hadamard accumulate (+ F2L when fused)
   kPassL2L = 5,
   kPassP2P = 6,
   kPassP2PRed = 7,
   kPassL2P = 8,
   kPassScatter = 9,
-  kNumPasses = 10
+  kPassF2L = 10,    // separate F2L when the M2L runs frequency-sliced
+  kNumPasses = 11
 };
 
 struct DevTree {
@@ -52,6 +53,7 @@ struct LevelTable {  // per-level operator table on the device
 struct DevPlan {
   HostPlan host;   // kept for introspection and stats
   int L = 5, precision = 1;
+  int m2l_variant = 1;  // 0: Hadamard + F2L fused per target, 1: frequency-sliced + separate F2L
   double kappa = 0.0, D = 0.0, origin[3] = {0, 0, 0}, tau = 0.0;
   DevTree tx, ty;
   bool same = false;
@@ -63,8 +65,10 @@ struct DevPlan {
   std::vector<LevelTable> m2m;  // a = parent exps, b = 8 child exps per parent, oct = 8 per parent
   int32_t* m2f_exp = nullptr;
   int64_t n_m2f = 0;
-  int32_t *m2l_tgt = nullptr, *m2l_begin = nullptr, *m2l_src = nullptr, *m2l_off = nullptr;
+  int32_t *m2l_tgt = nullptr, *m2l_begin = nullptr;
+  int32_t* m2l_pair = nullptr;  // per entry: (Fourier-domain multipole row, spectrum id)
   int64_t n_m2l_tgt = 0, n_m2l = 0;
+  std::vector<int64_t> m2l_level_tgt;  // target range per level (host copy)
   std::vector<LevelTable> l2l;  // a = child exps, b = CSR begin (n+1), c = parent exps, oct
   int32_t *l2p_cell = nullptr, *l2p_first = nullptr, *l2p_count = nullptr;
   int64_t n_l2p = 0;
@@ -87,6 +91,7 @@ struct Workspace {
   void* M = nullptr;     // multipoles, ty.nexp x L^3
   void* Lx = nullptr;    // locals, tx.nexp x L^3
   void* Mt = nullptr;    // Fourier-domain multipoles, n_m2f x P^3
+  void* Lt = nullptr;    // Fourier-domain locals, n_m2l_tgt x P^3 (sliced M2L only)
   void* part = nullptr;  // P2P partial sums, nwi x 64
   size_t bytes = 0;
   bool timing = false;

@@ -365,9 +365,9 @@ __global__ __launch_bounds__(256) void k_m2f(int64_t n, const int32_t* __restric
 // frequencies; operand loads are contiguous across the workgroup.
 template <typename R, int L>
 __global__ __launch_bounds__(256) void k_m2l(int64_t ntgt, const int32_t* __restrict__ tgt,
-                                             const int32_t* __restrict__ begin, const int32_t* __restrict__ src,
-                                             const int32_t* __restrict__ off, const C2<R>* __restrict__ Mt,
-                                             const C2<R>* __restrict__ S, C2<R>* __restrict__ Lx) {
+                                             const int32_t* __restrict__ begin, const int2* __restrict__ pairs,
+                                             const C2<R>* __restrict__ Mt, const C2<R>* __restrict__ S,
+                                             C2<R>* __restrict__ Lx) {
   constexpr int P = 2 * L - 1, P3 = P * P * P, L3 = L * L * L;
   constexpr int NT = 256, NF = (P3 + NT - 1) / NT;
   __shared__ C2<R> A[P3];
@@ -382,8 +382,9 @@ __global__ __launch_bounds__(256) void k_m2l(int64_t ntgt, const int32_t* __rest
   for (int f = 0; f < NF; ++f) acc[f] = {(R)0, (R)0};
   int kb = begin[i], ke = begin[i + 1];
   for (int k = kb; k < ke; ++k) {
-    const C2<R>* ms = Mt + (int64_t)src[k] * P3;
-    const C2<R>* ds = S + (int64_t)off[k] * P3;
+    const int2 pr = pairs[k];
+    const C2<R>* ms = Mt + (int64_t)pr.x * P3;
+    const C2<R>* ds = S + (int64_t)pr.y * P3;
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       int xi = tid + f * NT;
@@ -414,6 +415,113 @@ __global__ __launch_bounds__(256) void k_m2l(int64_t ntgt, const int32_t* __rest
   }
   __syncthreads();
   for (int j = tid; j < L3; j += NT) {  // x: (kx, ky, kz)
+    int kx = j % L, kyz = j / L;
+    C2<R> s = {(R)0, (R)0};
+#pragma unroll
+    for (int m = 0; m < P; ++m) cfma(s, B2[m + P * kyz], W[(m * kx) % P]);
+    Lx[(int64_t)tgt[i] * L3 + j] = s;
+  }
+}
+
+// M2L Hadamard accumulate, frequency-sliced: the P^3 frequencies are split
+// into 8 slices and workgroup b handles slice b % 8 of target b / 8.  The
+// hardware deals workgroups to the 8 XCDs round-robin, so XCD j only ever
+// touches slice j of every spectrum and every Fourier-domain multipole: each
+// XCD's L2 holds 1/8 of the operands.  One wave per workgroup; the pair loop
+// is unrolled by 4 so each lane keeps 8*NF loads in flight.
+template <typename R, int L, int NSL>
+__global__ __launch_bounds__(64) void k_m2l_slice(int64_t ntgt, const int32_t* __restrict__ begin,
+                                                  const int2* __restrict__ pairs, const C2<R>* __restrict__ Mt,
+                                                  const C2<R>* __restrict__ S, C2<R>* __restrict__ Lt) {
+  // NSL slices (a multiple of 8): XCD j gets slices j, j+8, ...; the block
+  // order walks all targets of one slice before the next on each XCD.
+  constexpr int P = 2 * L - 1, P3 = P * P * P;
+  constexpr int SL = (P3 + NSL - 1) / NSL, NF = (SL + 63) / 64, U = 8;
+  const int64_t b = blockIdx.x;
+  const int xcd = (int)(b % 8);
+  const int64_t j = b / 8;
+  const int slice = xcd + 8 * (int)(j / ntgt);
+  const int64_t i = j % ntgt;
+  const int lane = threadIdx.x;
+  int fl[NF];
+  bool ok[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    int loc = lane + 64 * f;
+    fl[f] = slice * SL + loc;
+    ok[f] = loc < SL && fl[f] < P3;
+    if (!ok[f]) fl[f] = 0;
+  }
+  C2<R> acc[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) acc[f] = {(R)0, (R)0};
+  int k = begin[i];
+  const int ke = begin[i + 1];
+  for (; k + U <= ke; k += U) {
+    int2 pr[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) pr[u] = pairs[k + u];
+    C2<R> mv[U][NF], dv[U][NF];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const C2<R>* ms = Mt + (int64_t)pr[u].x * P3;
+      const C2<R>* ds = S + (int64_t)pr[u].y * P3;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        mv[u][f] = ms[fl[f]];
+        dv[u][f] = ds[fl[f]];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int f = 0; f < NF; ++f) cfma(acc[f], dv[u][f], mv[u][f]);
+  }
+  for (; k < ke; ++k) {
+    const int2 pr = pairs[k];
+    const C2<R>* ms = Mt + (int64_t)pr.x * P3;
+    const C2<R>* ds = S + (int64_t)pr.y * P3;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) cfma(acc[f], ds[fl[f]], ms[fl[f]]);
+  }
+#pragma unroll
+  for (int f = 0; f < NF; ++f)
+    if (ok[f]) Lt[i * P3 + fl[f]] = acc[f];
+}
+
+// F2L: pruned inverse DFT of each target's accumulated Fourier-domain local
+// expansion, restricted to [0,L)^3 (the 1/P^3 is folded into the spectra).
+template <typename R, int L>
+__global__ __launch_bounds__(256) void k_f2l(int64_t ntgt, const int32_t* __restrict__ tgt,
+                                             const C2<R>* __restrict__ Lt, C2<R>* __restrict__ Lx) {
+  constexpr int P = 2 * L - 1, P3 = P * P * P, L3 = L * L * L, NT = 256;
+  __shared__ C2<R> A[P3];
+  __shared__ C2<R> B1[P * P * L];
+  __shared__ C2<R> B2[P * L * L];
+  __shared__ C2<R> W[P];
+  int64_t i = xcd_item(ntgt);
+  if (i >= ntgt) return;
+  int tid = threadIdx.x;
+  for (int j = tid; j < P3; j += NT) A[j] = Lt[i * P3 + j];
+  if (tid < P) W[tid] = expi<R>(2.0 * M_PI * (double)tid / (double)P);
+  __syncthreads();
+  for (int j = tid; j < P * P * L; j += NT) {
+    int xy = j % (P * P), kz = j / (P * P);
+    C2<R> s = {(R)0, (R)0};
+#pragma unroll
+    for (int m = 0; m < P; ++m) cfma(s, A[xy + P * P * m], W[(m * kz) % P]);
+    B1[j] = s;
+  }
+  __syncthreads();
+  for (int j = tid; j < P * L * L; j += NT) {
+    int xi = j % P, ky = (j / P) % L, kz = j / (P * L);
+    C2<R> s = {(R)0, (R)0};
+#pragma unroll
+    for (int m = 0; m < P; ++m) cfma(s, B1[xi + P * m + P * P * kz], W[(m * ky) % P]);
+    B2[j] = s;
+  }
+  __syncthreads();
+  for (int j = tid; j < L3; j += NT) {
     int kx = j % L, kyz = j / L;
     C2<R> s = {(R)0, (R)0};
 #pragma unroll
@@ -597,61 +705,121 @@ __device__ __forceinline__ void p2p_pair<double>(C2<double>& acc, double x0, dou
 }
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_p2p(int64_t nwi, const int32_t* __restrict__ wi_blk,
-                                             const int32_t* __restrict__ wi_seg, const int32_t* __restrict__ seg_first,
-                                             const int32_t* __restrict__ seg_count, const int32_t* __restrict__ blk_first,
-                                             const int32_t* __restrict__ blk_count, const double* __restrict__ X,
-                                             int64_t nx, const double* __restrict__ Y, int64_t ny,
-                                             const C2<R>* __restrict__ qs, C2<R>* __restrict__ part, double kappa,
-                                             double tau2) {
-  constexpr int NT = 256;
+__global__ __launch_bounds__(64) void k_p2p(int64_t nwi, const int32_t* __restrict__ wi_blk,
+                                            const int32_t* __restrict__ wi_seg, const int32_t* __restrict__ seg_first,
+                                            const int32_t* __restrict__ seg_count, const int32_t* __restrict__ blk_first,
+                                            const int32_t* __restrict__ blk_count, const double* __restrict__ X,
+                                            int64_t nx, const double* __restrict__ Y, int64_t ny,
+                                            const C2<R>* __restrict__ qs, C2<R>* __restrict__ part, double kappa,
+                                            double tau2) {
+  // One wave per work item.  Lane = (target pair, sub-stream): each lane owns
+  // two targets of the block, so each source read from LDS feeds two
+  // independent pair evaluations.
+  constexpr int NT = 64;
   __shared__ double sx[NT], sy[NT], sz[NT];
   __shared__ C2<R> sq[NT];
-  __shared__ C2<R> red[NT];
+  __shared__ C2<R> red[2 * NT];
+  __shared__ int pre[NT + 1];  // exclusive prefix of segment lengths, pre[ns] = total
+  __shared__ int sfirst[NT];
   int64_t w = xcd_item(nwi);
   if (w >= nwi) return;
-  int blk = wi_blk[w];
-  int tf = blk_first[blk], tc = blk_count[blk];
-  int S = NT / tc;
-  int tid = threadIdx.x;
-  int ti = tid % tc, sub = tid / tc;
-  bool active = sub < S;
-  double x0 = 0, x1 = 0, x2 = 0;
+  const int blk = wi_blk[w];
+  const int tf = blk_first[blk], tc = blk_count[blk];
+  const int np = (tc + 1) >> 1;  // target pairs
+  const int S = NT / np;         // sub-streams
+  const int lane = threadIdx.x;
+  const int tp = lane % np, sub = lane / np;
+  const bool active = sub < S;
+  const int ta = 2 * tp, tb = min(2 * tp + 1, tc - 1);
+  double xa0 = 0, xa1 = 0, xa2 = 0, xb0 = 0, xb1 = 0, xb2 = 0;
   if (active) {
-    x0 = X[tf + ti];
-    x1 = X[nx + tf + ti];
-    x2 = X[2 * nx + tf + ti];
+    xa0 = X[tf + ta];
+    xa1 = X[nx + tf + ta];
+    xa2 = X[2 * nx + tf + ta];
+    xb0 = X[tf + tb];
+    xb1 = X[nx + tf + tb];
+    xb2 = X[2 * nx + tf + tb];
   }
+  // segment prefix sums: one segment per lane, wave-wide inclusive scan
+  const int sb = wi_seg[w], ns = wi_seg[w + 1] - sb;
+  int len = 0;
+  if (lane < ns) {
+    len = seg_count[sb + lane];
+    sfirst[lane] = seg_first[sb + lane];
+  }
+  int incl = len;
+#pragma unroll
+  for (int d = 1; d < NT; d <<= 1) {
+    int v = __shfl_up(incl, d, NT);
+    if (lane >= d) incl += v;
+  }
+  pre[lane + 1] = incl;
+  if (lane == 0) pre[0] = 0;
+  __syncthreads();
+  const int total = pre[ns];
   const R inv4pi = (R)(1.0 / (4.0 * M_PI));
   const R kap2pi = (R)(kappa / (2.0 * M_PI));
-  C2<R> acc = {(R)0, (R)0};
-  for (int sg = wi_seg[w]; sg < wi_seg[w + 1]; ++sg) {
-    int f = seg_first[sg], cnt = seg_count[sg];
-    for (int base = 0; base < cnt; base += NT) {
-      int j = base + tid;
-      if (j < cnt) {
-        sx[tid] = Y[f + j];
-        sy[tid] = Y[ny + f + j];
-        sz[tid] = Y[2 * ny + f + j];
-        sq[tid] = cscale(qs[f + j], inv4pi);
-      }
-      __syncthreads();
-      int m = min(NT, cnt - base);
-      if (active)
-        for (int k = sub; k < m; k += S)
-          p2p_pair<R>(acc, x0, x1, x2, sx[k], sy[k], sz[k], sq[k], kap2pi, (R)kappa, (R)tau2);
-      __syncthreads();
+  auto locate = [&](int pos) {
+    int lo = 0, hi = ns - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (pre[mid] <= pos) lo = mid;
+      else hi = mid - 1;
     }
+    return sfirst[lo] + (pos - pre[lo]);
+  };
+  double ry0 = 0, ry1 = 0, ry2 = 0;
+  C2<R> rq = {(R)0, (R)0};
+  bool valid = lane < total;
+  if (valid) {
+    int j = locate(lane);
+    ry0 = Y[j];
+    ry1 = Y[ny + j];
+    ry2 = Y[2 * ny + j];
+    rq = cscale(qs[j], inv4pi);
   }
-  red[tid] = acc;
+  C2<R> acca = {(R)0, (R)0}, accb = {(R)0, (R)0};
+  for (int base = 0; base < total; base += NT) {
+    if (valid) {
+      sx[lane] = ry0;
+      sy[lane] = ry1;
+      sz[lane] = ry2;
+      sq[lane] = rq;
+    }
+    __syncthreads();
+    int npos = base + NT + lane;
+    valid = npos < total;
+    if (valid) {  // prefetch the next tile while this one is consumed
+      int j = locate(npos);
+      ry0 = Y[j];
+      ry1 = Y[ny + j];
+      ry2 = Y[2 * ny + j];
+      rq = cscale(qs[j], inv4pi);
+    }
+    int m = min(NT, total - base);
+    if (active) {
+#pragma unroll 2
+      for (int k = sub; k < m; k += S) {
+        double y0 = sx[k], y1 = sy[k], y2 = sz[k];
+        C2<R> q = sq[k];
+        p2p_pair<R>(acca, xa0, xa1, xa2, y0, y1, y2, q, kap2pi, (R)kappa, (R)tau2);
+        p2p_pair<R>(accb, xb0, xb1, xb2, y0, y1, y2, q, kap2pi, (R)kappa, (R)tau2);
+      }
+    }
+    __syncthreads();
+  }
+  red[2 * lane] = acca;
+  red[2 * lane + 1] = accb;
   __syncthreads();
-  if (tid < tc) {
+  if (lane < tc) {
+    const int p = lane >> 1, which = lane & 1;
     C2<R> s = {(R)0, (R)0};
     for (int u = 0; u < S; ++u) {
-      s.x += red[u * tc + tid].x;
-      s.y += red[u * tc + tid].y;
+      C2<R> v = red[2 * (u * np + p) + which];
+      s.x += v.x;
+      s.y += v.y;
     }
-    part[w * 64 + tid] = s;
+    part[w * 64 + lane] = s;
   }
 }
 
@@ -781,10 +949,23 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
   tm.end();
 
   tm.begin(kPassM2L);
-  if (P.n_m2l_tgt > 0)
-    DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l<R, LL>), dim3(xcd_grid(P.n_m2l_tgt)), dim3(256), 0, s,
-                                          P.n_m2l_tgt, P.m2l_tgt, P.m2l_begin, P.m2l_src, P.m2l_off,
-                                          (const C2<R>*)Mt, S, Lx));
+  if (P.n_m2l_tgt > 0) {
+    if (P.m2l_variant == 0) {
+      DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l<R, LL>), dim3(xcd_grid(P.n_m2l_tgt)), dim3(256), 0, s,
+                                           P.n_m2l_tgt, P.m2l_tgt, P.m2l_begin, (const int2*)P.m2l_pair,
+                                           (const C2<R>*)Mt, S, Lx));
+    } else {
+      C2<R>* Lt = (C2<R>*)W.Lt;
+      // one launch over all levels; 8 slices (one per XCD)
+      DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_slice<R, LL, 8>), dim3((unsigned)(8 * P.n_m2l_tgt)), dim3(64), 0, s,
+                                           P.n_m2l_tgt, P.m2l_begin, (const int2*)P.m2l_pair, (const C2<R>*)Mt, S,
+                                           Lt));
+      tm.end();
+      tm.begin(kPassF2L);
+      DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_f2l<R, LL>), dim3(xcd_grid(P.n_m2l_tgt)), dim3(256), 0, s,
+                                           P.n_m2l_tgt, P.m2l_tgt, (const C2<R>*)Lt, Lx));
+    }
+  }
   tm.end();
 
   tm.begin(kPassL2L);
@@ -798,7 +979,7 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
 
   tm.begin(kPassP2P);
   if (P.nwi > 0)
-    hipLaunchKernelGGL((k_p2p<R>), dim3(xcd_grid(P.nwi)), dim3(256), 0, s, P.nwi, P.wi_blk, P.wi_seg_begin,
+    hipLaunchKernelGGL((k_p2p<R>), dim3(xcd_grid(P.nwi)), dim3(64), 0, s, P.nwi, P.wi_blk, P.wi_seg_begin,
                        P.seg_first, P.seg_count, P.blk_first, P.blk_count, P.tx.soa, P.tx.n, P.ty.soa, P.ty.n,
                        (const C2<R>*)qs, part, P.kappa, P.tau * P.tau);
   tm.end();

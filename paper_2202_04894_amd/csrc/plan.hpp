@@ -12,8 +12,9 @@ namespace defmm {
 constexpr int kKeyBits = 21;   // Morton key bits per dimension
 constexpr int kMaxLevel = 21;  // cells at this level are always leaves
 constexpr int kP2PBlock = 64;  // target points per P2P block
-constexpr int kP2PChunk = 4096;  // source points per P2P work item (balance)
+constexpr int kP2PChunk = 2048;  // source points per P2P work item (balance)
 constexpr int kL2PChunk = 256;   // target points per L2P work item
+constexpr int kMaxSegPerItem = 64;  // source segments per P2P work item (one wave-wide scan)
 
 struct BuildParams {
   int L = 5;
@@ -78,6 +79,7 @@ struct HostPlan {
   std::vector<int32_t> m2f_exp;
   // M2L: target expansions with interactions, CSR of (Fourier row, offset id)
   std::vector<int32_t> m2l_tgt, m2l_begin;  // begin: ntgt + 1
+  std::vector<int32_t> m2l_level_tgt;       // per level l: first target of level l (nlevels + 1)
   std::vector<int32_t> m2l_src, m2l_off;
   // L2L per level l (children at l+1): child expansions, CSR of (parent exp, octant)
   std::vector<std::vector<int32_t>> l2l_ch, l2l_begin, l2l_par;

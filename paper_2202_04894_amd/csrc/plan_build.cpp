@@ -12,6 +12,7 @@
 #include <cstring>
 #include <numeric>
 #include <stdexcept>
+#include <tuple>
 #include <thread>
 #include <unordered_map>
 
@@ -409,8 +410,15 @@ void build_tables(HostPlan& hp) {
     }
   std::vector<int64_t> order(nm);
   std::iota(order.begin(), order.end(), 0);
+  // targets ordered by (level, direction, Morton cell): neighbouring work
+  // shares sources and spectra; inside a target, sources in Morton order
+  auto tkey = [&](int64_t i) {
+    int32_t c = X.exp_cell[te[i]];
+    return std::make_tuple(X.level[c], X.exp_dir[te[i]], c);
+  };
   std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
-    if (te[a] != te[b]) return te[a] < te[b];
+    auto ka = tkey(a), kb = tkey(b);
+    if (ka != kb) return ka < kb;
     return se[a] < se[b];
   });
   hp.m2l_src.resize(nm);
@@ -425,6 +433,9 @@ void build_tables(HostPlan& hp) {
     hp.m2l_off[k] = hp.m2l[i].off;
   }
   hp.m2l_begin.push_back((int32_t)nm);
+  hp.m2l_level_tgt.assign(X.nlevels + 1, 0);
+  for (int32_t e : hp.m2l_tgt) hp.m2l_level_tgt[X.level[X.exp_cell[e]] + 1]++;
+  for (int l = 0; l < X.nlevels; ++l) hp.m2l_level_tgt[l + 1] += hp.m2l_level_tgt[l];
   // L2L, sons level by level
   hp.l2l_ch.assign(X.nlevels, {});
   hp.l2l_begin.assign(X.nlevels, {});
@@ -514,13 +525,16 @@ void build_tables(HostPlan& hp) {
       hp.p2p_point_pairs += total * bc;
       int32_t blk = (int32_t)hp.blk_first.size() - 1;
       int64_t acc = kP2PChunk;  // forces a new work item first
+      int nseg = 0;
       for (auto& r : ranges) {
         for (int32_t off = 0; off < r.second;) {
-          if (acc >= kP2PChunk) {
+          if (acc >= kP2PChunk || nseg >= kMaxSegPerItem) {
             hp.wi_blk.push_back(blk);
             hp.wi_seg_begin.push_back((int32_t)hp.seg_first.size());
             acc = 0;
+            nseg = 0;
           }
+          ++nseg;
           int32_t take = (int32_t)std::min<int64_t>(r.second - off, kP2PChunk - acc);
           hp.seg_first.push_back(r.first + off);
           hp.seg_count.push_back(take);

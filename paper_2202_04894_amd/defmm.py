@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libdefmm.so")
 C128, C64 = 0, 1
 M2L_AUTO, M2L_FFT, M2L_DENSE = 0, 1, 2
 SAME_POINTS = 1
-NUM_PASSES = 10
+NUM_PASSES = 11
 
 
 class DefmmError(RuntimeError):

@@ -65,6 +65,8 @@ FMM_CASES = [
     ("ellipsoid", 5000, 48.0, dict(order_L=4, ncrit=20, hf_threshold=1.0)),
     ("cube_surface", 4000, 30.0, dict(order_L=3, ncrit=40, eta=0.7, dir_refine=2)),
     ("cube_volume", 3000, 12.0, dict(order_L=6, ncrit=50)),
+    # tiny leaves: many one-cell source segments per near-field work item
+    ("cube_volume", 6000, 6.0, dict(order_L=3, ncrit=3)),
 ]
 
 
