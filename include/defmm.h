@@ -149,6 +149,13 @@ defmm_status defmm_workspace_export_expansions(defmm_workspace* ws, int32_t whic
    last reset, calls[i] counts launches.  Pass names: defmm_pass_name(i). */
 #define DEFMM_NUM_PASSES 11
 defmm_status defmm_workspace_set_timing(defmm_workspace* ws, int32_t enable);
+
+/* Overlap (default on): the near field (P2P) runs on a stream owned by the
+   workspace, forked after the charge gather and joined before L2P, as a
+   persistent kernel that leaves wave slots to the far field.  Off: every pass
+   runs in sequence on the caller's stream at full occupancy (used to time
+   each kernel alone).  Results are bitwise identical either way. */
+defmm_status defmm_workspace_set_overlap(defmm_workspace* ws, int32_t enable);
 defmm_status defmm_workspace_pass_times(defmm_workspace* ws, double* pass_ms, int64_t* calls);
 const char* defmm_pass_name(int32_t i);
 

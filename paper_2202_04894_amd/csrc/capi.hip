@@ -79,6 +79,12 @@ void upload_tree(DevPlan& P, DevTree& d, const Tree& t) {
 
 size_t csize(const DevPlan& P) { return P.precision == 0 ? 16 : 8; }
 
+// Row stride of the Fourier-domain arrays: (2L-1)^3 rounded up to 16 entries.
+int fourier_row(int L) {
+  int P3 = (2 * L - 1) * (2 * L - 1) * (2 * L - 1);
+  return ((P3 + 15) / 16) * 16;
+}
+
 }  // namespace
 
 namespace defmm {
@@ -86,9 +92,12 @@ DevPlan::~DevPlan() {
   for (void* p : allocs) hipFree(p);
 }
 Workspace::~Workspace() {
-  for (void* p : {qs, ps, M, Lx, Mt, Lt, part})
+  for (void* p : {qs, ps, M, Lx, Mt, Lt, part, (void*)queue})
     if (p) hipFree(p);
   for (hipEvent_t e : ev_pool) hipEventDestroy(e);
+  if (ev_fork) hipEventDestroy(ev_fork);
+  if (ev_join) hipEventDestroy(ev_join);
+  if (side) hipStreamDestroy(side);
 }
 }  // namespace defmm
 
@@ -254,6 +263,27 @@ defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int
     }
     P.n_m2l_tgt = (int64_t)H.m2l_tgt.size();
     P.m2l_level_tgt.assign(H.m2l_level_tgt.begin(), H.m2l_level_tgt.end());
+    P.grp_tfirst = upload(P, H.grp_tfirst);
+    P.grp_tcount = upload(P, H.grp_tcount);
+    P.grp_run_begin = upload(P, H.grp_run_begin);
+    P.runs = upload(P, H.runs);
+    P.n_grp = (int64_t)H.grp_tfirst.size();
+    if (const char* e = std::getenv("DEFMM_M2L_VARIANT")) {
+      int v = std::atoi(e);
+      if (v >= 0 && v <= 2) P.m2l_variant = v;
+    }
+    {
+      int dev = 0;
+      hipDeviceProp_t prop;
+      if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
+          prop.multiProcessorCount > 0)
+        P.num_cu = prop.multiProcessorCount;
+      P.p2p_waves_per_cu = 2;
+      if (const char* e = std::getenv("DEFMM_P2P_WAVES_PER_CU")) {
+        int v = std::atoi(e);
+        if (v >= 1 && v <= 32) P.p2p_waves_per_cu = v;
+      }
+    }
 
     P.n_m2l = (int64_t)H.m2l_src.size();
     P.l2l.resize(H.l2l_ch.size());
@@ -281,8 +311,7 @@ defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int
     // spectra, one per distinct (level, delta), computed on the device in FP64
     P.n_off = (int64_t)H.offsets.size();
     if (P.n_off > 0) {
-      int P3 = (2 * P.L - 1) * (2 * P.L - 1) * (2 * P.L - 1);
-      P.spectra = dalloc(P, (size_t)P.n_off * P3 * csize(P));
+      P.spectra = dalloc(P, (size_t)P.n_off * fourier_row(P.L) * csize(P));
       std::vector<int32_t> lev(P.n_off), dl(3 * P.n_off);
       for (int64_t i = 0; i < P.n_off; ++i) {
         lev[i] = H.offsets[i].level;
@@ -310,9 +339,9 @@ defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int
 
 static size_t workspace_bytes(const DevPlan& P) {
   size_t cs = csize(P);
-  int L3 = P.L * P.L * P.L, P3 = (2 * P.L - 1) * (2 * P.L - 1) * (2 * P.L - 1);
+  int L3 = P.L * P.L * P.L, P3 = fourier_row(P.L);
   return cs * ((size_t)P.ny + (size_t)P.nx + (size_t)P.ty.nexp * L3 + (size_t)P.tx.nexp * L3 +
-               (size_t)P.n_m2f * P3 + (size_t)P.nwi * 64 + (P.m2l_variant == 1 ? (size_t)P.n_m2l_tgt * P3 : 0));
+               (size_t)P.n_m2f * P3 + (size_t)P.nwi * 64 + (P.m2l_variant >= 1 ? (size_t)P.n_m2l_tgt * P3 : 0));
 }
 
 defmm_status defmm_plan_footprint(const defmm_plan* plan, size_t* resident, size_t* ws) {
@@ -357,7 +386,7 @@ defmm_status defmm_workspace_create(defmm_plan* plan, defmm_workspace** out) {
   Workspace& W = ws->impl;
   W.plan = &P;
   size_t cs = csize(P);
-  int L3 = P.L * P.L * P.L, P3 = (2 * P.L - 1) * (2 * P.L - 1) * (2 * P.L - 1);
+  int L3 = P.L * P.L * P.L, P3 = fourier_row(P.L);
   struct {
     void** p;
     size_t n;
@@ -366,8 +395,9 @@ defmm_status defmm_workspace_create(defmm_plan* plan, defmm_workspace** out) {
               {&W.M, cs * (size_t)P.ty.nexp * L3},
               {&W.Lx, cs * (size_t)P.tx.nexp * L3},
               {&W.Mt, cs * (size_t)P.n_m2f * P3},
-              {&W.Lt, P.m2l_variant == 1 ? cs * (size_t)P.n_m2l_tgt * P3 : 0},
-              {&W.part, cs * (size_t)P.nwi * 64}};
+              {&W.Lt, P.m2l_variant >= 1 ? cs * (size_t)P.n_m2l_tgt * P3 : 0},
+              {&W.part, cs * (size_t)P.nwi * 64},
+              {(void**)&W.queue, 8 * sizeof(int)}};
   for (auto& b : bufs) {
     if (b.n == 0) continue;
     hipError_t e = hipMalloc(b.p, b.n);
@@ -377,6 +407,15 @@ defmm_status defmm_workspace_create(defmm_plan* plan, defmm_workspace** out) {
                   std::string("workspace hipMalloc: ") + hipGetErrorString(e));
     }
     W.bytes += b.n;
+  }
+  {
+    hipError_t e = hipStreamCreateWithFlags(&W.side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&W.ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&W.ev_join, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      delete ws;
+      return fail(DEFMM_ERR_DEVICE, std::string("workspace stream/events: ") + hipGetErrorString(e));
+    }
   }
   *out = ws;
   return DEFMM_OK;
@@ -479,6 +518,12 @@ defmm_status defmm_workspace_export_expansions(defmm_workspace* ws, int32_t whic
 defmm_status defmm_workspace_set_timing(defmm_workspace* ws, int32_t enable) {
   if (!ws) return fail(DEFMM_ERR_INVALID_ARG, "workspace is NULL");
   ws->impl.timing = enable != 0;
+  return DEFMM_OK;
+}
+
+defmm_status defmm_workspace_set_overlap(defmm_workspace* ws, int32_t enable) {
+  if (!ws) return fail(DEFMM_ERR_INVALID_ARG, "workspace is NULL");
+  ws->impl.overlap = enable != 0;
   return DEFMM_OK;
 }
 

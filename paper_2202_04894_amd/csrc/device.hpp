@@ -53,7 +53,9 @@ struct LevelTable {  // per-level operator table on the device
 struct DevPlan {
   HostPlan host;   // kept for introspection and stats
   int L = 5, precision = 1;
-  int m2l_variant = 1;  // 0: Hadamard + F2L fused per target, 1: frequency-sliced + separate F2L
+  int m2l_variant = 2;  // 0: fused per target, 1: sliced per target, 2: sliced per group of 8 (source runs)
+  int num_cu = 256;           // compute units of the device (hipDeviceProp)
+  int p2p_waves_per_cu = 2;   // persistent near-field workgroups (one wave each) per CU when overlapped
   double kappa = 0.0, D = 0.0, origin[3] = {0, 0, 0}, tau = 0.0;
   DevTree tx, ty;
   bool same = false;
@@ -69,6 +71,8 @@ struct DevPlan {
   int32_t* m2l_pair = nullptr;  // per entry: (Fourier-domain multipole row, spectrum id)
   int64_t n_m2l_tgt = 0, n_m2l = 0;
   std::vector<int64_t> m2l_level_tgt;  // target range per level (host copy)
+  int32_t *grp_tfirst = nullptr, *grp_tcount = nullptr, *grp_run_begin = nullptr, *runs = nullptr;
+  int64_t n_grp = 0;
   std::vector<LevelTable> l2l;  // a = child exps, b = CSR begin (n+1), c = parent exps, oct
   int32_t *l2p_cell = nullptr, *l2p_first = nullptr, *l2p_count = nullptr;
   int64_t n_l2p = 0;
@@ -93,7 +97,11 @@ struct Workspace {
   void* Mt = nullptr;    // Fourier-domain multipoles, n_m2f x P^3
   void* Lt = nullptr;    // Fourier-domain locals, n_m2l_tgt x P^3 (sliced M2L only)
   void* part = nullptr;  // P2P partial sums, nwi x 64
+  int* queue = nullptr;  // 8 work-queue heads of the persistent P2P
   size_t bytes = 0;
+  hipStream_t side = nullptr;   // near-field stream (default priority), forked per matvec
+  bool overlap = true;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <algorithm>
 #include <cstdio>
 
 #include "device.hpp"
@@ -82,6 +83,12 @@ __device__ __forceinline__ void lagrange(R t, R* w) {
 }
 
 constexpr int round64(int x) { return ((x + 63) / 64) * 64; }
+
+// Row stride of every Fourier-domain array (spectra, M~, L~): P^3 rounded up
+// to a multiple of 16 complex values, so that a row splits into 8 slices of
+// an even number of entries and each lane moves two entries (16 B in
+// complex64) per load.  The padding entries are never read back.
+constexpr int row_stride(int P3) { return ((P3 + 15) / 16) * 16; }
 
 // XCD-aware block order: the hardware deals consecutive workgroups to the 8
 // XCDs round-robin; remap so each XCD walks a contiguous range of items and
@@ -194,7 +201,7 @@ __global__ __launch_bounds__(256) void k_spectra(int64_t n, const int32_t* __res
   }
   const double scale = 1.0 / (double)P3;
   for (int i = tid; i < P3; i += blockDim.x)
-    S[o * P3 + i] = {(R)(a[i].x * scale), (R)(a[i].y * scale)};
+    S[o * row_stride(P3) + i] = {(R)(a[i].x * scale), (R)(a[i].y * scale)};
 }
 
 // ------------------------------------------------------------------ P2M
@@ -354,7 +361,7 @@ __global__ __launch_bounds__(256) void k_m2f(int64_t n, const int32_t* __restric
     C2<R> s = {(R)0, (R)0};
 #pragma unroll
     for (int r = 0; r < L; ++r) cfma(s, c[xy + P * P * r], W[(zi * r) % P]);
-    Mt[item * P3 + i] = s;
+    Mt[item * row_stride(P3) + i] = s;
   }
 }
 
@@ -383,8 +390,8 @@ __global__ __launch_bounds__(256) void k_m2l(int64_t ntgt, const int32_t* __rest
   int kb = begin[i], ke = begin[i + 1];
   for (int k = kb; k < ke; ++k) {
     const int2 pr = pairs[k];
-    const C2<R>* ms = Mt + (int64_t)pr.x * P3;
-    const C2<R>* ds = S + (int64_t)pr.y * P3;
+    const C2<R>* ms = Mt + (int64_t)pr.x * row_stride(P3);
+    const C2<R>* ds = S + (int64_t)pr.y * row_stride(P3);
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       int xi = tid + f * NT;
@@ -429,14 +436,21 @@ __global__ __launch_bounds__(256) void k_m2l(int64_t ntgt, const int32_t* __rest
 // touches slice j of every spectrum and every Fourier-domain multipole: each
 // XCD's L2 holds 1/8 of the operands.  One wave per workgroup; the pair loop
 // is unrolled by 4 so each lane keeps 8*NF loads in flight.
+template <typename R>
+struct alignas(2 * sizeof(C2<R>)) C2x2 {
+  C2<R> a, b;
+};
+
 template <typename R, int L, int NSL>
 __global__ __launch_bounds__(64) void k_m2l_slice(int64_t ntgt, const int32_t* __restrict__ begin,
                                                   const int2* __restrict__ pairs, const C2<R>* __restrict__ Mt,
                                                   const C2<R>* __restrict__ S, C2<R>* __restrict__ Lt) {
   // NSL slices (a multiple of 8): XCD j gets slices j, j+8, ...; the block
   // order walks all targets of one slice before the next on each XCD.
-  constexpr int P = 2 * L - 1, P3 = P * P * P;
-  constexpr int SL = (P3 + NSL - 1) / NSL, NF = (SL + 63) / 64, U = 8;
+  // Each lane owns two consecutive frequencies of the slice.
+  constexpr int P = 2 * L - 1, P3 = P * P * P, P3R = row_stride(P3);
+  constexpr int SL = P3R / NSL, NP = SL / 2, NF = (NP + 63) / 64, U = 8;
+  static_assert(SL % 2 == 0, "slices hold an even number of entries");
   const int64_t b = blockIdx.x;
   const int xcd = (int)(b % 8);
   const int64_t j = b / 8;
@@ -447,46 +461,135 @@ __global__ __launch_bounds__(64) void k_m2l_slice(int64_t ntgt, const int32_t* _
   bool ok[NF];
 #pragma unroll
   for (int f = 0; f < NF; ++f) {
-    int loc = lane + 64 * f;
-    fl[f] = slice * SL + loc;
-    ok[f] = loc < SL && fl[f] < P3;
-    if (!ok[f]) fl[f] = 0;
+    int pi = lane + 64 * f;
+    ok[f] = pi < NP;
+    fl[f] = ok[f] ? slice * SL + 2 * pi : slice * SL;
   }
-  C2<R> acc[NF];
+  C2<R> acc0[NF], acc1[NF];
 #pragma unroll
-  for (int f = 0; f < NF; ++f) acc[f] = {(R)0, (R)0};
+  for (int f = 0; f < NF; ++f) acc0[f] = acc1[f] = {(R)0, (R)0};
   int k = begin[i];
   const int ke = begin[i + 1];
   for (; k + U <= ke; k += U) {
     int2 pr[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) pr[u] = pairs[k + u];
-    C2<R> mv[U][NF], dv[U][NF];
+    C2x2<R> mv[U][NF], dv[U][NF];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const C2<R>* ms = Mt + (int64_t)pr[u].x * P3;
-      const C2<R>* ds = S + (int64_t)pr[u].y * P3;
+      const C2<R>* ms = Mt + (int64_t)pr[u].x * P3R;
+      const C2<R>* ds = S + (int64_t)pr[u].y * P3R;
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
-        mv[u][f] = ms[fl[f]];
-        dv[u][f] = ds[fl[f]];
+        mv[u][f] = *reinterpret_cast<const C2x2<R>*>(ms + fl[f]);
+        dv[u][f] = *reinterpret_cast<const C2x2<R>*>(ds + fl[f]);
       }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int f = 0; f < NF; ++f) cfma(acc[f], dv[u][f], mv[u][f]);
+      for (int f = 0; f < NF; ++f) {
+        cfma(acc0[f], dv[u][f].a, mv[u][f].a);
+        cfma(acc1[f], dv[u][f].b, mv[u][f].b);
+      }
   }
   for (; k < ke; ++k) {
     const int2 pr = pairs[k];
-    const C2<R>* ms = Mt + (int64_t)pr.x * P3;
-    const C2<R>* ds = S + (int64_t)pr.y * P3;
+    const C2<R>* ms = Mt + (int64_t)pr.x * P3R;
+    const C2<R>* ds = S + (int64_t)pr.y * P3R;
 #pragma unroll
-    for (int f = 0; f < NF; ++f) cfma(acc[f], ds[fl[f]], ms[fl[f]]);
+    for (int f = 0; f < NF; ++f) {
+      C2x2<R> m = *reinterpret_cast<const C2x2<R>*>(ms + fl[f]);
+      C2x2<R> d = *reinterpret_cast<const C2x2<R>*>(ds + fl[f]);
+      cfma(acc0[f], d.a, m.a);
+      cfma(acc1[f], d.b, m.b);
+    }
   }
 #pragma unroll
   for (int f = 0; f < NF; ++f)
-    if (ok[f]) Lt[i * P3 + fl[f]] = acc[f];
+    if (ok[f]) *reinterpret_cast<C2x2<R>*>(Lt + i * P3R + fl[f]) = C2x2<R>{acc0[f], acc1[f]};
+}
+
+// Hadamard accumulate over source runs.  A workgroup (one wave) handles one
+// group of <= 8 targets sharing level and direction, and one frequency slice
+// (slice-major per XCD as in k_m2l_slice).  Each run loads the source's
+// Fourier-domain multipole once and the spectrum of every group target that
+// interacts with it, so one source load feeds several targets.  All branches
+// depend only on the run records (uniform), accumulators sit at fixed
+// register indices.
+template <typename R, int L, int NSL>
+__global__ __launch_bounds__(64) void k_m2l_runs(int64_t ngrp, const int32_t* __restrict__ grp_tfirst,
+                                                 const int32_t* __restrict__ grp_tcount,
+                                                 const int32_t* __restrict__ run_begin, const int32_t* __restrict__ runs,
+                                                 const C2<R>* __restrict__ Mt, const C2<R>* __restrict__ S,
+                                                 C2<R>* __restrict__ Lt) {
+  constexpr int P = 2 * L - 1, P3 = P * P * P, P3R = row_stride(P3);
+  constexpr int SL = P3R / NSL, NP = SL / 2, NF = (NP + 63) / 64, G = 8;
+  constexpr int U = sizeof(R) == 4 ? 2 : 1;  // runs per batch
+  const int64_t b = blockIdx.x;
+  const int xcd = (int)(b % 8);
+  const int64_t j = b / 8;
+  const int slice = xcd + 8 * (int)(j / ngrp);
+  const int64_t g = j % ngrp;
+  const int lane = threadIdx.x;
+  int fl[NF];
+  bool ok[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    int pi = lane + 64 * f;
+    ok[f] = pi < NP;
+    fl[f] = ok[f] ? slice * SL + 2 * pi : slice * SL;
+  }
+  C2x2<R> acc[G][NF];
+#pragma unroll
+  for (int t = 0; t < G; ++t)
+#pragma unroll
+    for (int f = 0; f < NF; ++f) acc[t][f] = C2x2<R>{{(R)0, (R)0}, {(R)0, (R)0}};
+  int r = run_begin[g];
+  const int re = run_begin[g + 1];
+  for (; r < re; r += U) {
+    int rec[U][9];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int q = 0; q < 9; ++q) rec[u][q] = (r + u < re) ? runs[(int64_t)(r + u) * 9 + q] : -1;
+    C2x2<R> mv[U][NF], dv[U][G][NF];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (rec[u][0] < 0) continue;
+      const C2<R>* ms = Mt + (int64_t)rec[u][0] * P3R;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) mv[u][f] = *reinterpret_cast<const C2x2<R>*>(ms + fl[f]);
+#pragma unroll
+      for (int t = 0; t < G; ++t) {
+        if (rec[u][1 + t] < 0) continue;
+        const C2<R>* ds = S + (int64_t)rec[u][1 + t] * P3R;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) dv[u][t][f] = *reinterpret_cast<const C2x2<R>*>(ds + fl[f]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (rec[u][0] < 0) continue;
+#pragma unroll
+      for (int t = 0; t < G; ++t) {
+        if (rec[u][1 + t] < 0) continue;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          cfma(acc[t][f].a, dv[u][t][f].a, mv[u][f].a);
+          cfma(acc[t][f].b, dv[u][t][f].b, mv[u][f].b);
+        }
+      }
+    }
+  }
+  const int64_t tf = grp_tfirst[g];
+  const int tc = grp_tcount[g];
+#pragma unroll
+  for (int t = 0; t < G; ++t)
+    if (t < tc)
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+        if (ok[f]) *reinterpret_cast<C2x2<R>*>(Lt + (tf + t) * P3R + fl[f]) = acc[t][f];
 }
 
 // F2L: pruned inverse DFT of each target's accumulated Fourier-domain local
@@ -502,7 +605,7 @@ __global__ __launch_bounds__(256) void k_f2l(int64_t ntgt, const int32_t* __rest
   int64_t i = xcd_item(ntgt);
   if (i >= ntgt) return;
   int tid = threadIdx.x;
-  for (int j = tid; j < P3; j += NT) A[j] = Lt[i * P3 + j];
+  for (int j = tid; j < P3; j += NT) A[j] = Lt[i * row_stride(P3) + j];
   if (tid < P) W[tid] = expi<R>(2.0 * M_PI * (double)tid / (double)P);
   __syncthreads();
   for (int j = tid; j < P * P * L; j += NT) {
@@ -705,24 +808,18 @@ __device__ __forceinline__ void p2p_pair<double>(C2<double>& acc, double x0, dou
 }
 
 template <typename R>
-__global__ __launch_bounds__(64) void k_p2p(int64_t nwi, const int32_t* __restrict__ wi_blk,
+__device__ __forceinline__ void p2p_item(int64_t w, const int32_t* __restrict__ wi_blk,
                                             const int32_t* __restrict__ wi_seg, const int32_t* __restrict__ seg_first,
                                             const int32_t* __restrict__ seg_count, const int32_t* __restrict__ blk_first,
                                             const int32_t* __restrict__ blk_count, const double* __restrict__ X,
                                             int64_t nx, const double* __restrict__ Y, int64_t ny,
                                             const C2<R>* __restrict__ qs, C2<R>* __restrict__ part, double kappa,
-                                            double tau2) {
+                                            double tau2, double* sx, double* sy, double* sz, C2<R>* sq,
+                                            C2<R>* red, int* pre, int* sfirst) {
   // One wave per work item.  Lane = (target pair, sub-stream): each lane owns
   // two targets of the block, so each source read from LDS feeds two
   // independent pair evaluations.
   constexpr int NT = 64;
-  __shared__ double sx[NT], sy[NT], sz[NT];
-  __shared__ C2<R> sq[NT];
-  __shared__ C2<R> red[2 * NT];
-  __shared__ int pre[NT + 1];  // exclusive prefix of segment lengths, pre[ns] = total
-  __shared__ int sfirst[NT];
-  int64_t w = xcd_item(nwi);
-  if (w >= nwi) return;
   const int blk = wi_blk[w];
   const int tf = blk_first[blk], tc = blk_count[blk];
   const int np = (tc + 1) >> 1;  // target pairs
@@ -821,6 +918,49 @@ __global__ __launch_bounds__(64) void k_p2p(int64_t nwi, const int32_t* __restri
     }
     part[w * 64 + lane] = s;
   }
+  __syncthreads();
+}
+
+// Persistent near field: a bounded number of one-wave workgroups per CU pull
+// work items from 8 queues, queue j covering the j-th eighth of the items
+// (workgroup b starts on queue b % 8, which the hardware places on XCD b % 8,
+// keeping neighbouring items in one L2), then help the other queues.  The
+// free wave slots stay available to the far-field kernels on the other
+// stream.  Every workgroup leaves once all queues are drained.
+template <typename R>
+__global__ __launch_bounds__(64) void k_p2p(int64_t nwi, int* __restrict__ queue, const int32_t* __restrict__ wi_blk,
+                                            const int32_t* __restrict__ wi_seg, const int32_t* __restrict__ seg_first,
+                                            const int32_t* __restrict__ seg_count, const int32_t* __restrict__ blk_first,
+                                            const int32_t* __restrict__ blk_count, const double* __restrict__ X,
+                                            int64_t nx, const double* __restrict__ Y, int64_t ny,
+                                            const C2<R>* __restrict__ qs, C2<R>* __restrict__ part, double kappa,
+                                            double tau2) {
+  __shared__ double sx[64], sy[64], sz[64];
+  __shared__ C2<R> sq[64];
+  __shared__ C2<R> red[128];
+  __shared__ int pre[65];
+  __shared__ int sfirst[64];
+  __shared__ int next;
+  const int64_t nper = (nwi + 7) / 8;
+  const int q0 = (int)(blockIdx.x % 8);
+  for (int qq = 0; qq < 8; ++qq) {
+    const int qi = (q0 + qq) % 8;
+    const int64_t lo = qi * nper, hi = min(nwi, (int64_t)(qi + 1) * nper);
+    for (;;) {
+      if (threadIdx.x == 0) next = atomicAdd(&queue[qi], 1);
+      __syncthreads();
+      const int64_t w = lo + next;
+      __syncthreads();
+      if (w >= hi) break;
+      p2p_item<R>(w, wi_blk, wi_seg, seg_first, seg_count, blk_first, blk_count, X, nx, Y, ny, qs, part, kappa,
+                  tau2, sx, sy, sz, sq, red, pre, sfirst);
+    }
+  }
+}
+
+__global__ void k_zero_int(int n, int* __restrict__ a) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0;
 }
 
 template <typename R>
@@ -869,9 +1009,10 @@ namespace {
 struct PassTimer {
   Workspace& W;
   hipStream_t s;
+  hipStream_t cur;
   int pass = -1;
   size_t a = 0;
-  PassTimer(Workspace& w, hipStream_t st) : W(w), s(st) {}
+  PassTimer(Workspace& w, hipStream_t st) : W(w), s(st), cur(st) {}
   hipEvent_t next() {
     if (W.ev_used == W.ev_pool.size()) {
       hipEvent_t e;
@@ -880,19 +1021,21 @@ struct PassTimer {
     }
     return W.ev_pool[W.ev_used++];
   }
-  void begin(int p) {
+  void begin(int p) { begin(p, s); }
+  void begin(int p, hipStream_t st) {
+    cur = st;
     if (!W.timing) return;
     pass = p;
     a = W.ev_used;
     hipEvent_t e = next();
-    if (e) (void)hipEventRecord(e, s);
+    if (e) (void)hipEventRecord(e, cur);
   }
   void end() {
     if (!W.timing || pass < 0) return;
     size_t b = W.ev_used;
     hipEvent_t e = next();
     if (e) {
-      (void)hipEventRecord(e, s);
+      (void)hipEventRecord(e, cur);
       W.pending.push_back({pass, a, b});
     }
     pass = -1;
@@ -924,8 +1067,36 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
                        (const C2<R>*)q, qs);
   if (P.tx.nexp > 0)
     hipLaunchKernelGGL((k_zero<R>), dim3(blocks_for(P.tx.nexp * L3, 256)), dim3(256), 0, s, P.tx.nexp * L3, Lx);
-  if (P.nx > 0) hipLaunchKernelGGL((k_zero<R>), dim3(blocks_for(P.nx, 256)), dim3(256), 0, s, P.nx, ps);
   tm.end();
+
+  // Near field on the workspace's side stream, concurrently with the far
+  // field (the ALU-bound P2P overlaps the L2-bound M2L); joined before L2P.
+  hipStream_t s2 = (W.side && W.overlap) ? W.side : s;
+  if (s2 != s) {
+    hipError_t e = hipEventRecord(W.ev_fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s2, W.ev_fork, 0);
+    if (e != hipSuccess) return e;
+  }
+  if (P.nx > 0) hipLaunchKernelGGL((k_zero<R>), dim3(blocks_for(P.nx, 256)), dim3(256), 0, s2, P.nx, ps);
+  tm.begin(kPassP2P, s2);
+  if (P.nwi > 0) {
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s2, 8, W.queue);
+    const int wpc = (s2 != s) ? P.p2p_waves_per_cu : 8;  // alone: fill every wave slot
+    const unsigned nb = (unsigned)std::min<int64_t>(P.nwi, (int64_t)P.num_cu * wpc);
+    hipLaunchKernelGGL((k_p2p<R>), dim3(nb), dim3(64), 0, s2, P.nwi, W.queue, P.wi_blk, P.wi_seg_begin,
+                       P.seg_first, P.seg_count, P.blk_first, P.blk_count, P.tx.soa, P.tx.n, P.ty.soa, P.ty.n,
+                       (const C2<R>*)qs, part, P.kappa, P.tau * P.tau);
+  }
+  tm.end();
+  tm.begin(kPassP2PRed, s2);
+  if (P.nblk > 0)
+    hipLaunchKernelGGL((k_p2p_reduce<R>), dim3((unsigned)P.nblk), dim3(64), 0, s2, P.nblk, P.blk_first,
+                       P.blk_count, P.blk_wi_begin, (const C2<R>*)part, ps);
+  tm.end();
+  if (s2 != s) {
+    hipError_t e = hipEventRecord(W.ev_join, s2);
+    if (e != hipSuccess) return e;
+  }
 
   tm.begin(kPassP2M);
   if (P.n_p2m > 0)
@@ -956,10 +1127,16 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
                                            (const C2<R>*)Mt, S, Lx));
     } else {
       C2<R>* Lt = (C2<R>*)W.Lt;
-      // one launch over all levels; 8 slices (one per XCD)
-      DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_slice<R, LL, 8>), dim3((unsigned)(8 * P.n_m2l_tgt)), dim3(64), 0, s,
-                                           P.n_m2l_tgt, P.m2l_begin, (const int2*)P.m2l_pair, (const C2<R>*)Mt, S,
-                                           Lt));
+      if (P.m2l_variant == 2) {
+        DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_runs<R, LL, 8>), dim3((unsigned)(8 * P.n_grp)), dim3(64), 0,
+                                             s, P.n_grp, P.grp_tfirst, P.grp_tcount, P.grp_run_begin, P.runs,
+                                             (const C2<R>*)Mt, S, Lt));
+      } else {
+        // one launch over all levels; 8 slices (one per XCD)
+        DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_slice<R, LL, 8>), dim3((unsigned)(8 * P.n_m2l_tgt)), dim3(64),
+                                             0, s, P.n_m2l_tgt, P.m2l_begin, (const int2*)P.m2l_pair,
+                                             (const C2<R>*)Mt, S, Lt));
+      }
       tm.end();
       tm.begin(kPassF2L);
       DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_f2l<R, LL>), dim3(xcd_grid(P.n_m2l_tgt)), dim3(256), 0, s,
@@ -977,18 +1154,10 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
   }
   tm.end();
 
-  tm.begin(kPassP2P);
-  if (P.nwi > 0)
-    hipLaunchKernelGGL((k_p2p<R>), dim3(xcd_grid(P.nwi)), dim3(64), 0, s, P.nwi, P.wi_blk, P.wi_seg_begin,
-                       P.seg_first, P.seg_count, P.blk_first, P.blk_count, P.tx.soa, P.tx.n, P.ty.soa, P.ty.n,
-                       (const C2<R>*)qs, part, P.kappa, P.tau * P.tau);
-  tm.end();
-
-  tm.begin(kPassP2PRed);
-  if (P.nblk > 0)
-    hipLaunchKernelGGL((k_p2p_reduce<R>), dim3((unsigned)P.nblk), dim3(64), 0, s, P.nblk, P.blk_first,
-                       P.blk_count, P.blk_wi_begin, (const C2<R>*)part, ps);
-  tm.end();
+  if (s2 != s) {
+    hipError_t e = hipStreamWaitEvent(s, W.ev_join, 0);
+    if (e != hipSuccess) return e;
+  }
 
   tm.begin(kPassL2P);
   if (P.n_l2p > 0)

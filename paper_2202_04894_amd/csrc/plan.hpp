@@ -80,6 +80,12 @@ struct HostPlan {
   // M2L: target expansions with interactions, CSR of (Fourier row, offset id)
   std::vector<int32_t> m2l_tgt, m2l_begin;  // begin: ntgt + 1
   std::vector<int32_t> m2l_level_tgt;       // per level l: first target of level l (nlevels + 1)
+  // M2L source runs: targets grouped by <= 8 (same level and direction,
+  // consecutive); per group the pairs are merged by source into runs of
+  // 9 int32: Fourier row of the source, then the spectrum id for each of the
+  // group's 8 targets (-1 where that target has no pair with this source).
+  std::vector<int32_t> grp_tfirst, grp_tcount, grp_run_begin;  // run CSR: ngrp + 1
+  std::vector<int32_t> runs;
   std::vector<int32_t> m2l_src, m2l_off;
   // L2L per level l (children at l+1): child expansions, CSR of (parent exp, octant)
   std::vector<std::vector<int32_t>> l2l_ch, l2l_begin, l2l_par;

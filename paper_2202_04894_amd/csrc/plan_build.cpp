@@ -433,6 +433,41 @@ void build_tables(HostPlan& hp) {
     hp.m2l_off[k] = hp.m2l[i].off;
   }
   hp.m2l_begin.push_back((int32_t)nm);
+  // groups of <= 8 targets sharing level and direction, merged by source
+  {
+    int64_t nt = (int64_t)hp.m2l_tgt.size();
+    std::vector<std::pair<int32_t, int32_t>> ent;  // (source row, tloc * 2^28 + offset)
+    for (int64_t t0 = 0; t0 < nt;) {
+      int32_t c0 = X.exp_cell[hp.m2l_tgt[t0]];
+      int lv = X.level[c0], dr = X.exp_dir[hp.m2l_tgt[t0]];
+      int64_t t1 = t0 + 1;
+      while (t1 < nt && t1 - t0 < 8 && X.level[X.exp_cell[hp.m2l_tgt[t1]]] == lv &&
+             X.exp_dir[hp.m2l_tgt[t1]] == dr)
+        ++t1;
+      ent.clear();
+      for (int64_t t = t0; t < t1; ++t)
+        for (int32_t k = hp.m2l_begin[t]; k < hp.m2l_begin[t + 1]; ++k)
+          ent.push_back({hp.m2l_src[k], (int32_t)(((t - t0) << 28) | hp.m2l_off[k])});
+      std::sort(ent.begin(), ent.end());
+      hp.grp_tfirst.push_back((int32_t)t0);
+      hp.grp_tcount.push_back((int32_t)(t1 - t0));
+      hp.grp_run_begin.push_back((int32_t)(hp.runs.size() / 9));
+      for (size_t a = 0; a < ent.size();) {
+        size_t b = a;
+        int32_t rec[9];
+        rec[0] = ent[a].first;
+        for (int q = 1; q < 9; ++q) rec[q] = -1;
+        while (b < ent.size() && ent[b].first == ent[a].first) {
+          rec[1 + (ent[b].second >> 28)] = ent[b].second & ((1 << 28) - 1);
+          ++b;
+        }
+        hp.runs.insert(hp.runs.end(), rec, rec + 9);
+        a = b;
+      }
+      t0 = t1;
+    }
+    hp.grp_run_begin.push_back((int32_t)(hp.runs.size() / 9));
+  }
   hp.m2l_level_tgt.assign(X.nlevels + 1, 0);
   for (int32_t e : hp.m2l_tgt) hp.m2l_level_tgt[X.level[X.exp_cell[e]] + 1]++;
   for (int l = 0; l < X.nlevels; ++l) hp.m2l_level_tgt[l + 1] += hp.m2l_level_tgt[l];

@@ -43,7 +43,8 @@ EXPORTS = ["defmm_default_params", "defmm_plan_create", "defmm_plan_inspect_crea
            "defmm_workspace_create", "defmm_matvec", "defmm_workspace_destroy", "defmm_plan_destroy",
            "defmm_status_string", "defmm_last_error", "defmm_plan_geometry", "defmm_plan_export_tree",
            "defmm_plan_export_m2l", "defmm_plan_export_p2p", "defmm_workspace_export_expansions",
-           "defmm_workspace_set_timing", "defmm_workspace_pass_times", "defmm_pass_name",
+           "defmm_workspace_set_timing", "defmm_workspace_set_overlap", "defmm_workspace_pass_times",
+           "defmm_pass_name",
            "defmm_plan_pass_work"]
 
 _lib = None
@@ -75,6 +76,7 @@ def lib():
     L.defmm_plan_export_p2p.argtypes = [P, P, P, P]
     L.defmm_workspace_export_expansions.argtypes = [P, i32, i32, P, P, P, P]
     L.defmm_workspace_set_timing.argtypes = [P, i32]
+    L.defmm_workspace_set_overlap.argtypes = [P, i32]
     L.defmm_workspace_pass_times.argtypes = [P, P, P]
     L.defmm_pass_name.argtypes = [i32]
     L.defmm_pass_name.restype = ctypes.c_char_p
@@ -269,6 +271,9 @@ class Workspace:
 
     def set_timing(self, on: bool):
         _check(lib().defmm_workspace_set_timing(self.h, 1 if on else 0))
+
+    def set_overlap(self, on: bool):
+        _check(lib().defmm_workspace_set_overlap(self.h, 1 if on else 0))
 
     def pass_times(self):
         ms = np.zeros(NUM_PASSES)

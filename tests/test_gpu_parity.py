@@ -140,6 +140,35 @@ def test_repeatable_bitwise():
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
 
 
+def test_overlap_and_variants_are_bitwise_identical():
+    """The near field overlapped on a second stream or run in sequence, and the
+    three M2L variants (fused, sliced, source runs), all give the same bits
+    (each accumulation is owned by one thread in a fixed order... except the
+    Hadamard sums, whose order differs between variants: compare to rounding)."""
+    import os
+    defmm = _defmm()
+    X = W.sphere(20000, 19)
+    q = W.charges(20000, 20)
+    prm = dict(order_L=5, ncrit=32, precision=defmm.C64)
+    plan = defmm.Plan(X, None, 64.0, defmm.Params(**prm))
+    ws = defmm.Workspace(plan)
+    qt = torch.as_tensor(q, device="cuda").to(plan.cdtype)
+    a = ws.matvec(qt).cpu().numpy()
+    ws.set_overlap(False)
+    b = ws.matvec(qt).cpu().numpy()
+    assert np.array_equal(a, b)
+    outs = []
+    for v in ("0", "1", "2"):
+        os.environ["DEFMM_M2L_VARIANT"] = v
+        try:
+            pv = defmm.Plan(X, None, 64.0, defmm.Params(**prm))
+        finally:
+            del os.environ["DEFMM_M2L_VARIANT"]
+        outs.append(defmm.Workspace(pv).matvec(qt).cpu().numpy().astype(np.complex128))
+    for o in outs[1:]:
+        assert rel(o, outs[0]) < 1e-6
+
+
 def test_degenerate_inputs():
     defmm = _defmm()
     # coincident points: every pair falls under tau
