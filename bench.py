@@ -168,12 +168,14 @@ def main():
 
     plan64, ws64, setup64 = make(defmm.C64)
     charges64 = [torch.as_tensor(wl.charges(k, np.complex64), device="cuda") for k in range(nq)]
-    # production mode: near field overlapped with the far field, no per-pass events
+    # execution choices (M2L variant, near-field overlap) tuned on this workspace
+    tuned = ws64.autotune(charges64[0], reps=3)
+    # production mode: tuned choices, no per-pass events
     ms64, lat64, _ = time_matvecs(ws64, charges64, nsteps, args.warmup, timing=False)
     # the same matvecs in sequence with per-pass HIP events: each kernel's own duration
     ws64.set_overlap(False)
     ms_seq, _, passes = time_matvecs(ws64, charges64, nsteps, 1, timing=True)
-    ws64.set_overlap(True)
+    ws64.set_tuning(tuned["overlap"], tuned["p2p_waves_per_cu"], tuned["m2l_variant"])
     p64 = ws64.matvec(charges64[0]).cpu().numpy().astype(np.complex128)
     del charges64
 
@@ -187,13 +189,14 @@ def main():
         del a, b
     if args.c64_only:
         print(json.dumps({"value": round(wl.n / (ms64 / 1e3) / 1e6, 3), "ms_per_step": round(ms64, 4),
-                          "sequential_ms_per_step": round(ms_seq, 4),
+                          "sequential_ms_per_step": round(ms_seq, 4), "tuning": tuned,
                           "passes_ms_per_step": {defmm.pass_name(i): round(float(v) / nsteps, 4)
                                                  for i, v in enumerate(passes[0])}}), flush=True)
         return
 
     plan128, ws128, setup128 = make(defmm.C128)
     charges128 = [torch.as_tensor(wl.charges(k), device="cuda") for k in range(min(nq, 8))]
+    ws128.autotune(charges128[0], reps=2)
     ms128, lat128, _ = time_matvecs(ws128, charges128, max(args.c128_steps, 1), 2, timing=False)
     p128 = ws128.matvec(charges128[0]).cpu().numpy()
     del charges128
@@ -255,6 +258,7 @@ def main():
                  "p99_ms": round(float(np.percentile(lat128, 99)), 4)},
         "setup_s": {"c64": round(setup64, 3), "c128": round(setup128, 3)},
         "sequential_ms_per_step": round(ms_seq, 4),
+        "tuning": tuned,
         "passes_ms_per_step": {n: round(float(v), 4) for n, v in zip(names, per_step)},
         "stats": st,
         "roofline": roof,

@@ -150,6 +150,33 @@ defmm_status defmm_workspace_export_expansions(defmm_workspace* ws, int32_t whic
 #define DEFMM_NUM_PASSES 11
 defmm_status defmm_workspace_set_timing(defmm_workspace* ws, int32_t enable);
 
+/* Execution choices of a workspace (results are the same to rounding; the
+   near-field split never changes a bit):
+   overlap          1: near field on the workspace's own stream, concurrently
+                    with the far field; 0: every pass in sequence;
+   p2p_waves_per_cu persistent near-field workgroups (one wave) per compute
+                    unit when overlapped, 1..32;
+   m2l_variant      0: Hadamard fused with F2L per target; 1: frequency-sliced
+                    per target; 2: frequency-sliced per group of 8 targets
+                    merged by source (default);
+   ms               median matvec time measured by defmm_workspace_autotune. */
+typedef struct {
+  int32_t overlap;
+  int32_t p2p_waves_per_cu;
+  int32_t m2l_variant;
+  double ms;
+} defmm_tuning;
+
+/* Times the candidate execution choices on this workspace (each: one warm-up
+   and `reps` matvecs of q into p on hip_stream; host-synchronous) and keeps
+   the fastest: the M2L variant in sequence first, then the overlapped near
+   field with 2, 3, 4 and 6 waves per CU.  q and p as in defmm_matvec; p holds
+   a valid result afterwards.  chosen (optional) receives the choice. */
+defmm_status defmm_workspace_autotune(defmm_plan* plan, defmm_workspace* ws, const void* q, void* p,
+                                      void* hip_stream, int32_t reps, defmm_tuning* chosen);
+defmm_status defmm_workspace_get_tuning(const defmm_workspace* ws, defmm_tuning* out);
+defmm_status defmm_workspace_set_tuning(defmm_workspace* ws, const defmm_tuning* t);
+
 /* Overlap (default on): the near field (P2P) runs on a stream owned by the
    workspace, forked after the charge gather and joined before L2P, as a
    persistent kernel that leaves wave slots to the far field.  Off: every pass

@@ -4,7 +4,9 @@
 
 #include <cmath>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
+#include <vector>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -79,11 +81,6 @@ void upload_tree(DevPlan& P, DevTree& d, const Tree& t) {
 
 size_t csize(const DevPlan& P) { return P.precision == 0 ? 16 : 8; }
 
-// Row stride of the Fourier-domain arrays: (2L-1)^3 rounded up to 16 entries.
-int fourier_row(int L) {
-  int P3 = (2 * L - 1) * (2 * L - 1) * (2 * L - 1);
-  return ((P3 + 15) / 16) * 16;
-}
 
 }  // namespace
 
@@ -341,7 +338,7 @@ static size_t workspace_bytes(const DevPlan& P) {
   size_t cs = csize(P);
   int L3 = P.L * P.L * P.L, P3 = fourier_row(P.L);
   return cs * ((size_t)P.ny + (size_t)P.nx + (size_t)P.ty.nexp * L3 + (size_t)P.tx.nexp * L3 +
-               (size_t)P.n_m2f * P3 + (size_t)P.nwi * 64 + (P.m2l_variant >= 1 ? (size_t)P.n_m2l_tgt * P3 : 0));
+               (size_t)P.n_m2f * P3 + (size_t)P.nwi * 64 + (size_t)P.n_m2l_tgt * P3);
 }
 
 defmm_status defmm_plan_footprint(const defmm_plan* plan, size_t* resident, size_t* ws) {
@@ -385,6 +382,8 @@ defmm_status defmm_workspace_create(defmm_plan* plan, defmm_workspace** out) {
   if (!ws) return fail(DEFMM_ERR_OUT_OF_MEMORY, "host allocation failed");
   Workspace& W = ws->impl;
   W.plan = &P;
+  W.m2l_variant = P.m2l_variant;
+  W.p2p_waves = P.p2p_waves_per_cu;
   size_t cs = csize(P);
   int L3 = P.L * P.L * P.L, P3 = fourier_row(P.L);
   struct {
@@ -395,7 +394,7 @@ defmm_status defmm_workspace_create(defmm_plan* plan, defmm_workspace** out) {
               {&W.M, cs * (size_t)P.ty.nexp * L3},
               {&W.Lx, cs * (size_t)P.tx.nexp * L3},
               {&W.Mt, cs * (size_t)P.n_m2f * P3},
-              {&W.Lt, P.m2l_variant >= 1 ? cs * (size_t)P.n_m2l_tgt * P3 : 0},
+              {&W.Lt, cs * (size_t)P.n_m2l_tgt * P3},
               {&W.part, cs * (size_t)P.nwi * 64},
               {(void**)&W.queue, 8 * sizeof(int)}};
   for (auto& b : bufs) {
@@ -527,6 +526,88 @@ defmm_status defmm_workspace_set_overlap(defmm_workspace* ws, int32_t enable) {
   return DEFMM_OK;
 }
 
+defmm_status defmm_workspace_get_tuning(const defmm_workspace* ws, defmm_tuning* out) {
+  if (!ws || !out) return fail(DEFMM_ERR_INVALID_ARG, "NULL argument");
+  out->overlap = ws->impl.overlap ? 1 : 0;
+  out->p2p_waves_per_cu = ws->impl.p2p_waves;
+  out->m2l_variant = ws->impl.m2l_variant;
+  out->ms = 0.0;
+  return DEFMM_OK;
+}
+
+defmm_status defmm_workspace_set_tuning(defmm_workspace* ws, const defmm_tuning* t) {
+  if (!ws || !t) return fail(DEFMM_ERR_INVALID_ARG, "NULL argument");
+  if (t->p2p_waves_per_cu < 1 || t->p2p_waves_per_cu > 32 || t->m2l_variant < 0 || t->m2l_variant > 2)
+    return fail(DEFMM_ERR_INVALID_ARG, "tuning out of range");
+  ws->impl.overlap = t->overlap != 0;
+  ws->impl.p2p_waves = t->p2p_waves_per_cu;
+  ws->impl.m2l_variant = t->m2l_variant;
+  return DEFMM_OK;
+}
+
+defmm_status defmm_workspace_autotune(defmm_plan* plan, defmm_workspace* ws, const void* q, void* p,
+                                      void* hip_stream, int32_t reps, defmm_tuning* chosen) {
+  if (!plan || !ws) return fail(DEFMM_ERR_INVALID_ARG, "plan or workspace is NULL");
+  DevPlan& P = plan->impl;
+  Workspace& W = ws->impl;
+  if (P.host_only || W.plan != &P) return fail(DEFMM_ERR_INVALID_ARG, "workspace/plan mismatch");
+  if ((P.ny > 0 && !q) || (P.nx > 0 && !p)) return fail(DEFMM_ERR_INVALID_ARG, "q or p is NULL");
+  if (reps < 1) reps = 3;
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(DEFMM_ERR_DEVICE, "autotune events");
+  bool timing = W.timing;
+  W.timing = false;
+  auto measure = [&](const defmm_tuning& t, double* ms) -> hipError_t {
+    W.overlap = t.overlap != 0;
+    W.p2p_waves = t.p2p_waves_per_cu;
+    W.m2l_variant = t.m2l_variant;
+    hipError_t e = run_matvec(P, W, q, p, s);  // warm-up
+    std::vector<double> v;
+    for (int r = 0; r < reps && e == hipSuccess; ++r) {
+      e = hipEventRecord(e0, s);
+      if (e == hipSuccess) e = run_matvec(P, W, q, p, s);
+      if (e == hipSuccess) e = hipEventRecord(e1, s);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float f = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&f, e0, e1);
+      v.push_back(f);
+    }
+    if (e == hipSuccess) {
+      std::sort(v.begin(), v.end());
+      *ms = v[v.size() / 2];
+    }
+    return e;
+  };
+  defmm_tuning best{0, 8, 2, 1e30};
+  hipError_t err = hipSuccess;
+  // M2L variant, timed with every pass in sequence
+  for (int var : {2, 1}) {
+    defmm_tuning t{0, 8, var, 0.0};
+    err = measure(t, &t.ms);
+    if (err != hipSuccess) break;
+    if (t.ms < best.ms) best = t;
+  }
+  // near field overlapped with the far field, with a few wave budgets
+  for (int w : {2, 3, 4, 6}) {
+    if (err != hipSuccess) break;
+    defmm_tuning t{1, w, best.m2l_variant, 0.0};
+    err = measure(t, &t.ms);
+    if (err != hipSuccess) break;
+    if (t.ms < best.ms) best = t;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  W.timing = timing;
+  if (err != hipSuccess) return fail(DEFMM_ERR_DEVICE, std::string("autotune: ") + hipGetErrorString(err));
+  W.overlap = best.overlap != 0;
+  W.p2p_waves = best.p2p_waves_per_cu;
+  W.m2l_variant = best.m2l_variant;
+  if (chosen) *chosen = best;
+  return DEFMM_OK;
+}
+
 defmm_status defmm_workspace_pass_times(defmm_workspace* ws, double* pass_ms, int64_t* calls) {
   if (!ws) return fail(DEFMM_ERR_INVALID_ARG, "workspace is NULL");
   Workspace& W = ws->impl;
@@ -579,7 +660,8 @@ defmm_status defmm_plan_pass_work(const defmm_plan* plan, double* bytes, double*
   b[kPassM2F] = n_m2f * cs * (L3 + P3);
   f[kPassM2F] = n_m2f * 8 * (Pp * L * L * L + Pp * Pp * L * L + P3 * L);
   double f2l_flops = n_tgt * 8 * (Pp * Pp * L * Pp + Pp * L * L * Pp + L3 * Pp);
-  if (P.m2l_variant == 0) {
+  const int ws_variant = P.m2l_variant;  // accounting for the default (non-fused) variants
+  if (ws_variant == 0) {
     b[kPassM2L] = n_m2l * 2 * cs * P3 + n_tgt * cs * L3;
     f[kPassM2L] = n_m2l * 8 * P3 + f2l_flops;
   } else {

@@ -12,6 +12,16 @@
 
 namespace defmm {
 
+// Frequency slices of the M2L kernels (a multiple of 8: one set per XCD) and
+// the row stride of every Fourier-domain array: (2L-1)^3 rounded up to
+// 2 * slices entries, so a row splits into slices of an even number of
+// entries and each lane moves two complex values per load.
+__host__ __device__ constexpr int m2l_slices(int L) { return L <= 5 ? 8 : (L == 6 ? 16 : 32); }
+__host__ __device__ constexpr int fourier_row(int L) {
+  return (((2 * L - 1) * (2 * L - 1) * (2 * L - 1) + 2 * m2l_slices(L) - 1) / (2 * m2l_slices(L))) *
+         (2 * m2l_slices(L));
+}
+
 // Pass indices for timing and work accounting.
 enum Pass {
   kPassSetup = 0,   // charge gather, zeroing
@@ -53,9 +63,9 @@ struct LevelTable {  // per-level operator table on the device
 struct DevPlan {
   HostPlan host;   // kept for introspection and stats
   int L = 5, precision = 1;
-  int m2l_variant = 2;  // 0: fused per target, 1: sliced per target, 2: sliced per group of 8 (source runs)
+  int m2l_variant = 2;  // default for new workspaces (see Workspace::m2l_variant)
   int num_cu = 256;           // compute units of the device (hipDeviceProp)
-  int p2p_waves_per_cu = 2;   // persistent near-field workgroups (one wave each) per CU when overlapped
+  int p2p_waves_per_cu = 2;   // default for new workspaces (see Workspace::p2p_waves)
   double kappa = 0.0, D = 0.0, origin[3] = {0, 0, 0}, tau = 0.0;
   DevTree tx, ty;
   bool same = false;
@@ -101,6 +111,8 @@ struct Workspace {
   size_t bytes = 0;
   hipStream_t side = nullptr;   // near-field stream (default priority), forked per matvec
   bool overlap = true;
+  int p2p_waves = 2;     // persistent near-field workgroups (one wave) per CU when overlapped
+  int m2l_variant = 2;   // 0: fused per target, 1: sliced per target, 2: sliced per group of 8 (source runs)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;

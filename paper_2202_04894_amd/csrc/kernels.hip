@@ -84,11 +84,8 @@ __device__ __forceinline__ void lagrange(R t, R* w) {
 
 constexpr int round64(int x) { return ((x + 63) / 64) * 64; }
 
-// Row stride of every Fourier-domain array (spectra, M~, L~): P^3 rounded up
-// to a multiple of 16 complex values, so that a row splits into 8 slices of
-// an even number of entries and each lane moves two entries (16 B in
-// complex64) per load.  The padding entries are never read back.
-constexpr int row_stride(int P3) { return ((P3 + 15) / 16) * 16; }
+// Row stride of the Fourier-domain arrays (spectra, M~, L~): fourier_row(L);
+// the padding entries are never read back.
 
 // XCD-aware block order: the hardware deals consecutive workgroups to the 8
 // XCDs round-robin; remap so each XCD walks a contiguous range of items and
@@ -201,7 +198,7 @@ __global__ __launch_bounds__(256) void k_spectra(int64_t n, const int32_t* __res
   }
   const double scale = 1.0 / (double)P3;
   for (int i = tid; i < P3; i += blockDim.x)
-    S[o * row_stride(P3) + i] = {(R)(a[i].x * scale), (R)(a[i].y * scale)};
+    S[o * fourier_row(L) + i] = {(R)(a[i].x * scale), (R)(a[i].y * scale)};
 }
 
 // ------------------------------------------------------------------ P2M
@@ -361,7 +358,7 @@ __global__ __launch_bounds__(256) void k_m2f(int64_t n, const int32_t* __restric
     C2<R> s = {(R)0, (R)0};
 #pragma unroll
     for (int r = 0; r < L; ++r) cfma(s, c[xy + P * P * r], W[(zi * r) % P]);
-    Mt[item * row_stride(P3) + i] = s;
+    Mt[item * fourier_row(L) + i] = s;
   }
 }
 
@@ -390,8 +387,8 @@ __global__ __launch_bounds__(256) void k_m2l(int64_t ntgt, const int32_t* __rest
   int kb = begin[i], ke = begin[i + 1];
   for (int k = kb; k < ke; ++k) {
     const int2 pr = pairs[k];
-    const C2<R>* ms = Mt + (int64_t)pr.x * row_stride(P3);
-    const C2<R>* ds = S + (int64_t)pr.y * row_stride(P3);
+    const C2<R>* ms = Mt + (int64_t)pr.x * fourier_row(L);
+    const C2<R>* ds = S + (int64_t)pr.y * fourier_row(L);
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       int xi = tid + f * NT;
@@ -448,7 +445,7 @@ __global__ __launch_bounds__(64) void k_m2l_slice(int64_t ntgt, const int32_t* _
   // NSL slices (a multiple of 8): XCD j gets slices j, j+8, ...; the block
   // order walks all targets of one slice before the next on each XCD.
   // Each lane owns two consecutive frequencies of the slice.
-  constexpr int P = 2 * L - 1, P3 = P * P * P, P3R = row_stride(P3);
+  constexpr int P = 2 * L - 1, P3 = P * P * P, P3R = fourier_row(L);
   constexpr int SL = P3R / NSL, NP = SL / 2, NF = (NP + 63) / 64, U = 8;
   static_assert(SL % 2 == 0, "slices hold an even number of entries");
   const int64_t b = blockIdx.x;
@@ -523,7 +520,7 @@ __global__ __launch_bounds__(64) void k_m2l_runs(int64_t ngrp, const int32_t* __
                                                  const int32_t* __restrict__ run_begin, const int32_t* __restrict__ runs,
                                                  const C2<R>* __restrict__ Mt, const C2<R>* __restrict__ S,
                                                  C2<R>* __restrict__ Lt) {
-  constexpr int P = 2 * L - 1, P3 = P * P * P, P3R = row_stride(P3);
+  constexpr int P = 2 * L - 1, P3 = P * P * P, P3R = fourier_row(L);
   constexpr int SL = P3R / NSL, NP = SL / 2, NF = (NP + 63) / 64, G = 8;
   constexpr int U = sizeof(R) == 4 ? 2 : 1;  // runs per batch
   const int64_t b = blockIdx.x;
@@ -605,7 +602,7 @@ __global__ __launch_bounds__(256) void k_f2l(int64_t ntgt, const int32_t* __rest
   int64_t i = xcd_item(ntgt);
   if (i >= ntgt) return;
   int tid = threadIdx.x;
-  for (int j = tid; j < P3; j += NT) A[j] = Lt[i * row_stride(P3) + j];
+  for (int j = tid; j < P3; j += NT) A[j] = Lt[i * fourier_row(L) + j];
   if (tid < P) W[tid] = expi<R>(2.0 * M_PI * (double)tid / (double)P);
   __syncthreads();
   for (int j = tid; j < P * P * L; j += NT) {
@@ -1081,7 +1078,7 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
   tm.begin(kPassP2P, s2);
   if (P.nwi > 0) {
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s2, 8, W.queue);
-    const int wpc = (s2 != s) ? P.p2p_waves_per_cu : 8;  // alone: fill every wave slot
+    const int wpc = (s2 != s) ? W.p2p_waves : 8;  // alone: fill every wave slot
     const unsigned nb = (unsigned)std::min<int64_t>(P.nwi, (int64_t)P.num_cu * wpc);
     hipLaunchKernelGGL((k_p2p<R>), dim3(nb), dim3(64), 0, s2, P.nwi, W.queue, P.wi_blk, P.wi_seg_begin,
                        P.seg_first, P.seg_count, P.blk_first, P.blk_count, P.tx.soa, P.tx.n, P.ty.soa, P.ty.n,
@@ -1121,19 +1118,19 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
 
   tm.begin(kPassM2L);
   if (P.n_m2l_tgt > 0) {
-    if (P.m2l_variant == 0) {
+    if (W.m2l_variant == 0) {
       DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l<R, LL>), dim3(xcd_grid(P.n_m2l_tgt)), dim3(256), 0, s,
                                            P.n_m2l_tgt, P.m2l_tgt, P.m2l_begin, (const int2*)P.m2l_pair,
                                            (const C2<R>*)Mt, S, Lx));
     } else {
       C2<R>* Lt = (C2<R>*)W.Lt;
-      if (P.m2l_variant == 2) {
-        DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_runs<R, LL, 8>), dim3((unsigned)(8 * P.n_grp)), dim3(64), 0,
+      if (W.m2l_variant == 2) {
+        DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_runs<R, LL, m2l_slices(LL)>), dim3((unsigned)(m2l_slices(LL) * P.n_grp)), dim3(64), 0,
                                              s, P.n_grp, P.grp_tfirst, P.grp_tcount, P.grp_run_begin, P.runs,
                                              (const C2<R>*)Mt, S, Lt));
       } else {
         // one launch over all levels; 8 slices (one per XCD)
-        DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_slice<R, LL, 8>), dim3((unsigned)(8 * P.n_m2l_tgt)), dim3(64),
+        DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_slice<R, LL, m2l_slices(LL)>), dim3((unsigned)(m2l_slices(LL) * P.n_m2l_tgt)), dim3(64),
                                              0, s, P.n_m2l_tgt, P.m2l_begin, (const int2*)P.m2l_pair,
                                              (const C2<R>*)Mt, S, Lt));
       }

@@ -31,6 +31,14 @@ class _Params(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("m2l_mode", ctypes.c_int32), ("flags", ctypes.c_uint32)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("overlap", ctypes.c_int32), ("p2p_waves_per_cu", ctypes.c_int32), ("m2l_variant", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class _Stats(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("hf_levels", ctypes.c_int32), ("cells", ctypes.c_int64),
                 ("leaves", ctypes.c_int64), ("m2l_pairs", ctypes.c_int64),
@@ -44,6 +52,7 @@ EXPORTS = ["defmm_default_params", "defmm_plan_create", "defmm_plan_inspect_crea
            "defmm_status_string", "defmm_last_error", "defmm_plan_geometry", "defmm_plan_export_tree",
            "defmm_plan_export_m2l", "defmm_plan_export_p2p", "defmm_workspace_export_expansions",
            "defmm_workspace_set_timing", "defmm_workspace_set_overlap", "defmm_workspace_pass_times",
+           "defmm_workspace_autotune", "defmm_workspace_get_tuning", "defmm_workspace_set_tuning",
            "defmm_pass_name",
            "defmm_plan_pass_work"]
 
@@ -77,6 +86,9 @@ def lib():
     L.defmm_workspace_export_expansions.argtypes = [P, i32, i32, P, P, P, P]
     L.defmm_workspace_set_timing.argtypes = [P, i32]
     L.defmm_workspace_set_overlap.argtypes = [P, i32]
+    L.defmm_workspace_autotune.argtypes = [P, P, P, P, P, i32, P]
+    L.defmm_workspace_get_tuning.argtypes = [P, P]
+    L.defmm_workspace_set_tuning.argtypes = [P, P]
     L.defmm_workspace_pass_times.argtypes = [P, P, P]
     L.defmm_pass_name.argtypes = [i32]
     L.defmm_pass_name.restype = ctypes.c_char_p
@@ -236,6 +248,11 @@ class Plan:
         return b, f
 
 
+def torch_empty_like_out(plan, q):
+    import torch
+    return torch.empty(plan.nx, dtype=plan.cdtype, device=q.device)
+
+
 class Workspace:
     def __init__(self, plan: Plan):
         self.plan = plan
@@ -271,6 +288,26 @@ class Workspace:
 
     def set_timing(self, on: bool):
         _check(lib().defmm_workspace_set_timing(self.h, 1 if on else 0))
+
+    def autotune(self, q, reps=3, stream=None):
+        """Time the execution choices on charges q and keep the fastest."""
+        pl = self.plan
+        q = q.contiguous()
+        p = torch_empty_like_out(pl, q)
+        t = Tuning()
+        _check(lib().defmm_workspace_autotune(pl.h, self.h, ctypes.c_void_p(q.data_ptr()),
+                                              ctypes.c_void_p(p.data_ptr()), _stream_handle(stream), reps,
+                                              ctypes.byref(t)))
+        return t.as_dict()
+
+    def tuning(self):
+        t = Tuning()
+        _check(lib().defmm_workspace_get_tuning(self.h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, overlap=1, p2p_waves_per_cu=2, m2l_variant=2):
+        t = Tuning(overlap, p2p_waves_per_cu, m2l_variant, 0.0)
+        _check(lib().defmm_workspace_set_tuning(self.h, ctypes.byref(t)))
 
     def set_overlap(self, on: bool):
         _check(lib().defmm_workspace_set_overlap(self.h, 1 if on else 0))

@@ -169,6 +169,21 @@ def test_overlap_and_variants_are_bitwise_identical():
         assert rel(o, outs[0]) < 1e-6
 
 
+def test_autotune_keeps_a_valid_choice():
+    defmm = _defmm()
+    X = W.ellipsoid(30000, 23)
+    q = W.charges(30000, 24)
+    plan = defmm.Plan(X, None, 80.0, defmm.Params(order_L=4, ncrit=32, precision=defmm.C64))
+    ws = defmm.Workspace(plan)
+    qt = torch.as_tensor(q, device="cuda").to(plan.cdtype)
+    ref = ws.matvec(qt).cpu().numpy().astype(np.complex128)
+    t = ws.autotune(qt, reps=2)
+    assert t["m2l_variant"] in (1, 2) and t["overlap"] in (0, 1) and t["ms"] > 0
+    assert ws.tuning()["m2l_variant"] == t["m2l_variant"]
+    got = ws.matvec(qt).cpu().numpy().astype(np.complex128)
+    assert rel(got, ref) < 1e-6
+
+
 def test_degenerate_inputs():
     defmm = _defmm()
     # coincident points: every pair falls under tau
