@@ -26,8 +26,9 @@ HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 HBM_PASSES = {"setup", "p2m", "m2m", "m2f", "m2l", "f2l", "l2l", "p2p_reduce", "l2p", "scatter"}
+MFMA_PASSES = {"m2l_dense"}
 KERNEL_OF_PASS = {"m2l": "k_m2l_runs", "f2l": "k_f2l", "p2p": "k_p2p", "m2f": "k_m2f", "m2m": "k_m2m",
-                  "l2l": "k_l2l", "p2m": "k_p2m", "l2p": "k_l2p"}
+                  "l2l": "k_l2l", "p2m": "k_p2m", "l2p": "k_l2p", "m2l_dense": "k_m2l_dense"}
 
 
 def parse():
@@ -161,7 +162,8 @@ def main():
     def make(prec):
         t0 = time.perf_counter()
         plan = defmm.Plan(X, None, wl.kappa, defmm.Params(order_L=wl.L, ncrit=wl.ncrit, eta=eta,
-                                                            hf_threshold=hf, dir_refine=e0, precision=prec))
+                                                            hf_threshold=hf, dir_refine=e0, precision=prec,
+                                                            m2l_mode=defmm.M2L_AUTO))
         torch.cuda.synchronize()
         setup = time.perf_counter() - t0
         return plan, defmm.Workspace(plan), setup
@@ -175,7 +177,7 @@ def main():
     # the same matvecs in sequence with per-pass HIP events: each kernel's own duration
     ws64.set_overlap(False)
     ms_seq, _, passes = time_matvecs(ws64, charges64, nsteps, 1, timing=True)
-    ws64.set_tuning(tuned["overlap"], tuned["p2p_waves_per_cu"], tuned["m2l_variant"])
+    ws64.set_tuning(**tuned)
     p64 = ws64.matvec(charges64[0]).cpu().numpy().astype(np.complex128)
     del charges64
 
@@ -211,13 +213,19 @@ def main():
     # roofline of the dominant kernel, from per-pass HIP events over the timed region
     ms_pass, calls = passes
     names = [defmm.pass_name(i) for i in range(defmm.NUM_PASSES)]
-    bytes_, flops = plan64.pass_work()
+    bytes_, flops = ws64.pass_work()
     per_step = ms_pass / nsteps
     dom = int(np.argmax(per_step))
     dname = names[dom]
     t_launch = per_step[dom] / 1e3  # s per matvec for this pass
     kern = KERNEL_OF_PASS.get(dname, dname)
-    if dname in HBM_PASSES:
+    if dname == "m2l" and tuned["m2l_variant"] == 1:
+        kern = "k_m2l_slice"
+    if dname in MFMA_PASSES:
+        ach = flops[dom] / t_launch / 1e12
+        roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(ach / FP32_PEAK_TFLOPS, 4)}
+    elif dname in HBM_PASSES:
         ach = bytes_[dom] / t_launch / 1e9
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4)}

@@ -39,6 +39,15 @@ typedef enum {
                      spectrum precomputation and phase-argument reduction */
 } defmm_precision;
 
+/* How M2L is applied (Sec. 4.2.3 gives the Fourier form; the dense form applies
+   the same L^3 x L^3 interpolated kernel matrix per (level, offset) directly):
+     DEFMM_M2L_FFT    circulant embedding + FFT-diagonal product at every level;
+     DEFMM_M2L_DENSE  dense matrix-matrix products on the matrix cores at every
+                      level whose matrices fit (<= 2 GiB per level, 8 GiB in all),
+                      Fourier form elsewhere;
+     DEFMM_M2L_AUTO   the plan builds the dense matrices where they fit, the
+                      workspace starts on the Fourier form and
+                      defmm_workspace_autotune picks, level by level, the faster. */
 typedef enum { DEFMM_M2L_AUTO = 0, DEFMM_M2L_FFT = 1, DEFMM_M2L_DENSE = 2 } defmm_m2l_mode;
 
 #define DEFMM_SAME_POINTS 1u /* X and Y are the same set: one tree; q and p share its order */
@@ -69,7 +78,8 @@ typedef struct {
   int64_t eff_expansions;     /* effective (cell, direction) expansions, both trees */
   int64_t m2l_expansions;     /* expansions taking part in M2L (sources + targets) */
   int64_t unique_offsets;     /* distinct (level, offset) M2L spectra */
-  int32_t m2l_mode_per_level[32];
+  int32_t m2l_mode_per_level[32]; /* DEFMM_M2L_DENSE where the plan holds dense M2L
+                                     matrices for that level, else DEFMM_M2L_FFT */
 } defmm_stats;
 
 /* Writes the default parameters: L=5, ncrit=64, eta=1, hf_threshold=2,
@@ -147,7 +157,7 @@ defmm_status defmm_workspace_export_expansions(defmm_workspace* ws, int32_t whic
 /* Per-pass device time.  When enabled, matvec records HIP events around each pass
    on its stream; pass_ms[i] accumulates milliseconds over the matvecs since the
    last reset, calls[i] counts launches.  Pass names: defmm_pass_name(i). */
-#define DEFMM_NUM_PASSES 11
+#define DEFMM_NUM_PASSES 12
 defmm_status defmm_workspace_set_timing(defmm_workspace* ws, int32_t enable);
 
 /* Execution choices of a workspace (results are the same to rounding; the
@@ -159,18 +169,22 @@ defmm_status defmm_workspace_set_timing(defmm_workspace* ws, int32_t enable);
    m2l_variant      0: Hadamard fused with F2L per target; 1: frequency-sliced
                     per target; 2: frequency-sliced per group of 8 targets
                     merged by source (default);
+   dense_levels     bit l set: level l runs the dense MFMA M2L (only levels whose
+                    dense matrices the plan built: DEFMM_M2L_AUTO or _DENSE);
    ms               median matvec time measured by defmm_workspace_autotune. */
 typedef struct {
   int32_t overlap;
   int32_t p2p_waves_per_cu;
   int32_t m2l_variant;
+  uint32_t dense_levels;
   double ms;
 } defmm_tuning;
 
 /* Times the candidate execution choices on this workspace (each: one warm-up
    and `reps` matvecs of q into p on hip_stream; host-synchronous) and keeps
-   the fastest: the M2L variant in sequence first, then the overlapped near
-   field with 2, 3, 4 and 6 waves per CU.  q and p as in defmm_matvec; p holds
+   the fastest: the Fourier-path M2L variant in sequence first, then, level by
+   level, the dense MFMA M2L where the plan holds its matrices, then the
+   overlapped near field with 2, 3, 4 and 6 waves per CU.  q and p as in defmm_matvec; p holds
    a valid result afterwards.  chosen (optional) receives the choice. */
 defmm_status defmm_workspace_autotune(defmm_plan* plan, defmm_workspace* ws, const void* q, void* p,
                                       void* hip_stream, int32_t reps, defmm_tuning* chosen);
@@ -186,9 +200,15 @@ defmm_status defmm_workspace_set_overlap(defmm_workspace* ws, int32_t enable);
 defmm_status defmm_workspace_pass_times(defmm_workspace* ws, double* pass_ms, int64_t* calls);
 const char* defmm_pass_name(int32_t i);
 
-/* Algorithmic work of one matvec per pass (bytes or flops as documented in the
-   design notes): work[i] for pass i. */
-defmm_status defmm_plan_pass_work(const defmm_plan* plan, double* bytes, double* flops);
+/* Algorithmic work of one matvec per pass under the workspace's current
+   execution choices (which levels run the dense M2L, which Fourier variant):
+   bytes[i] = compulsory HBM bytes of pass i (each input read once, each output
+   written once; e.g. Fourier M2L: per pair one spectrum row and one source row
+   of (2L-1)^3 values, per target one row written; dense M2L: each level-local
+   matrix, source and target expansion once), flops[i] = real floating-point
+   operations (a complex multiply-add counts 8).  Either pointer may be NULL;
+   each holds DEFMM_NUM_PASSES entries. */
+defmm_status defmm_workspace_pass_work(const defmm_workspace* ws, double* bytes, double* flops);
 
 #ifdef __cplusplus
 }

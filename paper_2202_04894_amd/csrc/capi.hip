@@ -89,7 +89,7 @@ DevPlan::~DevPlan() {
   for (void* p : allocs) hipFree(p);
 }
 Workspace::~Workspace() {
-  for (void* p : {qs, ps, M, Lx, Mt, Lt, part, (void*)queue})
+  for (void* p : {qs, ps, M, Lx, Mt, Lt, part, (void*)queue, slots})
     if (p) hipFree(p);
   for (hipEvent_t e : ev_pool) hipEventDestroy(e);
   if (ev_fork) hipEventDestroy(ev_fork);
@@ -142,8 +142,7 @@ static defmm_status validate(const double* X, int64_t nx, const double* Y, int64
   if (prm->dir_refine < 0 || prm->dir_refine > 4) return fail(DEFMM_ERR_INVALID_ARG, "dir_refine outside 0..4");
   if (prm->precision != DEFMM_C64 && prm->precision != DEFMM_C128)
     return fail(DEFMM_ERR_INVALID_ARG, "unknown precision");
-  if (prm->m2l_mode == DEFMM_M2L_DENSE) return fail(DEFMM_ERR_UNSUPPORTED, "dense M2L is not built");
-  if (prm->m2l_mode != DEFMM_M2L_AUTO && prm->m2l_mode != DEFMM_M2L_FFT)
+  if (prm->m2l_mode != DEFMM_M2L_AUTO && prm->m2l_mode != DEFMM_M2L_FFT && prm->m2l_mode != DEFMM_M2L_DENSE)
     return fail(DEFMM_ERR_INVALID_ARG, "unknown m2l_mode");
   return DEFMM_OK;
 }
@@ -265,6 +264,44 @@ defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int
     P.grp_run_begin = upload(P, H.grp_run_begin);
     P.runs = upload(P, H.runs);
     P.n_grp = (int64_t)H.grp_tfirst.size();
+    P.lvl_grp.assign(H.lvl_grp.begin(), H.lvl_grp.end());
+    P.lvl_m2f.assign(H.lvl_m2f.begin(), H.lvl_m2f.end());
+    P.m2l_level_tgt.assign(H.m2l_level_tgt.begin(), H.m2l_level_tgt.end());
+    // dense M2L tables: index lists always, K matrices where they fit
+    P.dns_src = upload(P, H.dns_src);
+    P.dns_slot = upload(P, H.dns_slot);
+    P.dns_tile_off = upload(P, H.dns_tile_off);
+    P.dns_tile_first = upload(P, H.dns_tile_first);
+    P.dns_tile_cnt = upload(P, H.dns_tile_cnt);
+    P.dns_off_begin.assign(H.dns_off_begin.begin(), H.dns_off_begin.end());
+    P.dns_pair_begin.assign(H.dns_pair_begin.begin(), H.dns_pair_begin.end());
+    P.dns_tile_begin.assign(H.dns_tile_begin.begin(), H.dns_tile_begin.end());
+    {
+      int nl = (int)P.lvl_m2f.size() - 1;
+      P.dense_K.assign(nl, nullptr);
+      P.dense_ok.assign(nl, 0);
+      P.m2l_mode = prm->m2l_mode;
+      if (prm->m2l_mode != DEFMM_M2L_FFT) {
+        const size_t per_off = (size_t)dense_pad(P.L) * dense_pad(P.L) * csize(P);
+        size_t total = 0;
+        for (int l = 0; l < nl; ++l) {
+          int64_t noff = P.dns_off_begin[l + 1] - P.dns_off_begin[l];
+          if (noff == 0) continue;
+          size_t bytes = (size_t)noff * per_off;
+          if (bytes > (2ull << 30) || total + bytes > (8ull << 30)) continue;
+          std::vector<int32_t> dl(3 * noff);
+          for (int64_t i = 0; i < noff; ++i)
+            for (int d = 0; d < 3; ++d) dl[3 * i + d] = H.offsets[H.dns_off[P.dns_off_begin[l] + i]].d[d];
+          P.dense_K[l] = dalloc(P, bytes);
+          int32_t* ddl = upload(P, dl);
+          check(compute_dense_K(P, l, ddl, s), "dense K launch");
+          P.dense_ok[l] = 1;
+          total += bytes;
+          P.dense_slots_max = std::max<int64_t>(P.dense_slots_max, P.dns_pair_begin[l + 1] - P.dns_pair_begin[l]);
+        }
+        check(hipStreamSynchronize(s), "dense K");
+      }
+    }
     if (const char* e = std::getenv("DEFMM_M2L_VARIANT")) {
       int v = std::atoi(e);
       if (v >= 0 && v <= 2) P.m2l_variant = v;
@@ -369,7 +406,9 @@ defmm_status defmm_plan_stats(const defmm_plan* plan, defmm_stats* out) {
   out->eff_expansions = H.tx.nexp() + (P.same ? 0 : H.ty->nexp());
   out->m2l_expansions = (int64_t)H.m2f_exp.size() + (int64_t)H.m2l_tgt.size();
   out->unique_offsets = (int64_t)H.offsets.size();
-  for (int l = 0; l < 32; ++l) out->m2l_mode_per_level[l] = DEFMM_M2L_FFT;
+  for (int l = 0; l < 32; ++l)
+    out->m2l_mode_per_level[l] =
+        (l < (int)P.dense_ok.size() && P.dense_ok[l]) ? DEFMM_M2L_DENSE : DEFMM_M2L_FFT;
   return DEFMM_OK;
 }
 
@@ -384,6 +423,9 @@ defmm_status defmm_workspace_create(defmm_plan* plan, defmm_workspace** out) {
   W.plan = &P;
   W.m2l_variant = P.m2l_variant;
   W.p2p_waves = P.p2p_waves_per_cu;
+  W.dense_level.assign(P.dense_ok.size(), 0);
+  if (P.m2l_mode == DEFMM_M2L_DENSE)
+    for (size_t l = 0; l < P.dense_ok.size(); ++l) W.dense_level[l] = P.dense_ok[l];
   size_t cs = csize(P);
   int L3 = P.L * P.L * P.L, P3 = fourier_row(P.L);
   struct {
@@ -396,7 +438,8 @@ defmm_status defmm_workspace_create(defmm_plan* plan, defmm_workspace** out) {
               {&W.Mt, cs * (size_t)P.n_m2f * P3},
               {&W.Lt, cs * (size_t)P.n_m2l_tgt * P3},
               {&W.part, cs * (size_t)P.nwi * 64},
-              {(void**)&W.queue, 8 * sizeof(int)}};
+              {(void**)&W.queue, 8 * sizeof(int)},
+              {&W.slots, cs * (size_t)P.dense_slots_max * L3}};
   for (auto& b : bufs) {
     if (b.n == 0) continue;
     hipError_t e = hipMalloc(b.p, b.n);
@@ -531,6 +574,9 @@ defmm_status defmm_workspace_get_tuning(const defmm_workspace* ws, defmm_tuning*
   out->overlap = ws->impl.overlap ? 1 : 0;
   out->p2p_waves_per_cu = ws->impl.p2p_waves;
   out->m2l_variant = ws->impl.m2l_variant;
+  out->dense_levels = 0;
+  for (size_t l = 0; l < ws->impl.dense_level.size() && l < 32; ++l)
+    if (ws->impl.dense_level[l]) out->dense_levels |= 1u << l;
   out->ms = 0.0;
   return DEFMM_OK;
 }
@@ -542,6 +588,9 @@ defmm_status defmm_workspace_set_tuning(defmm_workspace* ws, const defmm_tuning*
   ws->impl.overlap = t->overlap != 0;
   ws->impl.p2p_waves = t->p2p_waves_per_cu;
   ws->impl.m2l_variant = t->m2l_variant;
+  const DevPlan& P = *ws->impl.plan;
+  for (size_t l = 0; l < ws->impl.dense_level.size(); ++l)
+    ws->impl.dense_level[l] = (l < 32 && (t->dense_levels >> l) & 1u && P.dense_ok[l]) ? 1 : 0;
   return DEFMM_OK;
 }
 
@@ -559,10 +608,15 @@ defmm_status defmm_workspace_autotune(defmm_plan* plan, defmm_workspace* ws, con
     return fail(DEFMM_ERR_DEVICE, "autotune events");
   bool timing = W.timing;
   W.timing = false;
-  auto measure = [&](const defmm_tuning& t, double* ms) -> hipError_t {
+  auto apply = [&](const defmm_tuning& t) {
     W.overlap = t.overlap != 0;
     W.p2p_waves = t.p2p_waves_per_cu;
     W.m2l_variant = t.m2l_variant;
+    for (size_t l = 0; l < W.dense_level.size(); ++l)
+      W.dense_level[l] = (l < 32 && (t.dense_levels >> l) & 1u && P.dense_ok[l]) ? 1 : 0;
+  };
+  auto measure = [&](const defmm_tuning& t, double* ms) -> hipError_t {
+    apply(t);
     hipError_t e = run_matvec(P, W, q, p, s);  // warm-up
     std::vector<double> v;
     for (int r = 0; r < reps && e == hipSuccess; ++r) {
@@ -580,11 +634,19 @@ defmm_status defmm_workspace_autotune(defmm_plan* plan, defmm_workspace* ws, con
     }
     return e;
   };
-  defmm_tuning best{0, 8, 2, 1e30};
+  defmm_tuning best{0, 8, 2, 0u, 1e30};
   hipError_t err = hipSuccess;
   // M2L variant, timed with every pass in sequence
   for (int var : {2, 1}) {
-    defmm_tuning t{0, 8, var, 0.0};
+    defmm_tuning t{0, 8, var, 0u, 0.0};
+    err = measure(t, &t.ms);
+    if (err != hipSuccess) break;
+    if (t.ms < best.ms) best = t;
+  }
+  // per level: dense MFMA M2L instead of the Fourier path where it is faster
+  for (size_t l = 0; l < P.dense_ok.size() && l < 32 && err == hipSuccess; ++l) {
+    if (!P.dense_ok[l]) continue;
+    defmm_tuning t{0, 8, best.m2l_variant, best.dense_levels | (1u << l), 0.0};
     err = measure(t, &t.ms);
     if (err != hipSuccess) break;
     if (t.ms < best.ms) best = t;
@@ -592,7 +654,7 @@ defmm_status defmm_workspace_autotune(defmm_plan* plan, defmm_workspace* ws, con
   // near field overlapped with the far field, with a few wave budgets
   for (int w : {2, 3, 4, 6}) {
     if (err != hipSuccess) break;
-    defmm_tuning t{1, w, best.m2l_variant, 0.0};
+    defmm_tuning t{1, w, best.m2l_variant, best.dense_levels, 0.0};
     err = measure(t, &t.ms);
     if (err != hipSuccess) break;
     if (t.ms < best.ms) best = t;
@@ -601,9 +663,7 @@ defmm_status defmm_workspace_autotune(defmm_plan* plan, defmm_workspace* ws, con
   hipEventDestroy(e1);
   W.timing = timing;
   if (err != hipSuccess) return fail(DEFMM_ERR_DEVICE, std::string("autotune: ") + hipGetErrorString(err));
-  W.overlap = best.overlap != 0;
-  W.p2p_waves = best.p2p_waves_per_cu;
-  W.m2l_variant = best.m2l_variant;
+  apply(best);
   if (chosen) *chosen = best;
   return DEFMM_OK;
 }
@@ -633,14 +693,15 @@ defmm_status defmm_workspace_pass_times(defmm_workspace* ws, double* pass_ms, in
 
 const char* defmm_pass_name(int32_t i) {
   static const char* names[kNumPasses] = {"setup", "p2m", "m2m", "m2f", "m2l", "l2l", "p2p", "p2p_reduce",
-                                          "l2p", "scatter", "f2l"};
+                                          "l2p", "scatter", "f2l", "m2l_dense"};
   if (i < 0 || i >= kNumPasses) return "";
   return names[i];
 }
 
-defmm_status defmm_plan_pass_work(const defmm_plan* plan, double* bytes, double* flops) {
-  if (!plan) return fail(DEFMM_ERR_INVALID_ARG, "plan is NULL");
-  const DevPlan& P = plan->impl;
+defmm_status defmm_workspace_pass_work(const defmm_workspace* ws, double* bytes, double* flops) {
+  if (!ws) return fail(DEFMM_ERR_INVALID_ARG, "workspace is NULL");
+  const Workspace& W = ws->impl;
+  const DevPlan& P = *W.plan;
   const HostPlan& H = P.host;
   double cs = (double)csize(P);
   double L = P.L, Pp = 2 * P.L - 1, L3 = L * L * L, P3 = Pp * Pp * Pp;
@@ -656,19 +717,32 @@ defmm_status defmm_plan_pass_work(const defmm_plan* plan, double* bytes, double*
     for (int32_t c : v) nm2m_child += c >= 0;
   b[kPassM2M] = (nm2m + nm2m_child) * cs * L3;
   f[kPassM2M] = nm2m_child * 8 * (3 * L3 * L + 2 * L3);
-  double n_m2f = (double)H.m2f_exp.size(), n_m2l = (double)H.m2l_src.size(), n_tgt = (double)H.m2l_tgt.size();
-  b[kPassM2F] = n_m2f * cs * (L3 + P3);
-  f[kPassM2F] = n_m2f * 8 * (Pp * L * L * L + Pp * Pp * L * L + P3 * L);
-  double f2l_flops = n_tgt * 8 * (Pp * Pp * L * Pp + Pp * L * L * Pp + L3 * Pp);
-  const int ws_variant = P.m2l_variant;  // accounting for the default (non-fused) variants
-  if (ws_variant == 0) {
-    b[kPassM2L] = n_m2l * 2 * cs * P3 + n_tgt * cs * L3;
-    f[kPassM2L] = n_m2l * 8 * P3 + f2l_flops;
-  } else {
-    b[kPassM2L] = n_m2l * 2 * cs * P3 + n_tgt * cs * P3;
-    f[kPassM2L] = n_m2l * 8 * P3;
-    b[kPassF2L] = n_tgt * cs * (P3 + L3);
-    f[kPassF2L] = f2l_flops;
+  const double f2l_per_tgt = 8 * (Pp * Pp * L * Pp + Pp * L * L * Pp + L3 * Pp);
+  const double m2f_per_row = 8 * (Pp * L * L * L + Pp * Pp * L * L + P3 * L);
+  const int nlev = (int)H.lvl_m2f.size() - 1;
+  for (int l = 0; l < nlev; ++l) {
+    const double n_src = (double)(H.lvl_m2f[l + 1] - H.lvl_m2f[l]);
+    const int64_t tb = H.m2l_level_tgt[l], te = H.m2l_level_tgt[l + 1];
+    const double n_tgt = (double)(te - tb);
+    const double n_pair = (double)(H.m2l_begin[te] - H.m2l_begin[tb]);
+    const bool dense = l < (int)W.dense_level.size() && W.dense_level[l] && P.dense_ok[l];
+    if (dense) {
+      const double n_off = (double)(H.dns_off_begin[l + 1] - H.dns_off_begin[l]);
+      b[kPassM2LDense] += n_off * L3 * L3 * cs + (n_src + n_tgt) * L3 * cs;
+      f[kPassM2LDense] += n_pair * 8 * L3 * L3;
+      continue;
+    }
+    b[kPassM2F] += n_src * cs * (L3 + P3);
+    f[kPassM2F] += n_src * m2f_per_row;
+    if (W.m2l_variant == 0) {
+      b[kPassM2L] += n_pair * 2 * cs * P3 + n_tgt * cs * L3;
+      f[kPassM2L] += n_pair * 8 * P3 + n_tgt * f2l_per_tgt;
+    } else {
+      b[kPassM2L] += n_pair * 2 * cs * P3 + n_tgt * cs * P3;
+      f[kPassM2L] += n_pair * 8 * P3;
+      b[kPassF2L] += n_tgt * cs * (P3 + L3);
+      f[kPassF2L] += n_tgt * f2l_per_tgt;
+    }
   }
   double nl2l = 0;
   for (const auto& v : H.l2l_par) nl2l += (double)v.size();

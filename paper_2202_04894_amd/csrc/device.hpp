@@ -22,6 +22,9 @@ __host__ __device__ constexpr int fourier_row(int L) {
          (2 * m2l_slices(L));
 }
 
+// Dense M2L: L^3 padded to a multiple of 16 (the MFMA tile edge).
+__host__ __device__ constexpr int dense_pad(int L) { return ((L * L * L + 15) / 16) * 16; }
+
 // Pass indices for timing and work accounting.
 enum Pass {
   kPassSetup = 0,   // charge gather, zeroing
@@ -35,7 +38,8 @@ enum Pass {
   kPassL2P = 8,
   kPassScatter = 9,
   kPassF2L = 10,    // separate F2L when the M2L runs frequency-sliced
-  kNumPasses = 11
+  kPassM2LDense = 11,  // dense MFMA M2L (levels that run it) and its per-target sum
+  kNumPasses = 12
 };
 
 struct DevTree {
@@ -83,6 +87,15 @@ struct DevPlan {
   std::vector<int64_t> m2l_level_tgt;  // target range per level (host copy)
   int32_t *grp_tfirst = nullptr, *grp_tcount = nullptr, *grp_run_begin = nullptr, *runs = nullptr;
   int64_t n_grp = 0;
+  std::vector<int64_t> lvl_grp, lvl_m2f;  // per level: group range, Fourier-row range
+  // dense M2L (per level; K tables only where they fit, see dense_ok)
+  int32_t *dns_src = nullptr, *dns_slot = nullptr, *dns_tile_off = nullptr, *dns_tile_first = nullptr,
+          *dns_tile_cnt = nullptr;
+  std::vector<int64_t> dns_off_begin, dns_pair_begin, dns_tile_begin;
+  std::vector<void*> dense_K;        // per level: n_off_l x dense_pad^2 complex (transposed), or null
+  std::vector<char> dense_ok;        // per level: K built
+  int64_t dense_slots_max = 0;       // max pairs of a dense-capable level
+  int m2l_mode = 1;                  // defmm_m2l_mode the plan was built with
   std::vector<LevelTable> l2l;  // a = child exps, b = CSR begin (n+1), c = parent exps, oct
   int32_t *l2p_cell = nullptr, *l2p_first = nullptr, *l2p_count = nullptr;
   int64_t n_l2p = 0;
@@ -113,6 +126,8 @@ struct Workspace {
   bool overlap = true;
   int p2p_waves = 2;     // persistent near-field workgroups (one wave) per CU when overlapped
   int m2l_variant = 2;   // 0: fused per target, 1: sliced per target, 2: sliced per group of 8 (source runs)
+  std::vector<char> dense_level;  // per level: use the dense MFMA M2L
+  void* slots = nullptr;          // dense M2L per-pair results, dense_slots_max x L^3
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -126,6 +141,7 @@ struct Workspace {
 
 // Kernel launchers (kernels.hip).
 hipError_t compute_spectra(DevPlan& P, const int32_t* d_lev, const int32_t* d_delta, hipStream_t s);
+hipError_t compute_dense_K(DevPlan& P, int level, const int32_t* d_delta, hipStream_t s);
 hipError_t run_matvec(DevPlan& P, Workspace& W, const void* q, void* p, hipStream_t s);
 
 }  // namespace defmm

@@ -630,6 +630,142 @@ __global__ __launch_bounds__(256) void k_f2l(int64_t ntgt, const int32_t* __rest
   }
 }
 
+// ------------------------------------------------------------------ dense M2L
+// The alternative M2L (vector stacking of Sec. 4.2.2): all pairs sharing an
+// offset share one dense matrix K[k][l] = G(x_k - y_l) (Sec. 2.2, M2L by
+// definition), so tiles of 16 such pairs form a product [2L^3 x 2L^3] x
+// [2L^3 x 16] in real arithmetic ([Re K, -Im K; Im K, Re K] times [Re M; Im M])
+// on the matrix cores.  Results go to one slot per pair and are summed per
+// target in list order (deterministic).
+
+// K of each level-local offset, stored transposed (column-major, so the rows
+// of an MFMA A-fragment are contiguous), zero-padded to dense_pad(L).
+template <typename R, int L>
+__global__ __launch_bounds__(256) void k_dense_K(int64_t n, const int32_t* __restrict__ delta, double kappa,
+                                                 double h, C2<R>* __restrict__ Kt) {
+  constexpr int L3 = L * L * L, NP = dense_pad(L);
+  int64_t o = blockIdx.x;
+  if (o >= n) return;
+  const double dx = delta[3 * o], dy = delta[3 * o + 1], dz = delta[3 * o + 2];
+  const double s = h / (double)(L - 1);
+  for (int i = threadIdx.x; i < NP * NP; i += 256) {
+    int c = i / NP, r = i % NP;  // Kt[c][r] = K[r][c]
+    C2<R> v = {(R)0, (R)0};
+    if (r < L3 && c < L3) {
+      int rx = r % L, ry = (r / L) % L, rz = r / (L * L);
+      int cx = c % L, cy = (c / L) % L, cz = c / (L * L);
+      double z0 = h * dx + s * (double)(rx - cx), z1 = h * dy + s * (double)(ry - cy), z2 = h * dz + s * (double)(rz - cz);
+      double rr = sqrt(z0 * z0 + z1 * z1 + z2 * z2);
+      double sn, cs;
+      sincos(kappa * rr, &sn, &cs);
+      double g = 1.0 / (4.0 * M_PI * rr);
+      v = {(R)(cs * g), (R)(sn * g)};
+    }
+    Kt[o * NP * NP + i] = v;
+  }
+}
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename R>
+struct Mfma;
+template <>
+struct Mfma<float> {
+  typedef f32x4 acc_t;
+  __device__ static acc_t op(float a, float b, acc_t c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+};
+template <>
+struct Mfma<double> {
+  typedef f64x4 acc_t;
+  __device__ static acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+// One wave per tile.  16x16x4 MFMA fragments: A[m][k] in lane m + 16k,
+// B[k][n] in lane n + 16k; the result D[m][n] sits in lane n + 16 (m / 4),
+// element m % 4 for the f32 instruction and in lane n + 16 (m % 4), element
+// m / 4 for the f64 one (both checked on the device).
+template <typename R, int L>
+__global__ __launch_bounds__(64) void k_m2l_dense(int64_t ntile, const int32_t* __restrict__ t_off,
+                                                  const int32_t* __restrict__ t_first,
+                                                  const int32_t* __restrict__ t_cnt, const int32_t* __restrict__ src,
+                                                  const int32_t* __restrict__ slot, const C2<R>* __restrict__ Kt,
+                                                  const C2<R>* __restrict__ M, C2<R>* __restrict__ slots) {
+  constexpr int L3 = L * L * L, NP = dense_pad(L), RR = 2 * NP, NT = RR / 16, KS = RR / 4;
+  typedef typename Mfma<R>::acc_t acc_t;
+  __shared__ R Bm[RR][17];
+  const int64_t tile = blockIdx.x;
+  if (tile >= ntile) return;
+  const int lane = threadIdx.x;
+  const int64_t o = t_off[tile];
+  const int f = t_first[tile], cnt = t_cnt[tile];
+  for (int i = lane; i < 16 * NP; i += 64) {
+    int n = i / NP, k = i % NP;
+    C2<R> v = {(R)0, (R)0};
+    if (n < cnt && k < L3) v = M[(int64_t)src[f + n] * L3 + k];
+    Bm[k][n] = v.x;
+    Bm[NP + k][n] = v.y;
+  }
+  __syncthreads();
+  acc_t acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = acc_t{0, 0, 0, 0};
+  const C2<R>* Ko = Kt + o * NP * NP;
+  const int mrow = lane % 16, kq = lane / 16;
+  for (int st = 0; st < KS; ++st) {
+    const int kk = 4 * st + kq;  // real column
+    const R b = Bm[kk][mrow];
+    const bool ycol = kk >= NP;
+    const C2<R>* col = Ko + (int64_t)(ycol ? kk - NP : kk) * NP;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const bool imrow = t >= NT / 2;  // real rows NP.. hold imaginary parts
+      const int r = (imrow ? t - NT / 2 : t) * 16 + mrow;
+      const C2<R> kv = col[r];
+      R a;
+      if (!imrow) a = ycol ? -kv.y : kv.x;
+      else a = ycol ? kv.x : kv.y;
+      acc[t] = Mfma<R>::op(a, b, acc[t]);
+    }
+  }
+  const int n = lane % 16;
+  if (n < cnt) {
+    const int64_t sl = slot[f + n];
+    R* out = reinterpret_cast<R*>(slots + sl * L3);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const bool imrow = t >= NT / 2;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int m = sizeof(R) == 4 ? 4 * (lane / 16) + j : 4 * j + lane / 16;
+        int r = (imrow ? t - NT / 2 : t) * 16 + m;
+        if (r < L3) out[2 * r + (imrow ? 1 : 0)] = acc[t][j];
+      }
+    }
+  }
+}
+
+// L_t = sum over the target's pairs of the dense slots, in list order.
+template <typename R, int L>
+__global__ __launch_bounds__(128) void k_dense_reduce(int64_t ntgt, const int32_t* __restrict__ tgt,
+                                                      const int32_t* __restrict__ begin, int32_t kbase,
+                                                      const C2<R>* __restrict__ slots, C2<R>* __restrict__ Lx) {
+  constexpr int L3 = L * L * L;
+  int64_t i = blockIdx.x;
+  if (i >= ntgt) return;
+  for (int k = threadIdx.x; k < L3; k += 128) {
+    C2<R> acc = {(R)0, (R)0};
+    for (int p = begin[i]; p < begin[i + 1]; ++p) {
+      C2<R> v = slots[(int64_t)(p - kbase) * L3 + k];
+      acc.x += v.x;
+      acc.y += v.y;
+    }
+    Lx[(int64_t)tgt[i] * L3 + k] = acc;
+  }
+}
+
 // ------------------------------------------------------------------ L2L
 // L_{t'}^u(x'_h) += sum over father expansions v with Father(v) = u of
 // exp(ik<x'_h - a_t, v>) (x)A_b^T (exp(-ik<x_k - a_t, v>) L_t^v).
@@ -997,6 +1133,20 @@ static hipError_t spectra_impl(DevPlan& P, const int32_t* lev, const int32_t* de
   return hipGetLastError();
 }
 
+template <typename R>
+static hipError_t dense_K_impl(DevPlan& P, int l, const int32_t* delta, hipStream_t s) {
+  int64_t n = P.dns_off_begin[l + 1] - P.dns_off_begin[l];
+  if (n == 0) return hipSuccess;
+  double h = std::ldexp(P.D, -l);
+  DEFMM_L_SWITCH(P.L, hipLaunchKernelGGL((k_dense_K<R, LL>), dim3((unsigned)n), dim3(256), 0, s, n, delta, P.kappa,
+                                         h, (C2<R>*)P.dense_K[l]));
+  return hipGetLastError();
+}
+
+hipError_t compute_dense_K(DevPlan& P, int level, const int32_t* delta, hipStream_t s) {
+  return P.precision == 0 ? dense_K_impl<double>(P, level, delta, s) : dense_K_impl<float>(P, level, delta, s);
+}
+
 hipError_t compute_spectra(DevPlan& P, const int32_t* lev, const int32_t* delta, hipStream_t s) {
   return P.precision == 0 ? spectra_impl<double>(P, lev, delta, s) : spectra_impl<float>(P, lev, delta, s);
 }
@@ -1110,36 +1260,66 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
   }
   tm.end();
 
+  // levels whose M2L runs dense skip M2F/F2L; the others use the Fourier path
+  const int nlev = (int)P.lvl_m2f.size() - 1;
+  auto is_dense = [&](int l) {
+    return l < (int)W.dense_level.size() && W.dense_level[l] && l < (int)P.dense_ok.size() && P.dense_ok[l];
+  };
+  const int64_t P3R = fourier_row(L);
   tm.begin(kPassM2F);
-  if (P.n_m2f > 0)
-    DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2f<R, LL>), dim3((unsigned)P.n_m2f), dim3(256), 0, s, P.n_m2f,
-                                          P.m2f_exp, (const C2<R>*)M, Mt));
+  for (int l = 0; l < nlev; ++l) {
+    int64_t rb = P.lvl_m2f[l], nr = P.lvl_m2f[l + 1] - rb;
+    if (nr == 0 || is_dense(l)) continue;
+    DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2f<R, LL>), dim3((unsigned)nr), dim3(256), 0, s, nr, P.m2f_exp + rb,
+                                         (const C2<R>*)M, Mt + rb * P3R));
+  }
+  tm.end();
+
+  tm.begin(kPassM2LDense);
+  for (int l = 0; l < nlev; ++l) {
+    const int64_t tb = P.m2l_level_tgt[l], nt = P.m2l_level_tgt[l + 1] - tb;
+    if (nt == 0 || !is_dense(l)) continue;
+    const int64_t t0 = P.dns_tile_begin[l], ntl = P.dns_tile_begin[l + 1] - t0;
+    DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_dense<R, LL>), dim3((unsigned)ntl), dim3(64), 0, s, ntl,
+                                         P.dns_tile_off + t0, P.dns_tile_first + t0, P.dns_tile_cnt + t0,
+                                         P.dns_src, P.dns_slot, (const C2<R>*)P.dense_K[l], (const C2<R>*)M,
+                                         (C2<R>*)W.slots));
+    DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_dense_reduce<R, LL>), dim3((unsigned)nt), dim3(128), 0, s, nt,
+                                         P.m2l_tgt + tb, P.m2l_begin + tb, P.host.m2l_begin[tb],
+                                         (const C2<R>*)W.slots, Lx));
+  }
   tm.end();
 
   tm.begin(kPassM2L);
-  if (P.n_m2l_tgt > 0) {
+  C2<R>* Lt = (C2<R>*)W.Lt;
+  for (int l = 0; l < nlev; ++l) {
+    const int64_t tb = P.m2l_level_tgt[l], nt = P.m2l_level_tgt[l + 1] - tb;
+    if (nt == 0 || is_dense(l)) continue;
     if (W.m2l_variant == 0) {
-      DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l<R, LL>), dim3(xcd_grid(P.n_m2l_tgt)), dim3(256), 0, s,
-                                           P.n_m2l_tgt, P.m2l_tgt, P.m2l_begin, (const int2*)P.m2l_pair,
-                                           (const C2<R>*)Mt, S, Lx));
+      DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l<R, LL>), dim3(xcd_grid(nt)), dim3(256), 0, s, nt, P.m2l_tgt + tb,
+                                           P.m2l_begin + tb, (const int2*)P.m2l_pair, (const C2<R>*)Mt, S, Lx));
     } else {
-      C2<R>* Lt = (C2<R>*)W.Lt;
       if (W.m2l_variant == 2) {
-        DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_runs<R, LL, m2l_slices(LL)>), dim3((unsigned)(m2l_slices(LL) * P.n_grp)), dim3(64), 0,
-                                             s, P.n_grp, P.grp_tfirst, P.grp_tcount, P.grp_run_begin, P.runs,
-                                             (const C2<R>*)Mt, S, Lt));
+        const int64_t gb = P.lvl_grp[l], ng = P.lvl_grp[l + 1] - gb;
+        DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_runs<R, LL, m2l_slices(LL)>), dim3((unsigned)(m2l_slices(LL) * ng)),
+                                             dim3(64), 0, s, ng, P.grp_tfirst + gb, P.grp_tcount + gb,
+                                             P.grp_run_begin + gb, P.runs, (const C2<R>*)Mt, S, Lt));
       } else {
-        // one launch over all levels; 8 slices (one per XCD)
-        DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_slice<R, LL, m2l_slices(LL)>), dim3((unsigned)(m2l_slices(LL) * P.n_m2l_tgt)), dim3(64),
-                                             0, s, P.n_m2l_tgt, P.m2l_begin, (const int2*)P.m2l_pair,
-                                             (const C2<R>*)Mt, S, Lt));
+        DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_slice<R, LL, m2l_slices(LL)>), dim3((unsigned)(m2l_slices(LL) * nt)),
+                                             dim3(64), 0, s, nt, P.m2l_begin + tb, (const int2*)P.m2l_pair,
+                                             (const C2<R>*)Mt, S, Lt + tb * P3R));
       }
-      tm.end();
-      tm.begin(kPassF2L);
-      DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_f2l<R, LL>), dim3(xcd_grid(P.n_m2l_tgt)), dim3(256), 0, s,
-                                           P.n_m2l_tgt, P.m2l_tgt, (const C2<R>*)Lt, Lx));
     }
   }
+  tm.end();
+  tm.begin(kPassF2L);
+  if (W.m2l_variant != 0)
+    for (int l = 0; l < nlev; ++l) {
+      const int64_t tb = P.m2l_level_tgt[l], nt = P.m2l_level_tgt[l + 1] - tb;
+      if (nt == 0 || is_dense(l)) continue;
+      DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_f2l<R, LL>), dim3(xcd_grid(nt)), dim3(256), 0, s, nt, P.m2l_tgt + tb,
+                                           (const C2<R>*)(Lt + tb * P3R), Lx));
+    }
   tm.end();
 
   tm.begin(kPassL2L);

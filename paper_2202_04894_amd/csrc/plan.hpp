@@ -86,6 +86,14 @@ struct HostPlan {
   // group's 8 targets (-1 where that target has no pair with this source).
   std::vector<int32_t> grp_tfirst, grp_tcount, grp_run_begin;  // run CSR: ngrp + 1
   std::vector<int32_t> runs;
+  std::vector<int32_t> lvl_grp, lvl_m2f;  // per level: group range, Fourier-row range (nlevels + 1)
+  // Dense M2L per level: the level's distinct offsets (global ids), its pairs
+  // in offset-major order (source expansion, position in the target CSR
+  // relative to the level's first pair) and tiles of <= 16 pairs sharing an
+  // offset (level-local offset index, first pair, count).
+  std::vector<int32_t> dns_off_begin, dns_off;
+  std::vector<int32_t> dns_pair_begin, dns_src, dns_slot;
+  std::vector<int32_t> dns_tile_begin, dns_tile_off, dns_tile_first, dns_tile_cnt;
   std::vector<int32_t> m2l_src, m2l_off;
   // L2L per level l (children at l+1): child expansions, CSR of (parent exp, octant)
   std::vector<std::vector<int32_t>> l2l_ch, l2l_begin, l2l_par;

@@ -471,6 +471,53 @@ void build_tables(HostPlan& hp) {
   hp.m2l_level_tgt.assign(X.nlevels + 1, 0);
   for (int32_t e : hp.m2l_tgt) hp.m2l_level_tgt[X.level[X.exp_cell[e]] + 1]++;
   for (int l = 0; l < X.nlevels; ++l) hp.m2l_level_tgt[l + 1] += hp.m2l_level_tgt[l];
+  // per-level ranges of groups and of Fourier rows (both are level-major)
+  {
+    int nl = std::max(X.nlevels, Y.nlevels);
+    hp.lvl_grp.assign(nl + 1, 0);
+    for (int32_t t0 : hp.grp_tfirst) hp.lvl_grp[X.level[X.exp_cell[hp.m2l_tgt[t0]]] + 1]++;
+    hp.lvl_m2f.assign(nl + 1, 0);
+    for (int32_t e : hp.m2f_exp) hp.lvl_m2f[Y.level[Y.exp_cell[e]] + 1]++;
+    for (int l = 0; l < nl; ++l) {
+      hp.lvl_grp[l + 1] += hp.lvl_grp[l];
+      hp.lvl_m2f[l + 1] += hp.lvl_m2f[l];
+    }
+    if ((int)hp.m2l_level_tgt.size() < nl + 1) hp.m2l_level_tgt.resize(nl + 1, hp.m2l_level_tgt.back());
+    // dense M2L tables, offset-major per level
+    hp.dns_off_begin.assign(1, 0);
+    hp.dns_pair_begin.assign(1, 0);
+    hp.dns_tile_begin.assign(1, 0);
+    std::vector<int32_t> local(hp.offsets.size(), -1);
+    for (int l = 0; l < nl; ++l) {
+      int32_t tb = hp.m2l_level_tgt[l], te = hp.m2l_level_tgt[l + 1];
+      int32_t kb = hp.m2l_begin[tb], ke = hp.m2l_begin[te];
+      std::vector<int32_t> offs;
+      for (int32_t k = kb; k < ke; ++k) offs.push_back(hp.m2l_off[k]);
+      std::sort(offs.begin(), offs.end());
+      offs.erase(std::unique(offs.begin(), offs.end()), offs.end());
+      for (size_t i = 0; i < offs.size(); ++i) local[offs[i]] = (int32_t)i;
+      std::vector<std::pair<int32_t, int32_t>> pr;  // (local offset, CSR position)
+      for (int32_t k = kb; k < ke; ++k) pr.push_back({local[hp.m2l_off[k]], k});
+      std::sort(pr.begin(), pr.end());
+      int32_t pbase = (int32_t)hp.dns_src.size();
+      for (size_t i = 0; i < pr.size(); ++i) {
+        hp.dns_src.push_back(hp.m2f_exp[hp.m2l_src[pr[i].second]]);
+        hp.dns_slot.push_back(pr[i].second - kb);
+      }
+      for (size_t i = 0; i < pr.size();) {
+        size_t j = i;
+        while (j < pr.size() && pr[j].first == pr[i].first && j - i < 16) ++j;
+        hp.dns_tile_off.push_back(pr[i].first);
+        hp.dns_tile_first.push_back(pbase + (int32_t)i);
+        hp.dns_tile_cnt.push_back((int32_t)(j - i));
+        i = j;
+      }
+      hp.dns_off.insert(hp.dns_off.end(), offs.begin(), offs.end());
+      hp.dns_off_begin.push_back((int32_t)hp.dns_off.size());
+      hp.dns_pair_begin.push_back((int32_t)hp.dns_src.size());
+      hp.dns_tile_begin.push_back((int32_t)hp.dns_tile_off.size());
+    }
+  }
   // L2L, sons level by level
   hp.l2l_ch.assign(X.nlevels, {});
   hp.l2l_begin.assign(X.nlevels, {});

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libdefmm.so")
 C128, C64 = 0, 1
 M2L_AUTO, M2L_FFT, M2L_DENSE = 0, 1, 2
 SAME_POINTS = 1
-NUM_PASSES = 11
+NUM_PASSES = 12
 
 
 class DefmmError(RuntimeError):
@@ -33,7 +33,7 @@ class _Params(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("overlap", ctypes.c_int32), ("p2p_waves_per_cu", ctypes.c_int32), ("m2l_variant", ctypes.c_int32),
-                ("ms", ctypes.c_double)]
+                ("dense_levels", ctypes.c_uint32), ("ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -54,7 +54,7 @@ EXPORTS = ["defmm_default_params", "defmm_plan_create", "defmm_plan_inspect_crea
            "defmm_workspace_set_timing", "defmm_workspace_set_overlap", "defmm_workspace_pass_times",
            "defmm_workspace_autotune", "defmm_workspace_get_tuning", "defmm_workspace_set_tuning",
            "defmm_pass_name",
-           "defmm_plan_pass_work"]
+           "defmm_workspace_pass_work"]
 
 _lib = None
 
@@ -92,7 +92,7 @@ def lib():
     L.defmm_workspace_pass_times.argtypes = [P, P, P]
     L.defmm_pass_name.argtypes = [i32]
     L.defmm_pass_name.restype = ctypes.c_char_p
-    L.defmm_plan_pass_work.argtypes = [P, P, P]
+    L.defmm_workspace_pass_work.argtypes = [P, P, P]
     for name in EXPORTS:
         if name not in ("defmm_status_string", "defmm_last_error", "defmm_pass_name"):
             getattr(L, name).restype = st
@@ -194,6 +194,7 @@ class Plan:
         s = _Stats()
         _check(lib().defmm_plan_stats(self.h, ctypes.byref(s)))
         d = {k: getattr(s, k) for k, _ in _Stats._fields_ if k != "m2l_mode_per_level"}
+        d["m2l_mode_per_level"] = list(s.m2l_mode_per_level)[: max(d["levels"], 0)]
         return d
 
     def footprint(self):
@@ -241,11 +242,6 @@ class Plan:
         _check(lib().defmm_plan_export_p2p(self.h, ctypes.byref(n), _np_ptr(t), _np_ptr(s)))
         return dict(t=t, s=s)
 
-    def pass_work(self):
-        b = np.zeros(NUM_PASSES)
-        f = np.zeros(NUM_PASSES)
-        _check(lib().defmm_plan_pass_work(self.h, _np_ptr(b), _np_ptr(f)))
-        return b, f
 
 
 def torch_empty_like_out(plan, q):
@@ -305,12 +301,20 @@ class Workspace:
         _check(lib().defmm_workspace_get_tuning(self.h, ctypes.byref(t)))
         return t.as_dict()
 
-    def set_tuning(self, overlap=1, p2p_waves_per_cu=2, m2l_variant=2):
-        t = Tuning(overlap, p2p_waves_per_cu, m2l_variant, 0.0)
+    def set_tuning(self, overlap=1, p2p_waves_per_cu=2, m2l_variant=2, dense_levels=0, **_):
+        t = Tuning(overlap, p2p_waves_per_cu, m2l_variant, dense_levels, 0.0)
         _check(lib().defmm_workspace_set_tuning(self.h, ctypes.byref(t)))
 
     def set_overlap(self, on: bool):
         _check(lib().defmm_workspace_set_overlap(self.h, 1 if on else 0))
+
+    def pass_work(self):
+        """Compulsory HBM bytes and flops of one matvec per pass, under the
+        workspace's current execution choices."""
+        b = np.zeros(NUM_PASSES)
+        f = np.zeros(NUM_PASSES)
+        _check(lib().defmm_workspace_pass_work(self.h, _np_ptr(b), _np_ptr(f)))
+        return b, f
 
     def pass_times(self):
         ms = np.zeros(NUM_PASSES)

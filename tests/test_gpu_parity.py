@@ -102,6 +102,32 @@ def test_c64_matches_oracle(geom, n, kappa, kw):
     assert rel(p, ref) < 2e-5, rel(p, ref)
 
 
+DENSE_CASES = [
+    ("sphere", 3000, 24.0, dict(order_L=5, ncrit=24, eta=0.5, hf_threshold=2.0, dir_refine=1)),
+    ("cube_volume", 3000, 12.0, dict(order_L=4, ncrit=40)),
+    ("ellipsoid", 4000, 30.0, dict(order_L=3, ncrit=16, hf_threshold=1.0)),
+    ("sphere", 2000, 8.0, dict(order_L=2, ncrit=8)),
+    ("cube_surface", 3000, 10.0, dict(order_L=6, ncrit=60)),
+]
+
+
+@pytest.mark.parametrize("geom,n,kappa,kw", DENSE_CASES)
+def test_dense_m2l_matches_oracle(geom, n, kappa, kw):
+    """The dense MFMA M2L (every level) computes the same M2L sums as the
+    oracle: complex128 to rounding, complex64 within the c64 bound."""
+    defmm = _defmm()
+    X = W.GENERATORS[geom](n, 131)
+    q = W.charges(n, 132)
+    ref = oracle.FMM(X, None, kappa, oracle.Params(L=kw["order_L"], ncrit=kw["ncrit"], eta=kw.get("eta", 1.0),
+                                                   hf_threshold=kw.get("hf_threshold", 2.0),
+                                                   dir_refine=kw.get("dir_refine", 0))).apply(q)
+    for prec, tol in ((defmm.C128, 1e-11), (defmm.C64, 2e-5)):
+        prm = defmm.Params(precision=prec, m2l_mode=defmm.M2L_DENSE, **kw)
+        p, plan, _ = run_gpu(X, q, kappa, prm)
+        assert plan.stats()["m2l_pairs"] > 0
+        assert rel(p, ref) < tol, (prec, rel(p, ref))
+
+
 def test_distinct_target_and_source_sets():
     defmm = _defmm()
     X = W.sphere(2500, 3)
@@ -170,18 +196,32 @@ def test_overlap_and_variants_are_bitwise_identical():
 
 
 def test_autotune_keeps_a_valid_choice():
+    """M2L_AUTO: the plan holds dense matrices for its levels, the workspace
+    starts on the Fourier form, and the tuner's choice (variant, dense levels,
+    overlap) gives the same potentials to rounding."""
     defmm = _defmm()
     X = W.ellipsoid(30000, 23)
     q = W.charges(30000, 24)
-    plan = defmm.Plan(X, None, 80.0, defmm.Params(order_L=4, ncrit=32, precision=defmm.C64))
+    plan = defmm.Plan(X, None, 80.0, defmm.Params(order_L=4, ncrit=32, precision=defmm.C64,
+                                                  m2l_mode=defmm.M2L_AUTO))
+    capable = sum(1 << l for l, m in enumerate(plan.stats()["m2l_mode_per_level"]) if m == defmm.M2L_DENSE)
+    assert capable != 0
     ws = defmm.Workspace(plan)
+    assert ws.tuning()["dense_levels"] == 0
     qt = torch.as_tensor(q, device="cuda").to(plan.cdtype)
     ref = ws.matvec(qt).cpu().numpy().astype(np.complex128)
     t = ws.autotune(qt, reps=2)
     assert t["m2l_variant"] in (1, 2) and t["overlap"] in (0, 1) and t["ms"] > 0
-    assert ws.tuning()["m2l_variant"] == t["m2l_variant"]
+    assert t["dense_levels"] & ~capable == 0
+    assert ws.tuning() == {**t, "ms": 0.0}
     got = ws.matvec(qt).cpu().numpy().astype(np.complex128)
     assert rel(got, ref) < 1e-6
+    # every capable level dense, in sequence and overlapped
+    for ov in (0, 1):
+        ws.set_tuning(overlap=ov, p2p_waves_per_cu=2, m2l_variant=2, dense_levels=0xFFFFFFFF)
+        assert ws.tuning()["dense_levels"] == capable
+        got = ws.matvec(qt).cpu().numpy().astype(np.complex128)
+        assert rel(got, ref) < 1e-6
 
 
 def test_degenerate_inputs():

@@ -92,7 +92,7 @@ def test_lists_match_oracle_distinct_sets():
 def test_invalid_arguments_are_rejected():
     X = W.sphere(100, 1)
     bad = [(dict(order_L=1), 0.0), (dict(order_L=9), 0.0), (dict(ncrit=0), 0.0), (dict(eta=0.0), 0.0),
-           (dict(), -1.0), (dict(), float("nan")), (dict(precision=7), 0.0)]
+           (dict(), -1.0), (dict(), float("nan")), (dict(precision=7), 0.0), (dict(m2l_mode=5), 0.0)]
     for kw, kappa in bad:
         with pytest.raises(defmm.DefmmError, match="invalid argument"):
             defmm.Plan.inspect(X, None, kappa, defmm.Params(**kw))
@@ -100,8 +100,9 @@ def test_invalid_arguments_are_rejected():
     Xn[5, 1] = np.inf
     with pytest.raises(defmm.DefmmError, match="non-finite"):
         defmm.Plan.inspect(Xn, None, 1.0, defmm.Params())
-    with pytest.raises(defmm.DefmmError, match="unsupported"):
-        defmm.Plan.inspect(X, None, 1.0, defmm.Params(m2l_mode=defmm.M2L_DENSE))
+    # the dense M2L needs device matrices: an inspection plan accepts the mode
+    for mode in (defmm.M2L_AUTO, defmm.M2L_DENSE):
+        assert defmm.Plan.inspect(X, None, 1.0, defmm.Params(m2l_mode=mode)).stats()["m2l_pairs"] >= 0
 
 
 def test_degenerate_geometries_build():
