@@ -211,6 +211,7 @@ def main():
     rel_direct64 = float(np.linalg.norm(p64[tg] - pd) / np.linalg.norm(pd))
 
     # roofline of the dominant kernel, from per-pass HIP events over the timed region
+    st = plan64.stats()
     ms_pass, calls = passes
     names = [defmm.pass_name(i) for i in range(defmm.NUM_PASSES)]
     bytes_, flops = ws64.pass_work()
@@ -237,8 +238,20 @@ def main():
     roof["avg_launch_ms"] = round(t_launch * 1e3, 4)
     roof["timing"] = "per-pass HIP events, passes in sequence on one stream (near field not overlapped)"
     roof["traffic"] = load_traffic(kern, wl.name)
+    t_floor = max(bytes_[dom] / (HBM_PEAK_GBS * 1e9), flops[dom] / (FP32_PEAK_TFLOPS * 1e12))
+    roof["t_floor_ms"] = round(t_floor * 1e3, 4)
+    roof["t_over_t_floor"] = round(t_launch / t_floor, 2) if t_floor > 0 else None
+    if dname == "m2l":
+        # what the caches serve: both operands of every pair, s_c (2L-1)^3 bytes each
+        cs = 8
+        roof["effective_GBps"] = round(flops[dom] * cs / 4 / t_launch / 1e9, 1)
+    p2p_i = names.index("p2p")
+    t_p2p = per_step[p2p_i] / 1e3
+    p2p = {"kernel": "k_p2p", "point_pairs": int(st["p2p_point_pairs"]), "ms": round(t_p2p * 1e3, 4),
+           "Gpairs_per_s": round(st["p2p_point_pairs"] / t_p2p / 1e9, 2),
+           "TFLOPs_nominal": round(flops[p2p_i] / t_p2p / 1e12, 3),
+           "frac_fp32_vector_peak": round(flops[p2p_i] / t_p2p / 1e12 / FP32_PEAK_TFLOPS, 4)}
 
-    st = plan64.stats()
     out = {
         "metric": METRIC,
         "value": round(wl.n / (ms64 / 1e3) / 1e6, 3),
@@ -270,6 +283,7 @@ def main():
         "passes_ms_per_step": {n: round(float(v), 4) for n, v in zip(names, per_step)},
         "stats": st,
         "roofline": roof,
+        "p2p": p2p,
     }
     if not args.no_cpu_baseline:
         n_s = args.cpu_sample or min(wl.n, 131072)

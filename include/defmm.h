@@ -203,9 +203,10 @@ const char* defmm_pass_name(int32_t i);
 /* Algorithmic work of one matvec per pass under the workspace's current
    execution choices (which levels run the dense M2L, which Fourier variant):
    bytes[i] = compulsory HBM bytes of pass i (each input read once, each output
-   written once; e.g. Fourier M2L: per pair one spectrum row and one source row
-   of (2L-1)^3 values, per target one row written; dense M2L: each level-local
-   matrix, source and target expansion once), flops[i] = real floating-point
+   written once; e.g. Fourier M2L: each distinct spectrum and each source row of
+   (2L-1)^3 values read once, each target row written once; dense M2L: each
+   level-local matrix, source and target expansion once), flops[i] = real
+   floating-point
    operations (a complex multiply-add counts 8).  Either pointer may be NULL;
    each holds DEFMM_NUM_PASSES entries. */
 defmm_status defmm_workspace_pass_work(const defmm_workspace* ws, double* bytes, double* flops);

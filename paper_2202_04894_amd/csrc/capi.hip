@@ -720,6 +720,9 @@ defmm_status defmm_workspace_pass_work(const defmm_workspace* ws, double* bytes,
   const double f2l_per_tgt = 8 * (Pp * Pp * L * Pp + Pp * L * L * Pp + L3 * Pp);
   const double m2f_per_row = 8 * (Pp * L * L * L + Pp * Pp * L * L + P3 * L);
   const int nlev = (int)H.lvl_m2f.size() - 1;
+  std::vector<double> n_spec(nlev > 0 ? nlev : 0, 0.0);
+  for (const Offset& o : H.offsets)
+    if (o.level >= 0 && o.level < nlev) n_spec[o.level] += 1;
   for (int l = 0; l < nlev; ++l) {
     const double n_src = (double)(H.lvl_m2f[l + 1] - H.lvl_m2f[l]);
     const int64_t tb = H.m2l_level_tgt[l], te = H.m2l_level_tgt[l + 1];
@@ -734,11 +737,14 @@ defmm_status defmm_workspace_pass_work(const defmm_workspace* ws, double* bytes,
     }
     b[kPassM2F] += n_src * cs * (L3 + P3);
     f[kPassM2F] += n_src * m2f_per_row;
+    // Hadamard: each spectrum and each source row read once, each target row
+    // written once (the per-pair operand stream, 2 cs P^3 per pair, is what
+    // the caches must serve beyond that)
     if (W.m2l_variant == 0) {
-      b[kPassM2L] += n_pair * 2 * cs * P3 + n_tgt * cs * L3;
+      b[kPassM2L] += (n_spec[l] + n_src) * cs * P3 + n_tgt * cs * L3;
       f[kPassM2L] += n_pair * 8 * P3 + n_tgt * f2l_per_tgt;
     } else {
-      b[kPassM2L] += n_pair * 2 * cs * P3 + n_tgt * cs * P3;
+      b[kPassM2L] += (n_spec[l] + n_src + n_tgt) * cs * P3;
       f[kPassM2L] += n_pair * 8 * P3;
       b[kPassF2L] += n_tgt * cs * (P3 + L3);
       f[kPassF2L] += n_tgt * f2l_per_tgt;

@@ -1260,16 +1260,30 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
   }
   tm.end();
 
-  // levels whose M2L runs dense skip M2F/F2L; the others use the Fourier path
+  // levels whose M2L runs dense skip M2F/F2L; the others use the Fourier path,
+  // launched once per maximal range of consecutive Fourier levels (all levels
+  // share L, and every table is level-major, so a range is a contiguous slice)
   const int nlev = (int)P.lvl_m2f.size() - 1;
   auto is_dense = [&](int l) {
     return l < (int)W.dense_level.size() && W.dense_level[l] && l < (int)P.dense_ok.size() && P.dense_ok[l];
   };
+  int fr_lo[kMaxLevel + 2], fr_hi[kMaxLevel + 2], nfr = 0;
+  for (int l = 0; l < nlev;) {
+    if (is_dense(l)) {
+      ++l;
+      continue;
+    }
+    int e = l;
+    while (e < nlev && !is_dense(e)) ++e;
+    fr_lo[nfr] = l;
+    fr_hi[nfr++] = e;
+    l = e;
+  }
   const int64_t P3R = fourier_row(L);
   tm.begin(kPassM2F);
-  for (int l = 0; l < nlev; ++l) {
-    int64_t rb = P.lvl_m2f[l], nr = P.lvl_m2f[l + 1] - rb;
-    if (nr == 0 || is_dense(l)) continue;
+  for (int k = 0; k < nfr; ++k) {
+    const int64_t rb = P.lvl_m2f[fr_lo[k]], nr = P.lvl_m2f[fr_hi[k]] - rb;
+    if (nr == 0) continue;
     DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2f<R, LL>), dim3((unsigned)nr), dim3(256), 0, s, nr, P.m2f_exp + rb,
                                          (const C2<R>*)M, Mt + rb * P3R));
   }
@@ -1292,31 +1306,29 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
 
   tm.begin(kPassM2L);
   C2<R>* Lt = (C2<R>*)W.Lt;
-  for (int l = 0; l < nlev; ++l) {
-    const int64_t tb = P.m2l_level_tgt[l], nt = P.m2l_level_tgt[l + 1] - tb;
-    if (nt == 0 || is_dense(l)) continue;
+  for (int k = 0; k < nfr; ++k) {
+    const int64_t tb = P.m2l_level_tgt[fr_lo[k]], nt = P.m2l_level_tgt[fr_hi[k]] - tb;
+    if (nt == 0) continue;
     if (W.m2l_variant == 0) {
       DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l<R, LL>), dim3(xcd_grid(nt)), dim3(256), 0, s, nt, P.m2l_tgt + tb,
                                            P.m2l_begin + tb, (const int2*)P.m2l_pair, (const C2<R>*)Mt, S, Lx));
+    } else if (W.m2l_variant == 2) {
+      const int64_t gb = P.lvl_grp[fr_lo[k]], ng = P.lvl_grp[fr_hi[k]] - gb;
+      DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_runs<R, LL, m2l_slices(LL)>), dim3((unsigned)(m2l_slices(LL) * ng)),
+                                           dim3(64), 0, s, ng, P.grp_tfirst + gb, P.grp_tcount + gb,
+                                           P.grp_run_begin + gb, P.runs, (const C2<R>*)Mt, S, Lt));
     } else {
-      if (W.m2l_variant == 2) {
-        const int64_t gb = P.lvl_grp[l], ng = P.lvl_grp[l + 1] - gb;
-        DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_runs<R, LL, m2l_slices(LL)>), dim3((unsigned)(m2l_slices(LL) * ng)),
-                                             dim3(64), 0, s, ng, P.grp_tfirst + gb, P.grp_tcount + gb,
-                                             P.grp_run_begin + gb, P.runs, (const C2<R>*)Mt, S, Lt));
-      } else {
-        DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_slice<R, LL, m2l_slices(LL)>), dim3((unsigned)(m2l_slices(LL) * nt)),
-                                             dim3(64), 0, s, nt, P.m2l_begin + tb, (const int2*)P.m2l_pair,
-                                             (const C2<R>*)Mt, S, Lt + tb * P3R));
-      }
+      DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_slice<R, LL, m2l_slices(LL)>), dim3((unsigned)(m2l_slices(LL) * nt)),
+                                           dim3(64), 0, s, nt, P.m2l_begin + tb, (const int2*)P.m2l_pair,
+                                           (const C2<R>*)Mt, S, Lt + tb * P3R));
     }
   }
   tm.end();
   tm.begin(kPassF2L);
   if (W.m2l_variant != 0)
-    for (int l = 0; l < nlev; ++l) {
-      const int64_t tb = P.m2l_level_tgt[l], nt = P.m2l_level_tgt[l + 1] - tb;
-      if (nt == 0 || is_dense(l)) continue;
+    for (int k = 0; k < nfr; ++k) {
+      const int64_t tb = P.m2l_level_tgt[fr_lo[k]], nt = P.m2l_level_tgt[fr_hi[k]] - tb;
+      if (nt == 0) continue;
       DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_f2l<R, LL>), dim3(xcd_grid(nt)), dim3(256), 0, s, nt, P.m2l_tgt + tb,
                                            (const C2<R>*)(Lt + tb * P3R), Lx));
     }
