@@ -147,6 +147,13 @@ defmm_status defmm_plan_export_m2l(const defmm_plan* plan, int64_t* n, int32_t* 
 /* P2P pairs (Alg. 1): target cell, source cell. */
 defmm_status defmm_plan_export_p2p(const defmm_plan* plan, int64_t* n, int32_t* t, int32_t* s);
 
+/* Marks of tree `which` (0 = X, 1 = Y) after the blank passes (Alg. 2, 3): the
+   effective expansions as (cell id, direction index or -1 for the
+   non-directional mark), ordered by cell, then direction.  Call with NULL
+   arrays to get *n, then with arrays of *n entries. */
+defmm_status defmm_plan_export_marks(const defmm_plan* plan, int32_t which, int64_t* n, int32_t* cell,
+                                     int32_t* dir);
+
 /* Expansions of tree `which` after a matvec on ws: cell id, direction (-1 =
    non-directional) and kind 0 = multipole / 1 = local node values, L^3 complex
    per expansion (complex of the plan's precision). */

@@ -12,6 +12,7 @@
 #include <string>
 
 #include "../../include/defmm.h"
+#include "build_device.hpp"
 #include "device.hpp"
 
 using namespace defmm;
@@ -149,25 +150,13 @@ static defmm_status validate(const double* X, int64_t nx, const double* Y, int64
 
 // Host half of plan creation: copies the points, checks them and builds the
 // host plan.  Throws on allocation/device errors; returns a status for bad input.
-static defmm_status host_build(defmm_plan* plan, const double* X, int64_t nx, const double* Y, int64_t ny,
-                               double kappa, const defmm_params* prm, bool host_pointers) {
+// Builds the plan's trees, lists, marks and operator tables: on the device
+// (HIP kernels, stream s) from device coordinates, or entirely on the host
+// from host coordinates (inspection plans).  Throws on allocation/device
+// errors; returns a status for bad input.
+static defmm_status plan_build(defmm_plan* plan, const double* X, int64_t nx, const double* Y, int64_t ny,
+                               double kappa, const defmm_params* prm, bool host_pointers, hipStream_t s) {
   bool same = (prm->flags & DEFMM_SAME_POINTS) != 0;
-  std::vector<double> hx(3 * nx), hy;
-  if (nx > 0) {
-    if (host_pointers) std::memcpy(hx.data(), X, 3 * nx * sizeof(double));
-    else check(hipMemcpy(hx.data(), X, 3 * nx * sizeof(double), hipMemcpyDefault), "copy X");
-  }
-  if (!same) {
-    hy.resize(3 * ny);
-    if (ny > 0) {
-      if (host_pointers) std::memcpy(hy.data(), Y, 3 * ny * sizeof(double));
-      else check(hipMemcpy(hy.data(), Y, 3 * ny * sizeof(double), hipMemcpyDefault), "copy Y");
-    }
-  }
-  for (double v : hx)
-    if (!std::isfinite(v)) return fail(DEFMM_ERR_INVALID_ARG, "non-finite coordinate in X");
-  for (double v : hy)
-    if (!std::isfinite(v)) return fail(DEFMM_ERR_INVALID_ARG, "non-finite coordinate in Y");
   DevPlan& P = plan->impl;
   BuildParams bp;
   bp.L = prm->order_L;
@@ -177,7 +166,16 @@ static defmm_status host_build(defmm_plan* plan, const double* X, int64_t nx, co
   bp.dir_refine = prm->dir_refine;
   bp.same_points = same;
   bp.kappa = kappa;
-  build_host_plan(P.host, hx.data(), nx, same ? nullptr : hy.data(), ny, bp);
+  if (host_pointers) {
+    for (int64_t i = 0; i < 3 * nx; ++i)
+      if (!std::isfinite(X[i])) return fail(DEFMM_ERR_INVALID_ARG, "non-finite coordinate in X");
+    if (!same)
+      for (int64_t i = 0; i < 3 * ny; ++i)
+        if (!std::isfinite(Y[i])) return fail(DEFMM_ERR_INVALID_ARG, "non-finite coordinate in Y");
+    build_host_plan(P.host, X, nx, same ? nullptr : Y, ny, bp);
+  } else if (!build_device_plan(P.host, X, nx, same ? nullptr : Y, ny, bp, s)) {
+    return fail(DEFMM_ERR_INVALID_ARG, "non-finite coordinate in X or Y");
+  }
   const HostPlan& H = P.host;
   P.L = bp.L;
   P.precision = prm->precision;
@@ -200,7 +198,7 @@ defmm_status defmm_plan_inspect_create(const double* X, int64_t nx, const double
   try {
     plan = new defmm_plan();
     plan->impl.host_only = true;
-    st = host_build(plan, X, nx, Y, ny, kappa, prm, true);
+    st = plan_build(plan, X, nx, Y, ny, kappa, prm, true, nullptr);
     if (st != DEFMM_OK) {
       delete plan;
       return st;
@@ -226,7 +224,7 @@ defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int
   defmm_plan* plan = nullptr;
   try {
     plan = new defmm_plan();
-    st = host_build(plan, X, nx, Y, ny, kappa, prm, false);
+    st = plan_build(plan, X, nx, Y, ny, kappa, prm, false, s);
     if (st != DEFMM_OK) {
       delete plan;
       return st;
@@ -532,6 +530,17 @@ defmm_status defmm_plan_export_p2p(const defmm_plan* plan, int64_t* n, int32_t* 
   *n = (int64_t)H.p2p_t.size();
   if (t) std::memcpy(t, H.p2p_t.data(), H.p2p_t.size() * 4);
   if (s) std::memcpy(s, H.p2p_s.data(), H.p2p_s.size() * 4);
+  return DEFMM_OK;
+}
+
+defmm_status defmm_plan_export_marks(const defmm_plan* plan, int32_t which, int64_t* n, int32_t* cell,
+                                     int32_t* dir) {
+  if (!plan || !n || (which != 0 && which != 1)) return fail(DEFMM_ERR_INVALID_ARG, "bad argument");
+  const HostPlan& H = plan->impl.host;
+  const Tree& T = which == 0 ? H.tx : *H.ty;
+  *n = T.nexp();
+  if (cell) std::memcpy(cell, T.exp_cell.data(), T.exp_cell.size() * 4);
+  if (dir) std::memcpy(dir, T.exp_dir.data(), T.exp_dir.size() * 4);
   return DEFMM_OK;
 }
 

@@ -110,6 +110,20 @@ struct HostPlan {
 void build_host_plan(HostPlan& hp, const double* X, int64_t nx, const double* Y, int64_t ny,
                      const BuildParams& prm);
 
+// Stages shared by the host builder and the device builder.
+// Bounding cube from the coordinate extremes (any = at least one point).
+void set_geometry(HostPlan& hp, const double* lo, const double* hi, bool any);
+// Per level: high-frequency flag, squared MAC threshold, deepest HF level.
+void set_regimes(HostPlan& hp);
+// Direction sets up to the finest level any M2L offset needs (offsets set).
+void make_direction_tables(HostPlan& hp);
+// Unit direction of each expansion (exp_dir, exp_cell and directions set).
+void set_expansion_directions(HostPlan& hp, Tree& T);
+// Direction level (refinement E) of tree level l.
+int dir_level(const HostPlan& hp, int l);
+// Operator tables from the trees, lists, offsets and marks.
+void build_tables(HostPlan& hp);
+
 int64_t num_directions(int E);
 void make_directions(int E, double* dirs, int64_t* father);
 

@@ -225,9 +225,9 @@ int64_t Tree::find_exp(int32_t c, int32_t u) const {
   return exp_begin[c] + (it - b);
 }
 
-namespace {
-
 int dir_level(const HostPlan& hp, int l) { return hp.lstar - l + hp.prm.dir_refine; }
+
+namespace {
 
 int32_t best_direction(const HostPlan& hp, int E, const int32_t* d) {
   const double* V = hp.dirs.data() + 3 * hp.dir_off[E];
@@ -352,6 +352,8 @@ void mark_tree(HostPlan& hp, Tree& T, const std::vector<uint64_t>& own) {
     }
   }
 }
+
+}  // namespace
 
 void build_tables(HostPlan& hp) {
   Tree& X = hp.tx;
@@ -631,7 +633,52 @@ void build_tables(HostPlan& hp) {
   hp.wi_seg_begin.push_back((int32_t)hp.seg_first.size());
 }
 
-}  // namespace
+void set_geometry(HostPlan& hp, const double* lo, const double* hi, bool any) {
+  double D = 0.0;
+  if (any) {
+    for (int d = 0; d < 3; ++d) D = std::fmax(D, hi[d] - lo[d]);
+    for (int d = 0; d < 3; ++d) hp.origin[d] = 0.5 * (lo[d] + hi[d]) - 0.5 * D;
+  }
+  hp.D = D;
+  hp.tau = 1e-12 * D;
+}
+
+void set_regimes(HostPlan& hp) {
+  hp.lstar = -1;
+  for (int l = 0; l <= kMaxLevel; ++l) {
+    double w = std::ldexp(hp.D, -(l + 1));
+    hp.hf[l] = (hp.prm.kappa * w > hp.prm.hf_threshold) ? 1 : 0;
+    if (hp.hf[l]) hp.lstar = l;
+    double a = std::fmax(hp.prm.kappa * w, 2.0) / (2.0 * hp.prm.eta);
+    hp.thr[l] = a * a;
+  }
+}
+
+void make_direction_tables(HostPlan& hp) {
+  int Emax = -1;
+  for (const Offset& o : hp.offsets)
+    if (hp.hf[o.level]) Emax = std::max(Emax, dir_level(hp, o.level));
+  hp.dir_off.assign(std::max(Emax + 1, 1), -1);
+  int64_t tot = 0;
+  for (int E = 0; E <= Emax; ++E) {
+    hp.dir_off[E] = tot;
+    tot += num_directions(E);
+  }
+  hp.dirs.resize(3 * tot);
+  hp.father_flat.resize(tot);
+  for (int E = 0; E <= Emax; ++E)
+    make_directions(E, hp.dirs.data() + 3 * hp.dir_off[E], hp.father_flat.data() + hp.dir_off[E]);
+}
+
+void set_expansion_directions(HostPlan& hp, Tree& T) {
+  T.exp_u.assign(3 * T.nexp(), 0.0);
+  for (int64_t e = 0; e < T.nexp(); ++e) {
+    int32_t u = T.exp_dir[e];
+    if (u < 0) continue;
+    const double* v = hp.dirs.data() + 3 * (hp.dir_off[dir_level(hp, T.level[T.exp_cell[e]])] + u);
+    for (int d = 0; d < 3; ++d) T.exp_u[3 * e + d] = v[d];
+  }
+}
 
 void build_host_plan(HostPlan& hp, const double* X, int64_t nx, const double* Y, int64_t ny,
                      const BuildParams& prm) {
@@ -650,43 +697,18 @@ void build_host_plan(HostPlan& hp, const double* X, int64_t nx, const double* Y,
         lo[d] = std::fmin(lo[d], Yp[3 * i + d]);
         hi[d] = std::fmax(hi[d], Yp[3 * i + d]);
       }
-  double D = 0.0;
-  if (nx + (prm.same_points ? 0 : ny) > 0) {
-    for (int d = 0; d < 3; ++d) D = std::fmax(D, hi[d] - lo[d]);
-    for (int d = 0; d < 3; ++d) hp.origin[d] = 0.5 * (lo[d] + hi[d]) - 0.5 * D;
-  }
-  hp.D = D;
-  hp.tau = 1e-12 * D;
-  build_tree(hp.tx, X, nx, hp.origin, D, prm.ncrit);
+  set_geometry(hp, lo, hi, nx + (prm.same_points ? 0 : ny) > 0);
+  build_tree(hp.tx, X, nx, hp.origin, hp.D, prm.ncrit);
   if (prm.same_points) {
     hp.ty = &hp.tx;
   } else {
-    build_tree(hp.ty_own, Yp, ny, hp.origin, D, prm.ncrit);
+    build_tree(hp.ty_own, Yp, ny, hp.origin, hp.D, prm.ncrit);
     hp.ty = &hp.ty_own;
   }
-  hp.lstar = -1;
-  for (int l = 0; l <= kMaxLevel; ++l) {
-    double w = std::ldexp(D, -(l + 1));
-    hp.hf[l] = (prm.kappa * w > prm.hf_threshold) ? 1 : 0;
-    if (hp.hf[l]) hp.lstar = l;
-    double a = std::fmax(prm.kappa * w, 2.0) / (2.0 * prm.eta);
-    hp.thr[l] = a * a;
-  }
+  set_regimes(hp);
   if (nx > 0 && ny > 0) traverse(hp);
   // directions up to the finest level any M2L needs
-  int Emax = -1;
-  for (const Offset& o : hp.offsets)
-    if (hp.hf[o.level]) Emax = std::max(Emax, dir_level(hp, o.level));
-  hp.dir_off.assign(std::max(Emax + 1, 1), -1);
-  int64_t tot = 0;
-  for (int E = 0; E <= Emax; ++E) {
-    hp.dir_off[E] = tot;
-    tot += num_directions(E);
-  }
-  hp.dirs.resize(3 * tot);
-  hp.father_flat.resize(tot);
-  for (int E = 0; E <= Emax; ++E)
-    make_directions(E, hp.dirs.data() + 3 * hp.dir_off[E], hp.father_flat.data() + hp.dir_off[E]);
+  make_direction_tables(hp);
   parallel_chunks((int64_t)hp.offsets.size(), 64, [&](int64_t b, int64_t e, int) {
     for (int64_t i = b; i < e; ++i) {
       Offset& o = hp.offsets[i];

@@ -50,7 +50,8 @@ class _Stats(ctypes.Structure):
 EXPORTS = ["defmm_default_params", "defmm_plan_create", "defmm_plan_inspect_create", "defmm_plan_footprint", "defmm_plan_stats",
            "defmm_workspace_create", "defmm_matvec", "defmm_workspace_destroy", "defmm_plan_destroy",
            "defmm_status_string", "defmm_last_error", "defmm_plan_geometry", "defmm_plan_export_tree",
-           "defmm_plan_export_m2l", "defmm_plan_export_p2p", "defmm_workspace_export_expansions",
+           "defmm_plan_export_m2l", "defmm_plan_export_p2p", "defmm_plan_export_marks",
+           "defmm_workspace_export_expansions",
            "defmm_workspace_set_timing", "defmm_workspace_set_overlap", "defmm_workspace_pass_times",
            "defmm_workspace_autotune", "defmm_workspace_get_tuning", "defmm_workspace_set_tuning",
            "defmm_pass_name",
@@ -83,6 +84,7 @@ def lib():
     L.defmm_plan_export_tree.argtypes = [P, i32, P, P, P, P, P, P, P]
     L.defmm_plan_export_m2l.argtypes = [P, P, P, P, P, P, P]
     L.defmm_plan_export_p2p.argtypes = [P, P, P, P]
+    L.defmm_plan_export_marks.argtypes = [P, i32, P, P, P]
     L.defmm_workspace_export_expansions.argtypes = [P, i32, i32, P, P, P, P]
     L.defmm_workspace_set_timing.argtypes = [P, i32]
     L.defmm_workspace_set_overlap.argtypes = [P, i32]
@@ -233,6 +235,17 @@ class Plan:
         _check(lib().defmm_plan_export_m2l(self.h, ctypes.byref(ctypes.c_int64()), _np_ptr(lev), _np_ptr(t),
                                            _np_ptr(s), _np_ptr(d), _np_ptr(u)))
         return dict(level=lev, t=t, s=s, delta=d, dir=u)
+
+    def marks(self, which=0):
+        """Effective expansions of tree `which` (0 = X, 1 = Y): cell ids and
+        direction indices (-1 = non-directional), ordered by cell, direction."""
+        n = ctypes.c_int64()
+        _check(lib().defmm_plan_export_marks(self.h, which, ctypes.byref(n), None, None))
+        cell = np.zeros(n.value, np.int32)
+        d = np.zeros(n.value, np.int32)
+        _check(lib().defmm_plan_export_marks(self.h, which, ctypes.byref(ctypes.c_int64()), _np_ptr(cell),
+                                             _np_ptr(d)))
+        return dict(cell=cell, dir=d)
 
     def p2p(self):
         n = ctypes.c_int64()
