@@ -47,6 +47,12 @@ def parse():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after timing, run one plain device copy of this size (HBM counter calibration)")
     ap.add_argument("--c64-only", action="store_true", help="skip the complex128 path and the checks")
+    ap.add_argument("--serving", action="store_true",
+                    help="serving configuration: Poisson-arriving requests with continuous batching")
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--geometries", type=int, default=32)
+    ap.add_argument("--load", type=float, default=0.7, help="arrival rate as a fraction of one-stream capacity")
+    ap.add_argument("--slots", type=int, default=8)
     return ap.parse_args()
 
 
@@ -137,12 +143,79 @@ def cpu_baseline(wl, X, kappa, knobs, perm, n_sample):
                       f"(setup excluded) took {secs:.2f} s"}
 
 
+def run_serving(args):
+    """Serving configuration: requests with N log-uniform in [1e4, 5e5] on
+    spheres and cap-weighted ellipsoids (from a pool of geometries), kappa*D
+    uniform in [16, 256], L in {4, 5}, leaves <= 64, 20 matvecs each with fresh
+    complex64 charges drawn on the device from a per-request seed.
+
+    Three runs over the same requests, each starting with an empty plan cache:
+      * all requests queued at once, `slots` admitted at a time (continuous
+        batching at full load): the capacity, requests/s (`value`);
+      * the same, one request at a time: the one-stream capacity;
+      * Poisson arrivals at `load` times the one-stream capacity: latencies.
+    Then a sample of requests is run in a mix and alone: same bits."""
+    import torch
+    from paper_2202_04894_amd import serving as S
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(0.8 * free)
+
+    def requests(rate=None):
+        return S.config_requests(n_requests=args.requests, n_geometries=args.geometries, seed=7, rate=rate)
+
+    ex = S.DeviceExecutor()
+    S.Scheduler(ex, budget, max_slots=2).run(requests()[:4])  # warm-up: kernels, allocator
+
+    def run(reqs, slots):
+        sch = S.Scheduler(ex, budget, max_slots=slots)
+        t0 = time.perf_counter()
+        out = sch.run(reqs)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        pts = sum(r.n_points * r.n_matvecs for r, o in zip(reqs, out) if o.ok)
+        return dict(S.summarize(out, wall), Mpoints_per_s=round(pts / wall / 1e6, 3),
+                    requests_per_s=round(sum(o.ok for o in out) / wall, 3), scheduler=sch.stats)
+
+    full = run(requests(), args.slots)
+    one = run(requests(), 1)
+    rate = args.load * one["requests_per_s"]
+    open_loop = run(requests(rate), args.slots)
+    # the same requests alone give the same bits (sampled)
+    rng = np.random.default_rng(3)
+    sample = sorted(rng.choice(args.requests, size=min(4, args.requests), replace=False).tolist())
+    sub = [requests()[i] for i in sample]
+    for r in sub:
+        r.n_matvecs = 2
+    exk = S.DeviceExecutor(keep_results=True)
+    mix = S.Scheduler(exk, budget, max_slots=len(sub), keep_results=True).run(sub)
+    same = True
+    for r, m in zip(sub, mix):
+        alone = S.Scheduler(exk, budget, max_slots=1, keep_results=True).run([r])[0]
+        same = same and m.ok and alone.ok and all(np.array_equal(a, b) for a, b in zip(alone.results, m.results))
+    line = {"metric": "serving: requests/s under continuous batching (full load); p50/p99 latency at "
+                      f"{args.load:.0%} load",
+            "value": full["requests_per_s"], "unit": "requests/s", "n_gpus": 1, "higher_is_better": True,
+            "dtype": "c64", "data": "synthetic",
+            "config": {"workload": f"{args.requests} requests, N log-uniform in [1e4, 5e5] on spheres / "
+                                   f"cap-weighted ellipsoids from a pool of {args.geometries} geometries, "
+                                   "kappa*D in [16, 256], L in {4, 5}, leaf<=64, 20 complex64 matvecs each",
+                       "slots": args.slots, "budget_GiB": round(budget / 2 ** 30, 1)},
+            "full_load": full, "one_at_a_time": one,
+            "batching_speedup": round(full["requests_per_s"] / one["requests_per_s"], 3),
+            "open_loop": dict(open_loop, arrival_rate_per_s=round(rate, 3), load=args.load),
+            "alone_equals_mix_bitwise": bool(same), "alone_vs_mix_sample": sample}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is "
               f"described in DESIGN.md and not built", file=sys.stderr)
         sys.exit(2)
+    if args.serving:
+        run_serving(args)
+        return
     import torch
     from paper_2202_04894_amd import defmm
     from paper_2202_04894_amd import workloads as W

@@ -44,7 +44,12 @@ void chk(hipError_t e, const char* what) {
   if (e != hipSuccess) throw std::runtime_error(std::string("device builder: ") + what + ": " + hipGetErrorString(e));
 }
 
-// Owning device array.
+// Stream of the build in progress: the builder's temporaries are allocated
+// and freed in stream order on it (no device-wide synchronisation, so a
+// build does not stall other streams' work).
+thread_local hipStream_t g_stream = nullptr;
+
+// Owning device array (stream-ordered on the build stream).
 template <class T>
 struct DVec {
   T* p = nullptr;
@@ -63,13 +68,13 @@ struct DVec {
     return *this;
   }
   ~DVec() {
-    if (p) (void)hipFree(p);
+    if (p) (void)hipFreeAsync(p, g_stream);
   }
   void resize(size_t k) {
-    if (p) (void)hipFree(p);
+    if (p) (void)hipFreeAsync(p, g_stream);
     p = nullptr;
     n = k;
-    if (k) chk(hipMalloc(&p, k * sizeof(T)), "allocation");
+    if (k) chk(hipMallocAsync((void**)&p, k * sizeof(T), g_stream), "allocation");
   }
 };
 
@@ -780,6 +785,14 @@ bool build_device_plan(HostPlan& hp, const double* X, int64_t nx, const double* 
   hp.prm = prm;
   const double* Yp = prm.same_points ? X : Y;
   if (prm.same_points) ny = nx;
+  struct StreamScope {
+    hipStream_t prev;
+    explicit StreamScope(hipStream_t st) : prev(g_stream) { g_stream = st; }
+    ~StreamScope() {
+      (void)hipStreamSynchronize(g_stream);
+      g_stream = prev;
+    }
+  } scope(s);
   Temp tmp;
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
   bool ok = bbox(X, nx, lo, hi, s);

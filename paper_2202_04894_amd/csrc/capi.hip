@@ -166,6 +166,7 @@ static defmm_status plan_build(defmm_plan* plan, const double* X, int64_t nx, co
   bp.dir_refine = prm->dir_refine;
   bp.same_points = same;
   bp.kappa = kappa;
+  bp.dense_tables = prm->m2l_mode != DEFMM_M2L_FFT;
   if (host_pointers) {
     for (int64_t i = 0; i < 3 * nx; ++i)
       if (!std::isfinite(X[i])) return fail(DEFMM_ERR_INVALID_ARG, "non-finite coordinate in X");

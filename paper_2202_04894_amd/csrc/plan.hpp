@@ -24,6 +24,7 @@ struct BuildParams {
   int dir_refine = 0;
   bool same_points = false;
   double kappa = 0.0;
+  bool dense_tables = true;  // build the dense M2L index tables (the M2L mode may use them)
 };
 
 // One 2^d-tree over a point set, level-major, Morton order inside a level.

@@ -410,18 +410,33 @@ void build_tables(HostPlan& hp) {
       row[e] = (int32_t)hp.m2f_exp.size();
       hp.m2f_exp.push_back((int32_t)e);
     }
-  std::vector<int64_t> order(nm);
-  std::iota(order.begin(), order.end(), 0);
   // targets ordered by (level, direction, Morton cell): neighbouring work
-  // shares sources and spectra; inside a target, sources in Morton order
-  auto tkey = [&](int64_t i) {
-    int32_t c = X.exp_cell[te[i]];
-    return std::make_tuple(X.level[c], X.exp_dir[te[i]], c);
-  };
-  std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
-    auto ka = tkey(a), kb = tkey(b);
-    if (ka != kb) return ka < kb;
-    return se[a] < se[b];
+  // shares sources and spectra; inside a target, sources in Morton order.
+  // Counting sort of the pairs by target rank, then each target's pairs by
+  // source expansion.
+  std::vector<int32_t> rank(X.nexp(), -1), tl;
+  for (int64_t i = 0; i < nm; ++i)
+    if (rank[te[i]] < 0) {
+      rank[te[i]] = 0;
+      tl.push_back(te[i]);
+    }
+  std::sort(tl.begin(), tl.end(), [&](int32_t a, int32_t b) {
+    int32_t ca = X.exp_cell[a], cb = X.exp_cell[b];
+    return std::make_tuple(X.level[ca], X.exp_dir[a], ca) < std::make_tuple(X.level[cb], X.exp_dir[b], cb);
+  });
+  for (size_t r = 0; r < tl.size(); ++r) rank[tl[r]] = (int32_t)r;
+  std::vector<int64_t> tpos(tl.size() + 1, 0);
+  for (int64_t i = 0; i < nm; ++i) tpos[rank[te[i]] + 1]++;
+  for (size_t r = 0; r < tl.size(); ++r) tpos[r + 1] += tpos[r];
+  std::vector<int64_t> order(nm);
+  {
+    std::vector<int64_t> fill(tpos.begin(), tpos.end() - 1);
+    for (int64_t i = 0; i < nm; ++i) order[fill[rank[te[i]]]++] = i;
+  }
+  parallel_chunks((int64_t)tl.size(), 256, [&](int64_t b, int64_t e, int) {
+    for (int64_t r = b; r < e; ++r)
+      std::sort(order.begin() + tpos[r], order.begin() + tpos[r + 1],
+                [&](int64_t x, int64_t y) { return se[x] < se[y]; });
   });
   hp.m2l_src.resize(nm);
   hp.m2l_off.resize(nm);
@@ -438,7 +453,7 @@ void build_tables(HostPlan& hp) {
   // groups of <= 8 targets sharing level and direction, merged by source
   {
     int64_t nt = (int64_t)hp.m2l_tgt.size();
-    std::vector<std::pair<int32_t, int32_t>> ent;  // (source row, tloc * 2^28 + offset)
+    std::vector<int64_t> g0;  // first target of each group
     for (int64_t t0 = 0; t0 < nt;) {
       int32_t c0 = X.exp_cell[hp.m2l_tgt[t0]];
       int lv = X.level[c0], dr = X.exp_dir[hp.m2l_tgt[t0]];
@@ -446,29 +461,57 @@ void build_tables(HostPlan& hp) {
       while (t1 < nt && t1 - t0 < 8 && X.level[X.exp_cell[hp.m2l_tgt[t1]]] == lv &&
              X.exp_dir[hp.m2l_tgt[t1]] == dr)
         ++t1;
-      ent.clear();
-      for (int64_t t = t0; t < t1; ++t)
-        for (int32_t k = hp.m2l_begin[t]; k < hp.m2l_begin[t + 1]; ++k)
-          ent.push_back({hp.m2l_src[k], (int32_t)(((t - t0) << 28) | hp.m2l_off[k])});
-      std::sort(ent.begin(), ent.end());
-      hp.grp_tfirst.push_back((int32_t)t0);
-      hp.grp_tcount.push_back((int32_t)(t1 - t0));
-      hp.grp_run_begin.push_back((int32_t)(hp.runs.size() / 9));
-      for (size_t a = 0; a < ent.size();) {
-        size_t b = a;
-        int32_t rec[9];
-        rec[0] = ent[a].first;
-        for (int q = 1; q < 9; ++q) rec[q] = -1;
-        while (b < ent.size() && ent[b].first == ent[a].first) {
-          rec[1 + (ent[b].second >> 28)] = ent[b].second & ((1 << 28) - 1);
-          ++b;
-        }
-        hp.runs.insert(hp.runs.end(), rec, rec + 9);
-        a = b;
-      }
+      g0.push_back(t0);
       t0 = t1;
     }
-    hp.grp_run_begin.push_back((int32_t)(hp.runs.size() / 9));
+    const int64_t ng = (int64_t)g0.size();
+    g0.push_back(nt);
+    // groups in chunks on the host threads, runs concatenated in group order
+    const int64_t nch = std::max<int64_t>(1, std::min<int64_t>(64, ng / 512));
+    std::vector<std::vector<int32_t>> chunk_runs(nch), chunk_nrun(nch);
+    parallel_chunks(nch, 1, [&](int64_t cb, int64_t ce, int) {
+      std::vector<std::pair<int32_t, int32_t>> ent;  // (source row, tloc * 2^28 + offset)
+      for (int64_t ch = cb; ch < ce; ++ch) {
+        for (int64_t g = ng * ch / nch; g < ng * (ch + 1) / nch; ++g) {
+          ent.clear();
+          for (int64_t t = g0[g]; t < g0[g + 1]; ++t)
+            for (int32_t k = hp.m2l_begin[t]; k < hp.m2l_begin[t + 1]; ++k)
+              ent.push_back({hp.m2l_src[k], (int32_t)(((t - g0[g]) << 28) | hp.m2l_off[k])});
+          std::sort(ent.begin(), ent.end());
+          int32_t nr = 0;
+          for (size_t a = 0; a < ent.size();) {
+            size_t b = a;
+            int32_t rec[9];
+            rec[0] = ent[a].first;
+            for (int q = 1; q < 9; ++q) rec[q] = -1;
+            while (b < ent.size() && ent[b].first == ent[a].first) {
+              rec[1 + (ent[b].second >> 28)] = ent[b].second & ((1 << 28) - 1);
+              ++b;
+            }
+            chunk_runs[ch].insert(chunk_runs[ch].end(), rec, rec + 9);
+            ++nr;
+            a = b;
+          }
+          chunk_nrun[ch].push_back(nr);
+        }
+      }
+    });
+    hp.grp_tfirst.resize(ng);
+    hp.grp_tcount.resize(ng);
+    hp.grp_run_begin.resize(ng + 1);
+    int64_t g = 0, run = 0;
+    for (int64_t ch = 0; ch < nch; ++ch) {
+      for (int32_t nr : chunk_nrun[ch]) {
+        hp.grp_tfirst[g] = (int32_t)g0[g];
+        hp.grp_tcount[g] = (int32_t)(g0[g + 1] - g0[g]);
+        hp.grp_run_begin[g] = (int32_t)run;
+        run += nr;
+        ++g;
+      }
+      hp.runs.insert(hp.runs.end(), chunk_runs[ch].begin(), chunk_runs[ch].end());
+      std::vector<int32_t>().swap(chunk_runs[ch]);
+    }
+    hp.grp_run_begin[ng] = (int32_t)run;
   }
   hp.m2l_level_tgt.assign(X.nlevels + 1, 0);
   for (int32_t e : hp.m2l_tgt) hp.m2l_level_tgt[X.level[X.exp_cell[e]] + 1]++;
@@ -485,12 +528,18 @@ void build_tables(HostPlan& hp) {
       hp.lvl_m2f[l + 1] += hp.lvl_m2f[l];
     }
     if ((int)hp.m2l_level_tgt.size() < nl + 1) hp.m2l_level_tgt.resize(nl + 1, hp.m2l_level_tgt.back());
-    // dense M2L tables, offset-major per level
+    // dense M2L tables, offset-major per level (only when the M2L mode may use them)
     hp.dns_off_begin.assign(1, 0);
     hp.dns_pair_begin.assign(1, 0);
     hp.dns_tile_begin.assign(1, 0);
-    std::vector<int32_t> local(hp.offsets.size(), -1);
+    std::vector<int32_t> local(hp.prm.dense_tables ? hp.offsets.size() : 0, -1);
     for (int l = 0; l < nl; ++l) {
+      if (!hp.prm.dense_tables) {
+        hp.dns_off_begin.push_back(0);
+        hp.dns_pair_begin.push_back(0);
+        hp.dns_tile_begin.push_back(0);
+        continue;
+      }
       int32_t tb = hp.m2l_level_tgt[l], te = hp.m2l_level_tgt[l + 1];
       int32_t kb = hp.m2l_begin[tb], ke = hp.m2l_begin[te];
       std::vector<int32_t> offs;

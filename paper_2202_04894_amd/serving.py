@@ -1,0 +1,357 @@
+"""Serving loop: continuous batching of matvec requests on one GPU.
+
+A request is a geometry (points, kappa, L, leaf size) and a number of
+matvecs with fresh charges, as a GMRES solve of a boundary integral equation
+would issue them.  The scheduler:
+
+  * keeps plans (tree, lists, spectra) resident per geometry id and reuses
+    them (LRU eviction of plans no request is using);
+  * admits arrived requests in arrival order while a slot is free and their
+    HBM footprint (workspace, plus the plan when it is not cached) fits the
+    budget; requests that arrive while others run are admitted as soon as
+    slots and memory free up;
+  * gives each admitted request its own workspace and stream, so the work of
+    concurrent requests overlaps on the device;
+  * isolates failures: a request whose plan cannot be built (bad input,
+    out of memory) fails alone.
+
+The scheduler knows nothing of the device: it drives an executor.
+`DeviceExecutor` runs requests through the library; the tests also drive the
+scheduler with a simulated executor on the CPU.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Callable, Optional
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    geometry: str                         # plan-cache key: same key, same points and parameters
+    make_points: Callable[[], np.ndarray]  # (n, 3) float64
+    n_points: int
+    kappa: float
+    order_L: int = 5
+    ncrit: int = 64
+    n_matvecs: int = 20
+    charges: Optional[Callable[[int], np.ndarray]] = None  # k -> (n,) complex charges of matvec k
+    arrival: float = 0.0                  # seconds after the start of the run
+
+
+@dataclasses.dataclass
+class Outcome:
+    rid: int
+    ok: bool
+    error: str = ""
+    arrival: float = 0.0
+    admitted: float = float("nan")
+    done: float = float("nan")
+    plan_cached: bool = False
+    matvec_ms: list = dataclasses.field(default_factory=list)
+    results: Optional[list] = None        # potentials per matvec (host), when kept
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class Scheduler:
+    """Admission, plan cache and bookkeeping over an executor.
+
+    executor interface:
+      now() -> float                       seconds on the executor's clock
+      idle(dt)                             wait up to dt seconds (no work to admit)
+      estimate(req) -> (plan_bytes, ws_bytes)   before the plan exists
+      build(req) -> (plan, plan_bytes, ws_bytes) may raise: the request fails
+      start(req, plan) -> handle           enqueue the request's matvecs (reusing a
+                                           workspace the plan's last request left)
+      done(handle) -> bool
+      finish(handle) -> (done_time, matvec_ms, results); the workspace is kept
+      release_plan(plan)                   frees the plan and its kept workspaces
+    """
+
+    def __init__(self, executor, budget_bytes: int, max_slots: int = 8, keep_results: bool = False):
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.max_slots = int(max_slots)
+        self.keep_results = keep_results
+        # geometry -> [plan, plan_bytes, ws_bytes, users, pooled]: a finished
+        # request's workspace stays with its plan (pooled, still charged) and
+        # serves the next request of that geometry; eviction frees both
+        self.plans = collections.OrderedDict()
+        self.used = 0
+        self.stats = dict(builds=0, cache_hits=0, evictions=0, failed=0, max_running=0, peak_bytes=0)
+
+    def _evict_for(self, need: int, keep: str) -> bool:
+        for key in list(self.plans):
+            if self.used + need <= self.budget:
+                break
+            ent = self.plans[key]
+            if ent[3] == 0 and key != keep:
+                self.ex.release_plan(ent[0])
+                self.used -= ent[1] + ent[4] * ent[2]
+                del self.plans[key]
+                self.stats["evictions"] += 1
+        return self.used + need <= self.budget
+
+    def run(self, requests) -> list:
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        queue = collections.deque()
+        running = {}  # rid -> (req, handle, ws_bytes, outcome)
+        outcomes = {}
+        t0 = self.ex.now()
+        while pending or queue or running:
+            now = self.ex.now() - t0
+            while pending and pending[0].arrival <= now:
+                queue.append(pending.popleft())
+            progressed = False
+            for rid in list(running):
+                req, h, wsb, oc = running[rid]
+                if self.ex.done(h):
+                    done, ms, res = self.ex.finish(h)
+                    oc.done = done - t0
+                    oc.matvec_ms = ms
+                    oc.results = res if self.keep_results else None
+                    ent = self.plans[req.geometry]
+                    ent[3] -= 1
+                    ent[4] += 1
+                    outcomes[rid] = oc
+                    del running[rid]
+                    progressed = True
+            while queue and len(running) < self.max_slots:
+                req = queue[0]
+                ent = self.plans.get(req.geometry)
+                if ent is not None:
+                    need = 0 if ent[4] > 0 else ent[2]
+                else:
+                    pb, wb = self.ex.estimate(req)
+                    need = pb + wb
+                if self.used + need > self.budget and not self._evict_for(need, req.geometry):
+                    if running:
+                        break  # wait for memory to free up
+                    if ent is not None:
+                        # nothing runs and every other plan is gone: can never fit
+                        queue.popleft()
+                        outcomes[req.rid] = Outcome(req.rid, False, "footprint exceeds the memory budget",
+                                                    arrival=req.arrival)
+                        self.stats["failed"] += 1
+                        progressed = True
+                        continue
+                    # the device is idle: build, and let the real footprint decide
+                queue.popleft()
+                oc = Outcome(req.rid, True, arrival=req.arrival, admitted=self.ex.now() - t0)
+                if ent is None:
+                    try:
+                        plan, pb, wb = self.ex.build(req)
+                    except Exception as e:  # the request fails alone
+                        oc.ok = False
+                        oc.error = f"{type(e).__name__}: {e}"
+                        outcomes[req.rid] = oc
+                        self.stats["failed"] += 1
+                        progressed = True
+                        continue
+                    ent = self.plans[req.geometry] = [plan, pb, wb, 0, 0]
+                    self.used += pb
+                    self.stats["builds"] += 1
+                    if pb + wb > self.budget:
+                        self.ex.release_plan(plan)
+                        self.used -= pb
+                        del self.plans[req.geometry]
+                        oc.ok = False
+                        oc.error = "footprint exceeds the memory budget"
+                        outcomes[req.rid] = oc
+                        self.stats["failed"] += 1
+                        progressed = True
+                        continue
+                    if self.used + wb > self.budget and not self._evict_for(wb, req.geometry):
+                        # the estimate was low: wait for memory, the plan stays cached
+                        queue.appendleft(req)
+                        progressed = True
+                        break
+                else:
+                    self.plans.move_to_end(req.geometry)
+                    oc.plan_cached = True
+                    self.stats["cache_hits"] += 1
+                ent[3] += 1
+                pooled = ent[4] > 0
+                if pooled:
+                    ent[4] -= 1
+                else:
+                    self.used += ent[2]
+                try:
+                    h = self.ex.start(req, ent[0])
+                except Exception as e:
+                    ent[3] -= 1
+                    if pooled:
+                        ent[4] += 1
+                    else:
+                        self.used -= ent[2]
+                    oc.ok = False
+                    oc.error = f"{type(e).__name__}: {e}"
+                    outcomes[req.rid] = oc
+                    self.stats["failed"] += 1
+                    progressed = True
+                    continue
+                running[req.rid] = (req, h, ent[2], oc)
+                self.stats["max_running"] = max(self.stats["max_running"], len(running))
+                self.stats["peak_bytes"] = max(self.stats["peak_bytes"], self.used)
+                progressed = True
+            if not progressed:
+                nxt = pending[0].arrival - now if pending else 1e-3
+                self.ex.idle(min(max(nxt, 0.0), 1e-3))
+        for ent in self.plans.values():
+            self.ex.release_plan(ent[0])
+        self.plans.clear()
+        self.used = 0
+        return [outcomes[r.rid] for r in sorted(requests, key=lambda r: r.rid)]
+
+
+class DeviceExecutor:
+    """Runs requests through the library, complex64, on the current GPU.
+
+    Each started request gets a workspace, a stream (default priority) and
+    device buffers for its charges and potentials; its matvecs are enqueued
+    at once with a HIP event pair around each, which give the per-matvec
+    latencies (contention with other requests included) and the completion
+    time on the host clock.
+    """
+
+    def __init__(self, plan_bytes_per_point: float = 1024.0, ws_bytes_per_point: float = 2048.0,
+                 keep_results: bool = False):
+        import torch
+        from . import defmm
+        self.torch, self.defmm = torch, defmm
+        # per-point footprint estimates for plans not built yet; raised to the
+        # largest ratio seen on built plans (plan creation also needs
+        # transient builder memory of the same order)
+        self.plan_bpp = plan_bytes_per_point
+        self.ws_bpp = ws_bytes_per_point
+        self.keep_results = keep_results
+        self.pool = {}  # id(plan) -> idle workspaces of that plan
+        self.build_stream = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        self.ref = torch.cuda.Event(enable_timing=True)
+        self.ref.record()
+        self.ref.synchronize()
+        self.t_ref = time.perf_counter()
+
+    def now(self):
+        return time.perf_counter()
+
+    def idle(self, dt):
+        time.sleep(dt)
+
+    def estimate(self, req):
+        return int(self.plan_bpp * req.n_points), int(self.ws_bpp * req.n_points)
+
+    def build(self, req):
+        torch, defmm = self.torch, self.defmm
+        X = torch.as_tensor(np.ascontiguousarray(req.make_points(), dtype=np.float64), device="cuda")
+        prm = defmm.Params(order_L=req.order_L, ncrit=req.ncrit, precision=defmm.C64)
+        plan = defmm.Plan(X, None, req.kappa, prm, stream=self.build_stream)
+        self.build_stream.synchronize()
+        pb, wb = plan.footprint()
+        n = max(req.n_points, 1)
+        self.plan_bpp = max(self.plan_bpp, pb / n)
+        self.ws_bpp = max(self.ws_bpp, wb / n)
+        return plan, pb, wb
+
+    def start(self, req, plan):
+        torch, defmm = self.torch, self.defmm
+        s = torch.cuda.Stream()
+        pool = self.pool.setdefault(id(plan), [])
+        with torch.cuda.stream(s):
+            ws = pool.pop() if pool else defmm.Workspace(plan)
+            qs, ps, evs = [], [], []
+            if req.charges is not None:
+                for k in range(req.n_matvecs):
+                    q = torch.from_numpy(np.ascontiguousarray(req.charges(k), dtype=np.complex64)).pin_memory()
+                    qs.append(q.to("cuda", non_blocking=True))
+            else:
+                # seeded complex normal charges drawn on the device
+                g = torch.Generator(device="cuda")
+                g.manual_seed(1_000_003 * (req.rid + 1))
+                for k in range(req.n_matvecs):
+                    qs.append(torch.randn(req.n_points, dtype=torch.complex64, device="cuda", generator=g))
+            for k in range(req.n_matvecs):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(s)
+                ps.append(ws.matvec(qs[k], stream=s))
+                e1.record(s)
+                evs.append((e0, e1))
+        return dict(s=s, ws=ws, qs=qs, ps=ps, evs=evs)
+
+    def done(self, h):
+        return h["evs"][-1][1].query() if h["evs"] else True
+
+    def finish(self, h):
+        h["evs"][-1][1].synchronize() if h["evs"] else h["s"].synchronize()
+        ms = [a.elapsed_time(b) for a, b in h["evs"]]
+        done = self.t_ref + (self.ref.elapsed_time(h["evs"][-1][1]) / 1e3 if h["evs"] else 0.0)
+        res = [p.cpu().numpy() for p in h["ps"]] if self.keep_results else None
+        # keep the workspace for the plan's next request: freeing device
+        # memory synchronises the whole device, which would stall the others
+        self.pool.setdefault(id(h["ws"].plan), []).append(h["ws"])
+        h.clear()
+        return done, ms, res
+
+    def release_plan(self, plan):
+        for ws in self.pool.pop(id(plan), []):
+            ws.close()
+        plan.close()
+
+
+def config_requests(n_requests=256, n_geometries=32, seed=7, n_min=10_000, n_max=500_000, kd=(16.0, 256.0),
+                    orders=(4, 5), n_matvecs=20, rate=None, host_charges=False):
+    """Requests with the shapes of the serving configuration: N log-uniform in
+    [n_min, n_max] on the unit sphere or the cap-weighted ellipsoid (50/50),
+    kappa*D uniform in kd, L drawn from orders, leaves <= 64, fresh complex
+    N(0,1) charges per matvec; geometries drawn from a pool of n_geometries
+    (a request reuses its geometry's plan when it is cached); Poisson arrivals
+    at `rate` per second (None: all at time 0).  Charges come from numpy
+    (host_charges) or are drawn on the device from a per-request seed."""
+    from . import workloads as W
+    rng = np.random.default_rng(seed)
+    pool = []
+    for g in range(n_geometries):
+        n = int(round(np.exp(rng.uniform(np.log(n_min), np.log(n_max)))))
+        kind = "sphere" if rng.uniform() < 0.5 else "ellipsoid"
+        kD = float(rng.uniform(*kd))
+        L = int(rng.choice(orders))
+        pool.append((n, kind, kD, L, 5000 + g))
+    t = 0.0
+    reqs = []
+    for i in range(n_requests):
+        n, kind, kD, L, gseed = pool[int(rng.integers(n_geometries))]
+        if rate:
+            t += float(rng.exponential(1.0 / rate))
+        cseed = 9000 + 1000 * i
+
+        def mk(n=n, kind=kind, gseed=gseed):
+            return W.GENERATORS[kind](n, gseed)
+
+        def ch(k, n=n, cseed=cseed):
+            return W.charges(n, cseed + k, np.complex64)
+
+        reqs.append(Request(rid=i, geometry=f"{kind}-{n}-{kD:.3f}-{L}", make_points=mk, n_points=n,
+                            kappa=kD / 2.0, order_L=L, ncrit=64, n_matvecs=n_matvecs,
+                            charges=ch if host_charges else None, arrival=t))
+    return reqs
+
+
+def summarize(outcomes, wall_s):
+    ok = [o for o in outcomes if o.ok]
+    mv = np.array([m for o in ok for m in o.matvec_ms]) if ok else np.zeros(1)
+    lat = np.array([o.latency for o in ok]) if ok else np.zeros(1)
+    return dict(requests=len(outcomes), completed=len(ok), failed=len(outcomes) - len(ok),
+                wall_s=round(wall_s, 3),
+                matvec_p50_ms=round(float(np.percentile(mv, 50)), 3),
+                matvec_p99_ms=round(float(np.percentile(mv, 99)), 3),
+                request_p50_s=round(float(np.percentile(lat, 50)), 4),
+                request_p99_s=round(float(np.percentile(lat, 99)), 4))
