@@ -120,6 +120,17 @@ defmm_status defmm_workspace_create(defmm_plan* plan, defmm_workspace** out);
 defmm_status defmm_matvec(defmm_plan* plan, defmm_workspace* ws, const void* q, void* p,
                           void* hip_stream);
 
+/* The same matvec replayed from a HIP graph: the first call (or the first after
+   q, p or the workspace's execution choices changed) captures the launch
+   sequence on hip_stream into a graph held by the workspace; later calls with
+   the same q and p launch the graph, one submission instead of one per kernel.
+   q and p are baked into the graph: refill q in place between calls.
+   hip_stream must be a created stream (capture is not possible on the null
+   stream); per-pass timing must be off.  Same results as defmm_matvec, bit
+   for bit. */
+defmm_status defmm_matvec_graph(defmm_plan* plan, defmm_workspace* ws, const void* q, void* p,
+                                void* hip_stream);
+
 defmm_status defmm_workspace_destroy(defmm_workspace* ws);
 defmm_status defmm_plan_destroy(defmm_plan* plan);
 

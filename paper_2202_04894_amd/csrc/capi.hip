@@ -89,7 +89,15 @@ namespace defmm {
 DevPlan::~DevPlan() {
   for (void* p : allocs) hipFree(p);
 }
+void Workspace::drop_graph() {
+  if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  graph_exec = nullptr;
+  graph = nullptr;
+  graph_stale = true;
+}
 Workspace::~Workspace() {
+  drop_graph();
   for (void* p : {qs, ps, M, Lx, Mt, Lt, part, (void*)queue, slots})
     if (p) hipFree(p);
   for (hipEvent_t e : ev_pool) hipEventDestroy(e);
@@ -473,6 +481,42 @@ defmm_status defmm_matvec(defmm_plan* plan, defmm_workspace* ws, const void* q, 
   return DEFMM_OK;
 }
 
+defmm_status defmm_matvec_graph(defmm_plan* plan, defmm_workspace* ws, const void* q, void* p, void* hip_stream) {
+  if (!plan || !ws) return fail(DEFMM_ERR_INVALID_ARG, "plan or workspace is NULL");
+  DevPlan& P = plan->impl;
+  Workspace& W = ws->impl;
+  if (P.host_only) return fail(DEFMM_ERR_INVALID_ARG, "plan was built for inspection only");
+  if (W.plan != &P) return fail(DEFMM_ERR_INVALID_ARG, "workspace belongs to another plan");
+  if ((P.ny > 0 && !q) || (P.nx > 0 && !p)) return fail(DEFMM_ERR_INVALID_ARG, "q or p is NULL");
+  if (!hip_stream) return fail(DEFMM_ERR_INVALID_ARG, "graph mode needs a created stream, not the null stream");
+  if (W.timing) return fail(DEFMM_ERR_INVALID_ARG, "per-pass timing is on: use defmm_matvec");
+  hipStream_t s = (hipStream_t)hip_stream;
+  if (W.graph_stale || W.graph_q != q || W.graph_p != p || !W.graph_exec) {
+    W.drop_graph();
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail(DEFMM_ERR_DEVICE, std::string("begin capture: ") + hipGetErrorString(e));
+    hipError_t er = run_matvec(P, W, q, p, s);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s, &g);
+    if (er != hipSuccess || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(DEFMM_ERR_DEVICE, std::string("capture: ") + hipGetErrorString(er != hipSuccess ? er : e));
+    }
+    W.graph = g;
+    e = hipGraphInstantiate(&W.graph_exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      W.drop_graph();
+      return fail(DEFMM_ERR_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    W.graph_q = q;
+    W.graph_p = p;
+    W.graph_stale = false;
+  }
+  hipError_t e = hipGraphLaunch(W.graph_exec, s);
+  if (e != hipSuccess) return fail(DEFMM_ERR_DEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+  return DEFMM_OK;
+}
+
 defmm_status defmm_workspace_destroy(defmm_workspace* ws) {
   delete ws;
   return DEFMM_OK;
@@ -576,6 +620,7 @@ defmm_status defmm_workspace_set_timing(defmm_workspace* ws, int32_t enable) {
 defmm_status defmm_workspace_set_overlap(defmm_workspace* ws, int32_t enable) {
   if (!ws) return fail(DEFMM_ERR_INVALID_ARG, "workspace is NULL");
   ws->impl.overlap = enable != 0;
+  ws->impl.graph_stale = true;
   return DEFMM_OK;
 }
 
@@ -595,6 +640,7 @@ defmm_status defmm_workspace_set_tuning(defmm_workspace* ws, const defmm_tuning*
   if (!ws || !t) return fail(DEFMM_ERR_INVALID_ARG, "NULL argument");
   if (t->p2p_waves_per_cu < 1 || t->p2p_waves_per_cu > 32 || t->m2l_variant < 0 || t->m2l_variant > 2)
     return fail(DEFMM_ERR_INVALID_ARG, "tuning out of range");
+  ws->impl.graph_stale = true;
   ws->impl.overlap = t->overlap != 0;
   ws->impl.p2p_waves = t->p2p_waves_per_cu;
   ws->impl.m2l_variant = t->m2l_variant;
@@ -618,6 +664,7 @@ defmm_status defmm_workspace_autotune(defmm_plan* plan, defmm_workspace* ws, con
     return fail(DEFMM_ERR_DEVICE, "autotune events");
   bool timing = W.timing;
   W.timing = false;
+  W.graph_stale = true;
   auto apply = [&](const defmm_tuning& t) {
     W.overlap = t.overlap != 0;
     W.p2p_waves = t.p2p_waves_per_cu;

@@ -136,6 +136,14 @@ struct Workspace {
   std::vector<Rec> pending;
   double pass_ms[kNumPasses] = {0};
   int64_t pass_calls[kNumPasses] = {0};
+  // captured matvec (defmm_matvec_graph): valid for the recorded q and p and
+  // the execution choices at capture; any change of those recaptures
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  const void* graph_q = nullptr;
+  void* graph_p = nullptr;
+  bool graph_stale = true;
+  void drop_graph();
   ~Workspace();
 };
 

@@ -48,7 +48,7 @@ class _Stats(ctypes.Structure):
 
 
 EXPORTS = ["defmm_default_params", "defmm_plan_create", "defmm_plan_inspect_create", "defmm_plan_footprint", "defmm_plan_stats",
-           "defmm_workspace_create", "defmm_matvec", "defmm_workspace_destroy", "defmm_plan_destroy",
+           "defmm_workspace_create", "defmm_matvec", "defmm_matvec_graph", "defmm_workspace_destroy", "defmm_plan_destroy",
            "defmm_status_string", "defmm_last_error", "defmm_plan_geometry", "defmm_plan_export_tree",
            "defmm_plan_export_m2l", "defmm_plan_export_p2p", "defmm_plan_export_marks",
            "defmm_workspace_export_expansions",
@@ -75,6 +75,7 @@ def lib():
     L.defmm_plan_stats.argtypes = [P, P]
     L.defmm_workspace_create.argtypes = [P, P]
     L.defmm_matvec.argtypes = [P, P, P, P, P]
+    L.defmm_matvec_graph.argtypes = [P, P, P, P, P]
     L.defmm_workspace_destroy.argtypes = [P]
     L.defmm_plan_destroy.argtypes = [P]
     L.defmm_status_string.argtypes = [st]
@@ -280,8 +281,10 @@ class Workspace:
         except Exception:
             pass
 
-    def matvec(self, q, p=None, stream=None):
-        """p = G q on the device; q: complex tensor on cuda (caller order)."""
+    def matvec(self, q, p=None, stream=None, graph=False):
+        """p = G q on the device; q: complex tensor on cuda (caller order).
+        graph=True replays a HIP graph captured for this (q, p) pair (refill q
+        in place; a created stream is needed)."""
         import torch
         pl = self.plan
         if q.dtype != pl.cdtype or not q.is_cuda or q.shape != (pl.ny,):
@@ -291,8 +294,9 @@ class Workspace:
             p = torch.empty(pl.nx, dtype=pl.cdtype, device=q.device)
         elif p.dtype != pl.cdtype or not p.is_cuda or p.shape != (pl.nx,) or not p.is_contiguous():
             raise DefmmError(f"p must be a contiguous cuda {pl.cdtype} tensor of shape ({pl.nx},)")
-        _check(lib().defmm_matvec(pl.h, self.h, ctypes.c_void_p(q.data_ptr()),
-                                  ctypes.c_void_p(p.data_ptr()), _stream_handle(stream)))
+        fn = lib().defmm_matvec_graph if graph else lib().defmm_matvec
+        _check(fn(pl.h, self.h, ctypes.c_void_p(q.data_ptr()), ctypes.c_void_p(p.data_ptr()),
+                  _stream_handle(stream)))
         return p
 
     def set_timing(self, on: bool):

@@ -214,15 +214,15 @@ class Scheduler:
 class DeviceExecutor:
     """Runs requests through the library, complex64, on the current GPU.
 
-    Each started request gets a workspace, a stream (default priority) and
-    device buffers for its charges and potentials; its matvecs are enqueued
-    at once with a HIP event pair around each, which give the per-matvec
+    Each started request gets a workspace (reused from the plan's pool when
+    possible) and a stream (default priority).  Its matvecs are enqueued at
+    once, with a HIP event pair around each, which give the per-matvec
     latencies (contention with other requests included) and the completion
     time on the host clock.
     """
 
     def __init__(self, plan_bytes_per_point: float = 1024.0, ws_bytes_per_point: float = 2048.0,
-                 keep_results: bool = False):
+                 keep_results: bool = False, graphs: bool = False):
         import torch
         from . import defmm
         self.torch, self.defmm = torch, defmm
@@ -232,7 +232,11 @@ class DeviceExecutor:
         self.plan_bpp = plan_bytes_per_point
         self.ws_bpp = ws_bytes_per_point
         self.keep_results = keep_results
-        self.pool = {}  # id(plan) -> idle workspaces of that plan
+        # replay each workspace's captured HIP graph on fixed buffers instead
+        # of launching the matvec's kernels one by one (off by default: see
+        # the design notes on the serving loop)
+        self.graphs = graphs
+        self.pool = {}  # id(plan) -> idle (workspace, charge buffer, potential buffer) of that plan
         self.build_stream = torch.cuda.Stream()
         torch.cuda.synchronize()
         self.ref = torch.cuda.Event(enable_timing=True)
@@ -256,6 +260,7 @@ class DeviceExecutor:
         plan = defmm.Plan(X, None, req.kappa, prm, stream=self.build_stream)
         self.build_stream.synchronize()
         pb, wb = plan.footprint()
+        wb += 8 * (plan.nx + plan.ny)  # the workspace's charge and potential buffers
         n = max(req.n_points, 1)
         self.plan_bpp = max(self.plan_bpp, pb / n)
         self.ws_bpp = max(self.ws_bpp, wb / n)
@@ -266,8 +271,15 @@ class DeviceExecutor:
         s = torch.cuda.Stream()
         pool = self.pool.setdefault(id(plan), [])
         with torch.cuda.stream(s):
-            ws = pool.pop() if pool else defmm.Workspace(plan)
-            qs, ps, evs = [], [], []
+            if pool:
+                ws, qbuf, pbuf = pool.pop()
+            else:
+                ws = defmm.Workspace(plan)
+                qbuf = pbuf = None
+                if self.graphs:
+                    qbuf = torch.empty(plan.ny, dtype=torch.complex64, device="cuda")
+                    pbuf = torch.empty(plan.nx, dtype=torch.complex64, device="cuda")
+            qs = []
             if req.charges is not None:
                 for k in range(req.n_matvecs):
                     q = torch.from_numpy(np.ascontiguousarray(req.charges(k), dtype=np.complex64)).pin_memory()
@@ -278,14 +290,23 @@ class DeviceExecutor:
                 g.manual_seed(1_000_003 * (req.rid + 1))
                 for k in range(req.n_matvecs):
                     qs.append(torch.randn(req.n_points, dtype=torch.complex64, device="cuda", generator=g))
+            ps, evs = [], []
             for k in range(req.n_matvecs):
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record(s)
-                ps.append(ws.matvec(qs[k], stream=s))
+                if self.graphs:
+                    # the workspace's captured matvec on its fixed buffers
+                    qbuf.copy_(qs[k])
+                    ws.matvec(qbuf, pbuf, stream=s, graph=True)
+                    p = pbuf.clone() if self.keep_results else pbuf
+                else:
+                    p = ws.matvec(qs[k], stream=s)
                 e1.record(s)
+                if self.keep_results:
+                    ps.append(p)
                 evs.append((e0, e1))
-        return dict(s=s, ws=ws, qs=qs, ps=ps, evs=evs)
+        return dict(s=s, ws=ws, bufs=(qbuf, pbuf), qs=qs, ps=ps, evs=evs)
 
     def done(self, h):
         return h["evs"][-1][1].query() if h["evs"] else True
@@ -295,14 +316,15 @@ class DeviceExecutor:
         ms = [a.elapsed_time(b) for a, b in h["evs"]]
         done = self.t_ref + (self.ref.elapsed_time(h["evs"][-1][1]) / 1e3 if h["evs"] else 0.0)
         res = [p.cpu().numpy() for p in h["ps"]] if self.keep_results else None
-        # keep the workspace for the plan's next request: freeing device
-        # memory synchronises the whole device, which would stall the others
-        self.pool.setdefault(id(h["ws"].plan), []).append(h["ws"])
+        # keep the workspace (and its buffers and captured graph) for the
+        # plan's next request: freeing device memory synchronises the whole
+        # device, which would stall the other requests
+        self.pool.setdefault(id(h["ws"].plan), []).append((h["ws"], *h["bufs"]))
         h.clear()
         return done, ms, res
 
     def release_plan(self, plan):
-        for ws in self.pool.pop(id(plan), []):
+        for ws, _, _ in self.pool.pop(id(plan), []):
             ws.close()
         plan.close()
 
