@@ -77,9 +77,12 @@ typedef struct {
   int64_t p2p_point_pairs;    /* point-pair interactions of the near field */
   int64_t eff_expansions;     /* effective (cell, direction) expansions, both trees */
   int64_t m2l_expansions;     /* expansions taking part in M2L (sources + targets) */
-  int64_t unique_offsets;     /* distinct (level, offset) M2L spectra */
+  int64_t unique_offsets;     /* distinct (level, offset) pairs of the M2L lists */
   int32_t m2l_mode_per_level[32]; /* DEFMM_M2L_DENSE where the plan holds dense M2L
                                      matrices for that level, else DEFMM_M2L_FFT */
+  int64_t spectra;            /* stored Fourier-domain M2L spectra: one per class of
+                                 (level, offset) under the 48 signed axis permutations
+                                 (Sec. 4.3), i.e. per (level, sorted |offset|) */
 } defmm_stats;
 
 /* Writes the default parameters: L=5, ncrit=64, eta=1, hf_threshold=2,
@@ -228,6 +231,32 @@ const char* defmm_pass_name(int32_t i);
    operations (a complex multiply-add counts 8).  Either pointer may be NULL;
    each holds DEFMM_NUM_PASSES entries. */
 defmm_status defmm_workspace_pass_work(const defmm_workspace* ws, double* bytes, double* flops);
+
+/* Storage order of the Fourier-domain rows (spectra, M~, L~) for order L
+   (2..8), for inspection and tests.  Host only, no device use.  The
+   (2L-1)^3 frequencies xi (flattened kx + P ky + P^2 kz, each in [0, P)) are
+   stored as pairs (xi, -xi) at positions (2k, 2k+1), the pairs grouped into
+   `slices` slices of `cap` pairs, each slice a union of orbits of the 48
+   signed axis permutations (Sec. 4.3); *row = 2 * slices * cap.
+   freq (optional, *row entries): the frequency stored at each position, -1
+   for padding (stored as zero).  perm (optional, slices * 48 * 64 bytes):
+   for slice s, symmetry code r and pair k of the slice, byte
+   perm[(s * 48 + r) * 64 + k] = k' | swap << 7 says where the canonical
+   spectrum holds D[R_r^-1 xi_k]: pair k' of the same slice, second member
+   if swap.  Entries for k >= cap are 0.  Symmetry codes are those of
+   defmm_canonical_offset.  Errors: DEFMM_ERR_INVALID_ARG for L outside
+   2..8 or NULL slices/cap/row. */
+defmm_status defmm_fourier_layout(int32_t L, int32_t* slices, int32_t* cap, int32_t* row, int32_t* freq,
+                                  uint8_t* perm);
+
+/* Canonical representative of an M2L offset under the 48 signed axis
+   permutations (Sec. 4.3), for inspection and tests.  d: 3 integers; d0
+   receives the sorted absolute values (ascending) and *code the symmetry
+   r = 8 * p + signs with d_i = s_i * d0[pi(i)], s_i = -1 iff bit i of signs
+   is set, pi = the p-th permutation of (0,1,2) in lexicographic order.  The
+   spectrum of (level, d) equals that of (level, d0) read at R_r^-1 xi.
+   Errors: DEFMM_ERR_INVALID_ARG for NULL pointers. */
+defmm_status defmm_canonical_offset(const int32_t* d, int32_t* d0, int32_t* code);
 
 #ifdef __cplusplus
 }

@@ -32,6 +32,9 @@ def build(verbose: bool = False, jobs: int = 3) -> str:
     cmds = [["g++", "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-pthread", "-c",
              os.path.join(CSRC, "plan_build.cpp"), "-o", host_obj]]
     objs.append(host_obj)
+    layout_obj = os.path.join(bdir, "fourier_layout.o")
+    cmds.append(["g++", "-O2", "-std=c++17", "-fPIC", "-c", os.path.join(CSRC, "fourier_layout.cpp"), "-o", layout_obj])
+    objs.append(layout_obj)
     for src in ("kernels.hip", "capi.hip", "build_device.hip"):
         obj = os.path.join(bdir, src.replace(".hip", ".o"))
         cmds.append(["hipcc", *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])

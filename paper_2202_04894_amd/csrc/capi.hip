@@ -260,7 +260,7 @@ defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int
       std::vector<int32_t> pr(2 * H.m2l_src.size());
       for (size_t k = 0; k < H.m2l_src.size(); ++k) {
         pr[2 * k] = H.m2l_src[k];
-        pr[2 * k + 1] = H.m2l_off[k];
+        pr[2 * k + 1] = H.off_spec[H.m2l_off[k]];
       }
       P.m2l_pair = upload(P, pr);
     }
@@ -349,14 +349,21 @@ defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int
     P.nwi = (int64_t)H.wi_blk.size();
     P.seg_first = upload(P, H.seg_first);
     P.seg_count = upload(P, H.seg_count);
-    // spectra, one per distinct (level, delta), computed on the device in FP64
-    P.n_off = (int64_t)H.offsets.size();
-    if (P.n_off > 0) {
-      P.spectra = dalloc(P, (size_t)P.n_off * fourier_row(P.L) * csize(P));
-      std::vector<int32_t> lev(P.n_off), dl(3 * P.n_off);
-      for (int64_t i = 0; i < P.n_off; ++i) {
-        lev[i] = H.offsets[i].level;
-        for (int d = 0; d < 3; ++d) dl[3 * i + d] = H.offsets[i].d[d];
+    // Fourier layout and one spectrum per canonical (level, sorted |delta|),
+    // computed on the device in FP64
+    {
+      FourierLayout F = make_fourier_layout(P.L, m2l_slices(P.L), fourier_cap(P.L));
+      if (F.row != fourier_row(P.L)) throw std::logic_error("fourier layout: row length mismatch");
+      P.freq = upload(P, F.freq);
+      P.perm = upload(P, F.perm);
+    }
+    P.n_spec = (int64_t)H.canon.size();
+    if (P.n_spec > 0) {
+      P.spectra = dalloc(P, (size_t)2 * P.n_spec * fourier_row(P.L) * csize(P));
+      std::vector<int32_t> lev(P.n_spec), dl(3 * P.n_spec);
+      for (int64_t i = 0; i < P.n_spec; ++i) {
+        lev[i] = H.canon[i].level;
+        for (int d = 0; d < 3; ++d) dl[3 * i + d] = H.canon[i].d[d];
       }
       int32_t* dlev = upload(P, lev);
       int32_t* ddl = upload(P, dl);
@@ -413,6 +420,7 @@ defmm_status defmm_plan_stats(const defmm_plan* plan, defmm_stats* out) {
   out->eff_expansions = H.tx.nexp() + (P.same ? 0 : H.ty->nexp());
   out->m2l_expansions = (int64_t)H.m2f_exp.size() + (int64_t)H.m2l_tgt.size();
   out->unique_offsets = (int64_t)H.offsets.size();
+  out->spectra = (int64_t)H.canon.size();
   for (int l = 0; l < 32; ++l)
     out->m2l_mode_per_level[l] =
         (l < (int)P.dense_ok.size() && P.dense_ok[l]) ? DEFMM_M2L_DENSE : DEFMM_M2L_FFT;
@@ -748,6 +756,28 @@ defmm_status defmm_workspace_pass_times(defmm_workspace* ws, double* pass_ms, in
   return DEFMM_OK;
 }
 
+defmm_status defmm_fourier_layout(int32_t L, int32_t* slices, int32_t* cap, int32_t* row, int32_t* freq,
+                                  uint8_t* perm) {
+  if (L < 2 || L > 8 || !slices || !cap || !row) return fail(DEFMM_ERR_INVALID_ARG, "bad layout query");
+  try {
+    FourierLayout F = make_fourier_layout(L, m2l_slices(L), fourier_cap(L));
+    *slices = F.slices;
+    *cap = F.cap;
+    *row = F.row;
+    if (freq) std::memcpy(freq, F.freq.data(), F.freq.size() * sizeof(int32_t));
+    if (perm) std::memcpy(perm, F.perm.data(), F.perm.size());
+    return DEFMM_OK;
+  } catch (const std::exception& e) {
+    return fail(DEFMM_ERR_DEVICE, e.what());
+  }
+}
+
+defmm_status defmm_canonical_offset(const int32_t* d, int32_t* d0, int32_t* code) {
+  if (!d || !d0 || !code) return fail(DEFMM_ERR_INVALID_ARG, "NULL argument");
+  *code = canonical_offset(d, d0);
+  return DEFMM_OK;
+}
+
 const char* defmm_pass_name(int32_t i) {
   static const char* names[kNumPasses] = {"setup", "p2m", "m2m", "m2f", "m2l", "l2l", "p2p", "p2p_reduce",
                                           "l2p", "scatter", "f2l", "m2l_dense"};
@@ -778,7 +808,7 @@ defmm_status defmm_workspace_pass_work(const defmm_workspace* ws, double* bytes,
   const double m2f_per_row = 8 * (Pp * L * L * L + Pp * Pp * L * L + P3 * L);
   const int nlev = (int)H.lvl_m2f.size() - 1;
   std::vector<double> n_spec(nlev > 0 ? nlev : 0, 0.0);
-  for (const Offset& o : H.offsets)
+  for (const Offset& o : H.canon)
     if (o.level >= 0 && o.level < nlev) n_spec[o.level] += 1;
   for (int l = 0; l < nlev; ++l) {
     const double n_src = (double)(H.lvl_m2f[l + 1] - H.lvl_m2f[l]);

@@ -140,13 +140,16 @@ __global__ void k_zero(int64_t n, C2<R>* __restrict__ a) {
 }
 
 // ------------------------------------------------------------------ spectra
-// Fourier-domain M2L diagonal (eq. FourierDiagonal) for each (level, delta):
-// the kernel on the (2L-1)^3 difference grid (eq. CirculantKernel), a 3D DFT
-// in FP64, scaled by 1/P^3 so that F2L is a plain inverse sum.
+// Fourier-domain M2L diagonal (eq. FourierDiagonal) for each canonical
+// (level, delta): the kernel on the (2L-1)^3 difference grid (eq.
+// CirculantKernel), a 3D DFT in FP64, scaled by 1/P^3 so that F2L is a plain
+// inverse sum.  Two rows per spectrum: row 2o in the order of the Fourier
+// layout (freq), row 2o+1 with the two members of every pair exchanged, so
+// that a permuted read never needs to swap values after the load.
 template <typename R, int L>
 __global__ __launch_bounds__(256) void k_spectra(int64_t n, const int32_t* __restrict__ lev,
                                                  const int32_t* __restrict__ delta, double kappa, double D,
-                                                 C2<R>* __restrict__ S) {
+                                                 const int32_t* __restrict__ freq, C2<R>* __restrict__ S) {
   constexpr int P = 2 * L - 1, P3 = P * P * P;
   __shared__ C2<double> a[P3];
   __shared__ C2<double> W[P];
@@ -197,8 +200,11 @@ __global__ __launch_bounds__(256) void k_spectra(int64_t n, const int32_t* __res
     __syncthreads();
   }
   const double scale = 1.0 / (double)P3;
-  for (int i = tid; i < P3; i += blockDim.x)
-    S[o * fourier_row(L) + i] = {(R)(a[i].x * scale), (R)(a[i].y * scale)};
+  for (int p = tid; p < 2 * fourier_row(L); p += blockDim.x) {
+    const int q = p < fourier_row(L) ? p : (p - fourier_row(L)) ^ 1;
+    const int f = freq[q];
+    S[2 * o * fourier_row(L) + p] = f >= 0 ? C2<R>{(R)(a[f].x * scale), (R)(a[f].y * scale)} : C2<R>{(R)0, (R)0};
+  }
 }
 
 // ------------------------------------------------------------------ P2M
@@ -321,10 +327,12 @@ __global__ __launch_bounds__(round64(L* L* L)) void k_m2m(int64_t n, const int32
 
 // ------------------------------------------------------------------ M2F
 // M~ = DFT_P(pad(M)): three pruned 1D DFT passes (x, y, z) in LDS; only the
-// L nonzero inputs of each line enter the sums.
+// L nonzero inputs of each line enter the sums.  The row is written in the
+// order of the Fourier layout (freq), padding as zeros.
 template <typename R, int L>
 __global__ __launch_bounds__(256) void k_m2f(int64_t n, const int32_t* __restrict__ src,
-                                             const C2<R>* __restrict__ M, C2<R>* __restrict__ Mt) {
+                                             const int32_t* __restrict__ freq, const C2<R>* __restrict__ M,
+                                             C2<R>* __restrict__ Mt) {
   constexpr int P = 2 * L - 1, P3 = P * P * P, L3 = L * L * L;
   __shared__ C2<R> W[P];
   __shared__ C2<R> a[L3];
@@ -353,27 +361,35 @@ __global__ __launch_bounds__(256) void k_m2f(int64_t n, const int32_t* __restric
     c[i] = s;
   }
   __syncthreads();
-  for (int i = tid; i < P3; i += 256) {
-    int xy = i % (P * P), zi = i / (P * P);
+  for (int p = tid; p < fourier_row(L); p += 256) {
+    const int i = freq[p];
     C2<R> s = {(R)0, (R)0};
+    if (i >= 0) {
+      int xy = i % (P * P), zi = i / (P * P);
 #pragma unroll
-    for (int r = 0; r < L; ++r) cfma(s, c[xy + P * P * r], W[(zi * r) % P]);
-    Mt[item * fourier_row(L) + i] = s;
+      for (int r = 0; r < L; ++r) cfma(s, c[xy + P * P * r], W[(zi * r) % P]);
+    }
+    Mt[item * fourier_row(L) + p] = s;
   }
 }
 
 // ------------------------------------------------------------------ M2L + F2L
+// Spectrum entries of the M2L lists are codes (canonical id << 6) | symmetry
+// r: the offset's spectrum is the canonical row read through the layout's
+// pair permutation for r (D_{R delta}[xi] = D_delta[R^-1 xi], Sec. 4.3).
+//
 // For one target expansion: L~ = sum over its list of D_{l,delta} (.) M~_s
 // (Hadamard products, Sec. 2.3), then F2L = pruned inverse DFT restricted to
-// [0,L)^3 (the 1/P^3 is folded into the spectra).  Each thread owns NF
-// frequencies; operand loads are contiguous across the workgroup.
+// [0,L)^3 (the 1/P^3 is folded into the spectra).  Each thread owns NF row
+// positions; the permuted spectrum entries are gathered one by one.
 template <typename R, int L>
 __global__ __launch_bounds__(256) void k_m2l(int64_t ntgt, const int32_t* __restrict__ tgt,
                                              const int32_t* __restrict__ begin, const int2* __restrict__ pairs,
+                                             const int32_t* __restrict__ freq, const uint8_t* __restrict__ perm,
                                              const C2<R>* __restrict__ Mt, const C2<R>* __restrict__ S,
                                              C2<R>* __restrict__ Lx) {
-  constexpr int P = 2 * L - 1, P3 = P * P * P, L3 = L * L * L;
-  constexpr int NT = 256, NF = (P3 + NT - 1) / NT;
+  constexpr int P = 2 * L - 1, P3 = P * P * P, L3 = L * L * L, RW = fourier_row(L), SL = 2 * fourier_cap(L);
+  constexpr int NT = 256, NF = (RW + NT - 1) / NT;
   __shared__ C2<R> A[P3];
   __shared__ C2<R> B1[P * P * L];
   __shared__ C2<R> B2[P * L * L];
@@ -382,23 +398,34 @@ __global__ __launch_bounds__(256) void k_m2l(int64_t ntgt, const int32_t* __rest
   if (i >= ntgt) return;
   int tid = threadIdx.x;
   C2<R> acc[NF];
+  int pb[NF], qb[NF], sd[NF];
 #pragma unroll
-  for (int f = 0; f < NF; ++f) acc[f] = {(R)0, (R)0};
+  for (int f = 0; f < NF; ++f) {
+    acc[f] = {(R)0, (R)0};
+    const int p = min(tid + f * NT, RW - 1), sl = p / SL;
+    pb[f] = sl * 48 * 64 + (p % SL) / 2;  // perm entry of symmetry 0
+    qb[f] = sl * SL;                      // slice start
+    sd[f] = p & 1;                        // xi (0) or -xi (1) of the pair
+  }
   int kb = begin[i], ke = begin[i + 1];
   for (int k = kb; k < ke; ++k) {
     const int2 pr = pairs[k];
-    const C2<R>* ms = Mt + (int64_t)pr.x * fourier_row(L);
-    const C2<R>* ds = S + (int64_t)pr.y * fourier_row(L);
+    const C2<R>* ms = Mt + (int64_t)pr.x * RW;
+    const C2<R>* ds = S + (int64_t)(2 * (pr.y >> 6)) * RW;
+    const int r64 = (pr.y & 63) * 64;
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-      int xi = tid + f * NT;
-      if (xi < P3) cfma(acc[f], ds[xi], ms[xi]);
+      int p = tid + f * NT;
+      if (p < RW) {
+        const int pe = perm[pb[f] + r64];
+        cfma(acc[f], ds[qb[f] + 2 * (pe & 127) + (sd[f] ^ (pe >> 7))], ms[p]);
+      }
     }
   }
 #pragma unroll
   for (int f = 0; f < NF; ++f) {
-    int xi = tid + f * NT;
-    if (xi < P3) A[xi] = acc[f];
+    int p = tid + f * NT;
+    if (p < RW && freq[p] >= 0) A[freq[p]] = acc[f];
   }
   if (tid < P) W[tid] = expi<R>(2.0 * M_PI * (double)tid / (double)P);
   __syncthreads();
@@ -438,73 +465,75 @@ struct alignas(2 * sizeof(C2<R>)) C2x2 {
   C2<R> a, b;
 };
 
+// Loads one slice's pair permutations (48 symmetries x 64 lanes, bytes) into
+// LDS; the workgroup is one wave.
+__device__ __forceinline__ const uint8_t* load_slice_perm(const uint8_t* __restrict__ perm, int slice,
+                                                          uint32_t* lds) {
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(perm + (size_t)slice * 48 * 64);
+  for (int i = threadIdx.x; i < 48 * 16; i += 64) lds[i] = src[i];
+  __syncthreads();
+  return reinterpret_cast<const uint8_t*>(lds);
+}
+
+// The spectrum values of a lane's pair (xi, -xi) for spectrum code e: one
+// 16-byte (complex64) load from the canonical spectrum, from its pair-swapped
+// row when the symmetry maps xi onto the second member of a pair.
+template <typename R>
+__device__ __forceinline__ C2x2<R> spectrum_pair(const C2<R>* __restrict__ S, int e, int row, int slice_start,
+                                                 const uint8_t* pt, int lane) {
+  const int pe = pt[(e & 63) * 64 + lane];
+  return *reinterpret_cast<const C2x2<R>*>(S + (int64_t)(2 * (e >> 6) + (pe >> 7)) * row + slice_start +
+                                           2 * (pe & 127));
+}
+
 template <typename R, int L, int NSL>
 __global__ __launch_bounds__(64) void k_m2l_slice(int64_t ntgt, const int32_t* __restrict__ begin,
-                                                  const int2* __restrict__ pairs, const C2<R>* __restrict__ Mt,
-                                                  const C2<R>* __restrict__ S, C2<R>* __restrict__ Lt) {
+                                                  const int2* __restrict__ pairs, const uint8_t* __restrict__ perm,
+                                                  const C2<R>* __restrict__ Mt, const C2<R>* __restrict__ S,
+                                                  C2<R>* __restrict__ Lt) {
   // NSL slices (a multiple of 8): XCD j gets slices j, j+8, ...; the block
   // order walks all targets of one slice before the next on each XCD.
-  // Each lane owns two consecutive frequencies of the slice.
-  constexpr int P = 2 * L - 1, P3 = P * P * P, P3R = fourier_row(L);
-  constexpr int SL = P3R / NSL, NP = SL / 2, NF = (NP + 63) / 64, U = 8;
-  static_assert(SL % 2 == 0, "slices hold an even number of entries");
+  // Each lane owns one frequency pair (xi, -xi) of the slice.
+  constexpr int P3R = fourier_row(L), SL = P3R / NSL, NP = SL / 2, U = 8;
+  static_assert(SL % 2 == 0 && NP <= 64, "a slice holds at most 64 frequency pairs");
+  __shared__ uint32_t ptab[48 * 16];
   const int64_t b = blockIdx.x;
   const int xcd = (int)(b % 8);
   const int64_t j = b / 8;
   const int slice = xcd + 8 * (int)(j / ntgt);
   const int64_t i = j % ntgt;
   const int lane = threadIdx.x;
-  int fl[NF];
-  bool ok[NF];
-#pragma unroll
-  for (int f = 0; f < NF; ++f) {
-    int pi = lane + 64 * f;
-    ok[f] = pi < NP;
-    fl[f] = ok[f] ? slice * SL + 2 * pi : slice * SL;
-  }
-  C2<R> acc0[NF], acc1[NF];
-#pragma unroll
-  for (int f = 0; f < NF; ++f) acc0[f] = acc1[f] = {(R)0, (R)0};
+  const uint8_t* pt = load_slice_perm(perm, slice, ptab);
+  const bool ok = lane < NP;
+  const int s0 = slice * SL;
+  const int fl = ok ? s0 + 2 * lane : s0;
+  C2<R> acc0 = {(R)0, (R)0}, acc1 = {(R)0, (R)0};
   int k = begin[i];
   const int ke = begin[i + 1];
   for (; k + U <= ke; k += U) {
     int2 pr[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) pr[u] = pairs[k + u];
-    C2x2<R> mv[U][NF], dv[U][NF];
+    C2x2<R> mv[U], dv[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const C2<R>* ms = Mt + (int64_t)pr[u].x * P3R;
-      const C2<R>* ds = S + (int64_t)pr[u].y * P3R;
-#pragma unroll
-      for (int f = 0; f < NF; ++f) {
-        mv[u][f] = *reinterpret_cast<const C2x2<R>*>(ms + fl[f]);
-        dv[u][f] = *reinterpret_cast<const C2x2<R>*>(ds + fl[f]);
-      }
+      mv[u] = *reinterpret_cast<const C2x2<R>*>(Mt + (int64_t)pr[u].x * P3R + fl);
+      dv[u] = spectrum_pair(S, pr[u].y, P3R, s0, pt, lane);
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int f = 0; f < NF; ++f) {
-        cfma(acc0[f], dv[u][f].a, mv[u][f].a);
-        cfma(acc1[f], dv[u][f].b, mv[u][f].b);
-      }
+    for (int u = 0; u < U; ++u) {
+      cfma(acc0, dv[u].a, mv[u].a);
+      cfma(acc1, dv[u].b, mv[u].b);
+    }
   }
   for (; k < ke; ++k) {
     const int2 pr = pairs[k];
-    const C2<R>* ms = Mt + (int64_t)pr.x * P3R;
-    const C2<R>* ds = S + (int64_t)pr.y * P3R;
-#pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      C2x2<R> m = *reinterpret_cast<const C2x2<R>*>(ms + fl[f]);
-      C2x2<R> d = *reinterpret_cast<const C2x2<R>*>(ds + fl[f]);
-      cfma(acc0[f], d.a, m.a);
-      cfma(acc1[f], d.b, m.b);
-    }
+    const C2x2<R> m = *reinterpret_cast<const C2x2<R>*>(Mt + (int64_t)pr.x * P3R + fl);
+    const C2x2<R> d = spectrum_pair(S, pr.y, P3R, s0, pt, lane);
+    cfma(acc0, d.a, m.a);
+    cfma(acc1, d.b, m.b);
   }
-#pragma unroll
-  for (int f = 0; f < NF; ++f)
-    if (ok[f]) *reinterpret_cast<C2x2<R>*>(Lt + i * P3R + fl[f]) = C2x2<R>{acc0[f], acc1[f]};
+  if (ok) *reinterpret_cast<C2x2<R>*>(Lt + i * P3R + fl) = C2x2<R>{acc0, acc1};
 }
 
 // Hadamard accumulate over source runs.  A workgroup (one wave) handles one
@@ -513,69 +542,71 @@ __global__ __launch_bounds__(64) void k_m2l_slice(int64_t ntgt, const int32_t* _
 // Fourier-domain multipole once and the spectrum of every group target that
 // interacts with it, so one source load feeds several targets.  All branches
 // depend only on the run records (uniform), accumulators sit at fixed
-// register indices.
+// register indices.  Every load of a batch is issued before the first wait.
 template <typename R, int L, int NSL>
 __global__ __launch_bounds__(64) void k_m2l_runs(int64_t ngrp, const int32_t* __restrict__ grp_tfirst,
                                                  const int32_t* __restrict__ grp_tcount,
                                                  const int32_t* __restrict__ run_begin, const int32_t* __restrict__ runs,
-                                                 const C2<R>* __restrict__ Mt, const C2<R>* __restrict__ S,
-                                                 C2<R>* __restrict__ Lt) {
-  constexpr int P = 2 * L - 1, P3 = P * P * P, P3R = fourier_row(L);
-  constexpr int SL = P3R / NSL, NP = SL / 2, NF = (NP + 63) / 64, G = 8;
+                                                 const uint8_t* __restrict__ perm, const C2<R>* __restrict__ Mt,
+                                                 const C2<R>* __restrict__ S, C2<R>* __restrict__ Lt) {
+  constexpr int P3R = fourier_row(L), SL = P3R / NSL, NP = SL / 2, G = 8;
+  static_assert(SL % 2 == 0 && NP <= 64, "a slice holds at most 64 frequency pairs");
   constexpr int U = sizeof(R) == 4 ? 2 : 1;  // runs per batch
+  __shared__ uint32_t ptab[48 * 16];
   const int64_t b = blockIdx.x;
   const int xcd = (int)(b % 8);
   const int64_t j = b / 8;
   const int slice = xcd + 8 * (int)(j / ngrp);
   const int64_t g = j % ngrp;
   const int lane = threadIdx.x;
-  int fl[NF];
-  bool ok[NF];
+  const uint8_t* pt = load_slice_perm(perm, slice, ptab);
+  const bool ok = lane < NP;
+  const int s0 = slice * SL;
+  const int fl = ok ? s0 + 2 * lane : s0;
+  C2x2<R> acc[G];
 #pragma unroll
-  for (int f = 0; f < NF; ++f) {
-    int pi = lane + 64 * f;
-    ok[f] = pi < NP;
-    fl[f] = ok[f] ? slice * SL + 2 * pi : slice * SL;
-  }
-  C2x2<R> acc[G][NF];
-#pragma unroll
-  for (int t = 0; t < G; ++t)
-#pragma unroll
-    for (int f = 0; f < NF; ++f) acc[t][f] = C2x2<R>{{(R)0, (R)0}, {(R)0, (R)0}};
+  for (int t = 0; t < G; ++t) acc[t] = C2x2<R>{{(R)0, (R)0}, {(R)0, (R)0}};
   int r = run_begin[g];
   const int re = run_begin[g + 1];
+  // the next batch's run records are fetched (scalar loads) while this
+  // batch's vector loads are in flight
+  int nx[U][9];
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+#pragma unroll
+    for (int q = 0; q < 9; ++q) nx[u][q] = (r + u < re) ? runs[(int64_t)(r + u) * 9 + q] : (q == 0 ? -2 : -1);
   for (; r < re; r += U) {
     int rec[U][9];
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int q = 0; q < 9; ++q) rec[u][q] = (r + u < re) ? runs[(int64_t)(r + u) * 9 + q] : -1;
-    C2x2<R> mv[U][NF], dv[U][G][NF];
+      for (int q = 0; q < 9; ++q) rec[u][q] = nx[u][q];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int q = 0; q < 9; ++q) nx[u][q] = (r + U + u < re) ? runs[(int64_t)(r + U + u) * 9 + q] : (q == 0 ? -2 : -1);
+    // past the group's last run: re-read run 0's source row, no targets, so
+    // every batch issues its source loads unconditionally
+#pragma unroll
+    for (int u = 1; u < U; ++u)
+      if (rec[u][0] < 0) rec[u][0] = rec[0][0];
+    C2x2<R> mv[U], dv[U][G];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (rec[u][0] < 0) continue;
-      const C2<R>* ms = Mt + (int64_t)rec[u][0] * P3R;
-#pragma unroll
-      for (int f = 0; f < NF; ++f) mv[u][f] = *reinterpret_cast<const C2x2<R>*>(ms + fl[f]);
+      mv[u] = *reinterpret_cast<const C2x2<R>*>(Mt + (int64_t)rec[u][0] * P3R + fl);
 #pragma unroll
       for (int t = 0; t < G; ++t) {
         if (rec[u][1 + t] < 0) continue;
-        const C2<R>* ds = S + (int64_t)rec[u][1 + t] * P3R;
-#pragma unroll
-        for (int f = 0; f < NF; ++f) dv[u][t][f] = *reinterpret_cast<const C2x2<R>*>(ds + fl[f]);
+        dv[u][t] = spectrum_pair(S, rec[u][1 + t], P3R, s0, pt, lane);
       }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (rec[u][0] < 0) continue;
 #pragma unroll
       for (int t = 0; t < G; ++t) {
         if (rec[u][1 + t] < 0) continue;
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-          cfma(acc[t][f].a, dv[u][t][f].a, mv[u][f].a);
-          cfma(acc[t][f].b, dv[u][t][f].b, mv[u][f].b);
-        }
+        cfma(acc[t].a, dv[u][t].a, mv[u].a);
+        cfma(acc[t].b, dv[u][t].b, mv[u].b);
       }
     }
   }
@@ -583,17 +614,15 @@ __global__ __launch_bounds__(64) void k_m2l_runs(int64_t ngrp, const int32_t* __
   const int tc = grp_tcount[g];
 #pragma unroll
   for (int t = 0; t < G; ++t)
-    if (t < tc)
-#pragma unroll
-      for (int f = 0; f < NF; ++f)
-        if (ok[f]) *reinterpret_cast<C2x2<R>*>(Lt + (tf + t) * P3R + fl[f]) = acc[t][f];
+    if (t < tc && ok) *reinterpret_cast<C2x2<R>*>(Lt + (tf + t) * P3R + fl) = acc[t];
 }
 
 // F2L: pruned inverse DFT of each target's accumulated Fourier-domain local
 // expansion, restricted to [0,L)^3 (the 1/P^3 is folded into the spectra).
 template <typename R, int L>
 __global__ __launch_bounds__(256) void k_f2l(int64_t ntgt, const int32_t* __restrict__ tgt,
-                                             const C2<R>* __restrict__ Lt, C2<R>* __restrict__ Lx) {
+                                             const int32_t* __restrict__ freq, const C2<R>* __restrict__ Lt,
+                                             C2<R>* __restrict__ Lx) {
   constexpr int P = 2 * L - 1, P3 = P * P * P, L3 = L * L * L, NT = 256;
   __shared__ C2<R> A[P3];
   __shared__ C2<R> B1[P * P * L];
@@ -602,7 +631,10 @@ __global__ __launch_bounds__(256) void k_f2l(int64_t ntgt, const int32_t* __rest
   int64_t i = xcd_item(ntgt);
   if (i >= ntgt) return;
   int tid = threadIdx.x;
-  for (int j = tid; j < P3; j += NT) A[j] = Lt[i * fourier_row(L) + j];
+  for (int p = tid; p < fourier_row(L); p += NT) {
+    const int f = freq[p];
+    if (f >= 0) A[f] = Lt[i * fourier_row(L) + p];
+  }
   if (tid < P) W[tid] = expi<R>(2.0 * M_PI * (double)tid / (double)P);
   __syncthreads();
   for (int j = tid; j < P * P * L; j += NT) {
@@ -1127,9 +1159,9 @@ __global__ void k_p2p_reduce(int64_t nblk, const int32_t* __restrict__ blk_first
 
 template <typename R>
 static hipError_t spectra_impl(DevPlan& P, const int32_t* lev, const int32_t* delta, hipStream_t s) {
-  if (P.n_off == 0) return hipSuccess;
-  DEFMM_L_SWITCH(P.L, hipLaunchKernelGGL((k_spectra<R, LL>), dim3((unsigned)P.n_off), dim3(256), 0, s, P.n_off,
-                                         lev, delta, P.kappa, P.D, (C2<R>*)P.spectra));
+  if (P.n_spec == 0) return hipSuccess;
+  DEFMM_L_SWITCH(P.L, hipLaunchKernelGGL((k_spectra<R, LL>), dim3((unsigned)P.n_spec), dim3(256), 0, s, P.n_spec,
+                                         lev, delta, P.kappa, P.D, P.freq, (C2<R>*)P.spectra));
   return hipGetLastError();
 }
 
@@ -1285,7 +1317,7 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
     const int64_t rb = P.lvl_m2f[fr_lo[k]], nr = P.lvl_m2f[fr_hi[k]] - rb;
     if (nr == 0) continue;
     DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2f<R, LL>), dim3((unsigned)nr), dim3(256), 0, s, nr, P.m2f_exp + rb,
-                                         (const C2<R>*)M, Mt + rb * P3R));
+                                         P.freq, (const C2<R>*)M, Mt + rb * P3R));
   }
   tm.end();
 
@@ -1311,15 +1343,16 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
     if (nt == 0) continue;
     if (W.m2l_variant == 0) {
       DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l<R, LL>), dim3(xcd_grid(nt)), dim3(256), 0, s, nt, P.m2l_tgt + tb,
-                                           P.m2l_begin + tb, (const int2*)P.m2l_pair, (const C2<R>*)Mt, S, Lx));
+                                           P.m2l_begin + tb, (const int2*)P.m2l_pair, P.freq, P.perm,
+                                           (const C2<R>*)Mt, S, Lx));
     } else if (W.m2l_variant == 2) {
       const int64_t gb = P.lvl_grp[fr_lo[k]], ng = P.lvl_grp[fr_hi[k]] - gb;
       DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_runs<R, LL, m2l_slices(LL)>), dim3((unsigned)(m2l_slices(LL) * ng)),
                                            dim3(64), 0, s, ng, P.grp_tfirst + gb, P.grp_tcount + gb,
-                                           P.grp_run_begin + gb, P.runs, (const C2<R>*)Mt, S, Lt));
+                                           P.grp_run_begin + gb, P.runs, P.perm, (const C2<R>*)Mt, S, Lt));
     } else {
       DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_slice<R, LL, m2l_slices(LL)>), dim3((unsigned)(m2l_slices(LL) * nt)),
-                                           dim3(64), 0, s, nt, P.m2l_begin + tb, (const int2*)P.m2l_pair,
+                                           dim3(64), 0, s, nt, P.m2l_begin + tb, (const int2*)P.m2l_pair, P.perm,
                                            (const C2<R>*)Mt, S, Lt + tb * P3R));
     }
   }
@@ -1330,7 +1363,7 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
       const int64_t tb = P.m2l_level_tgt[fr_lo[k]], nt = P.m2l_level_tgt[fr_hi[k]] - tb;
       if (nt == 0) continue;
       DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_f2l<R, LL>), dim3(xcd_grid(nt)), dim3(256), 0, s, nt, P.m2l_tgt + tb,
-                                           (const C2<R>*)(Lt + tb * P3R), Lx));
+                                           P.freq, (const C2<R>*)(Lt + tb * P3R), Lx));
     }
   tm.end();
 

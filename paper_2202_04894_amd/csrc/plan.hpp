@@ -46,9 +46,21 @@ struct Tree {
   int64_t find_exp(int32_t c, int32_t u) const;
 };
 
-struct Offset {  // one distinct (level, delta) M2L spectrum
+struct Offset {  // one distinct (level, delta) M2L offset
   int32_t level, d[3], dir;
 };
+
+// Storage order of the Fourier-domain rows and the permutation tables that
+// read a canonical spectrum for any offset of its symmetry class.
+struct FourierLayout {
+  int L = 0, slices = 0, cap = 0, row = 0;  // row = 2 * slices * cap entries
+  std::vector<int32_t> freq;  // [row]: frequency kx + P ky + P^2 kz stored there, -1 = padding (zero)
+  std::vector<uint8_t> perm;  // [slices][48][64]: lane k of a slice, symmetry code r: pair (perm & 127), swapped if perm & 128
+};
+FourierLayout make_fourier_layout(int L, int slices, int cap);
+// Canonical offset d0 (sorted absolute components) and the symmetry code r
+// with d = R_r d0, (R_r v)_i = s_i v_{pi(i)}; r = 8 * (index of pi) + sign bits.
+int canonical_offset(const int32_t d[3], int32_t d0[3]);
 
 // Everything the matvec needs, built on the host.
 struct HostPlan {
@@ -67,6 +79,10 @@ struct HostPlan {
   struct M2L { int32_t t, s, off; };
   std::vector<M2L> m2l;
   std::vector<Offset> offsets;
+  // one spectrum per canonical (level, sorted |delta|); per offset id the
+  // spectrum code (canonical id << 6) | symmetry code
+  std::vector<Offset> canon;
+  std::vector<int32_t> off_spec;
   std::vector<int32_t> p2p_t, p2p_s;
   int64_t p2p_point_pairs = 0;
 
@@ -83,7 +99,7 @@ struct HostPlan {
   std::vector<int32_t> m2l_level_tgt;       // per level l: first target of level l (nlevels + 1)
   // M2L source runs: targets grouped by <= 8 (same level and direction,
   // consecutive); per group the pairs are merged by source into runs of
-  // 9 int32: Fourier row of the source, then the spectrum id for each of the
+  // 9 int32: Fourier row of the source, then the spectrum code for each of the
   // group's 8 targets (-1 where that target has no pair with this source).
   std::vector<int32_t> grp_tfirst, grp_tcount, grp_run_begin;  // run CSR: ngrp + 1
   std::vector<int32_t> runs;

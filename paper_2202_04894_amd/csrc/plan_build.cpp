@@ -8,8 +8,10 @@
 // definitions so that the lists are reproducible bit for bit; this file must
 // be compiled without floating-point contraction.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <numeric>
 #include <stdexcept>
 #include <tuple>
@@ -358,6 +360,26 @@ void mark_tree(HostPlan& hp, Tree& T, const std::vector<uint64_t>& own) {
 void build_tables(HostPlan& hp) {
   Tree& X = hp.tx;
   Tree& Y = *hp.ty;
+  // canonical spectra: offsets of one level related by a signed permutation
+  // share the spectrum of their sorted absolute offset (Sec. 4.3)
+  {
+    std::map<std::array<int32_t, 4>, int32_t> cid;
+    hp.canon.clear();
+    hp.off_spec.resize(hp.offsets.size());
+    for (size_t i = 0; i < hp.offsets.size(); ++i) {
+      const Offset& o = hp.offsets[i];
+      int32_t d0[3];
+      const int code = canonical_offset(o.d, d0);
+      const std::array<int32_t, 4> key{o.level, d0[0], d0[1], d0[2]};
+      auto it = cid.find(key);
+      if (it == cid.end()) {
+        it = cid.emplace(key, (int32_t)hp.canon.size()).first;
+        hp.canon.push_back(Offset{o.level, {d0[0], d0[1], d0[2]}, -1});
+      }
+      hp.off_spec[i] = (it->second << 6) | code;
+    }
+    if (hp.canon.size() >= (size_t(1) << 22)) throw std::runtime_error("too many distinct spectra");
+  }
   // P2M: every expansion of a source leaf
   for (int64_t e = 0; e < Y.nexp(); ++e)
     if (Y.leaf[Y.exp_cell[e]]) hp.p2m_exp.push_back((int32_t)e);
@@ -476,7 +498,7 @@ void build_tables(HostPlan& hp) {
           ent.clear();
           for (int64_t t = g0[g]; t < g0[g + 1]; ++t)
             for (int32_t k = hp.m2l_begin[t]; k < hp.m2l_begin[t + 1]; ++k)
-              ent.push_back({hp.m2l_src[k], (int32_t)(((t - g0[g]) << 28) | hp.m2l_off[k])});
+              ent.push_back({hp.m2l_src[k], (int32_t)(((t - g0[g]) << 28) | hp.off_spec[hp.m2l_off[k]])});
           std::sort(ent.begin(), ent.end());
           int32_t nr = 0;
           for (size_t a = 0; a < ent.size();) {

@@ -44,7 +44,8 @@ class _Stats(ctypes.Structure):
                 ("leaves", ctypes.c_int64), ("m2l_pairs", ctypes.c_int64),
                 ("p2p_cell_pairs", ctypes.c_int64), ("p2p_point_pairs", ctypes.c_int64),
                 ("eff_expansions", ctypes.c_int64), ("m2l_expansions", ctypes.c_int64),
-                ("unique_offsets", ctypes.c_int64), ("m2l_mode_per_level", ctypes.c_int32 * 32)]
+                ("unique_offsets", ctypes.c_int64), ("m2l_mode_per_level", ctypes.c_int32 * 32),
+                ("spectra", ctypes.c_int64)]
 
 
 EXPORTS = ["defmm_default_params", "defmm_plan_create", "defmm_plan_inspect_create", "defmm_plan_footprint", "defmm_plan_stats",
@@ -55,7 +56,7 @@ EXPORTS = ["defmm_default_params", "defmm_plan_create", "defmm_plan_inspect_crea
            "defmm_workspace_set_timing", "defmm_workspace_set_overlap", "defmm_workspace_pass_times",
            "defmm_workspace_autotune", "defmm_workspace_get_tuning", "defmm_workspace_set_tuning",
            "defmm_pass_name",
-           "defmm_workspace_pass_work"]
+           "defmm_workspace_pass_work", "defmm_fourier_layout", "defmm_canonical_offset"]
 
 _lib = None
 
@@ -96,6 +97,8 @@ def lib():
     L.defmm_pass_name.argtypes = [i32]
     L.defmm_pass_name.restype = ctypes.c_char_p
     L.defmm_workspace_pass_work.argtypes = [P, P, P]
+    L.defmm_fourier_layout.argtypes = [i32, P, P, P, P, P]
+    L.defmm_canonical_offset.argtypes = [P, P, P]
     for name in EXPORTS:
         if name not in ("defmm_status_string", "defmm_last_error", "defmm_pass_name"):
             getattr(L, name).restype = st
@@ -107,6 +110,27 @@ def _check(status):
     if status != 0:
         L = lib()
         raise DefmmError(f"{L.defmm_status_string(status).decode()}: {L.defmm_last_error().decode()}")
+
+
+def fourier_layout(L: int):
+    """Storage order of the Fourier-domain rows for order L (host only):
+    (slices, cap, freq [row] int32, perm [slices, 48, 64] uint8)."""
+    sl, cap, row = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().defmm_fourier_layout(L, ctypes.byref(sl), ctypes.byref(cap), ctypes.byref(row), None, None))
+    freq = np.zeros(row.value, np.int32)
+    perm = np.zeros((sl.value, 48, 64), np.uint8)
+    _check(lib().defmm_fourier_layout(L, ctypes.byref(sl), ctypes.byref(cap), ctypes.byref(row),
+                                      _np_ptr(freq), _np_ptr(perm)))
+    return sl.value, cap.value, freq, perm
+
+
+def canonical_offset(d):
+    """(sorted |d|, symmetry code) of an M2L offset (host only)."""
+    a = np.ascontiguousarray(d, dtype=np.int32)
+    d0 = np.zeros(3, np.int32)
+    code = ctypes.c_int32()
+    _check(lib().defmm_canonical_offset(_np_ptr(a), _np_ptr(d0), ctypes.byref(code)))
+    return d0, code.value
 
 
 def _np_ptr(a):

@@ -1,0 +1,113 @@
+"""Fourier-domain row layout and spectrum symmetry of libdefmm (host code, CPU).
+
+The library stores one M2L spectrum per class of (level, offset) under the 48
+signed axis permutations (Sec. 4.3) and reads an offset's spectrum from its
+class representative through a pair permutation of the frequencies.  These
+tests check the library's tables against numpy: the spectrum of an offset,
+computed directly with numpy.fft from the kernel on the difference grid
+(eqs. CirculantKernel, FourierDiagonal), must equal the canonical spectrum
+read through the tables at every stored position.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+from paper_2202_04894_amd import defmm
+from paper_2202_04894_amd import workloads as W
+
+
+def spectrum(L, h, delta, kappa):
+    """D = fftn(c) / P^3 of the circulant column c[j mod P] = G(h delta + h j / (L-1)),
+    j in [-(L-1), L-1]^3 (numpy convention, 1/P^3 folded in)."""
+    P = 2 * L - 1
+    j = np.arange(P)
+    j = np.where(j <= L - 1, j, j - P)
+    gx, gy, gz = np.meshgrid(j, j, j, indexing="ij")  # axis 0 = x
+    z = h * np.stack([delta[0] + gx / (L - 1), delta[1] + gy / (L - 1), delta[2] + gz / (L - 1)])
+    r = np.sqrt((z ** 2).sum(0))
+    c = np.exp(1j * kappa * r) / (4 * np.pi * r)
+    return np.fft.fftn(c) / P ** 3  # indexed [kx, ky, kz]
+
+
+def flat_value(D, P, f):
+    return D[f % P, (f // P) % P, f // (P * P)]
+
+
+@pytest.mark.parametrize("L", range(2, 9))
+def test_layout_stores_every_frequency_once_in_closed_slices(L):
+    P = 2 * L - 1
+    slices, cap, freq, perm = defmm.fourier_layout(L)
+    assert len(freq) == 2 * slices * cap
+    stored = freq[freq >= 0]
+    assert sorted(stored.tolist()) == list(range(P ** 3))
+    neg = lambda f: (-(f % P)) % P + P * ((-((f // P) % P)) % P) + P * P * ((-(f // (P * P))) % P)
+    for k in range(slices * cap):
+        a, b = freq[2 * k], freq[2 * k + 1]
+        if a < 0:
+            assert b < 0
+        elif a == 0:
+            assert b < 0  # the zero frequency has no partner
+        else:
+            assert b == neg(a)
+    # every permutation entry stays inside its slice and is a bijection on the slice's pairs
+    for s in range(slices):
+        used = [k for k in range(cap) if freq[2 * (s * cap + k)] >= 0]
+        for code in range(48):
+            tgt = sorted(int(perm[s, code, k] & 127) for k in used)
+            assert tgt == used, (s, code)
+            assert all(perm[s, code, k] == 0 for k in range(cap, 64))
+
+
+def test_canonical_offset_reproduces_the_offset():
+    perms = list(itertools.permutations(range(3)))
+    rng = np.random.default_rng(5)
+    for d in list(itertools.product(range(-2, 3), repeat=3)) + [tuple(rng.integers(-40, 41, 3)) for _ in range(50)]:
+        d0, code = defmm.canonical_offset(d)
+        assert list(d0) == sorted(abs(x) for x in d)
+        pi = perms[code >> 3]
+        back = [(-1 if (code >> i) & 1 else 1) * d0[pi[i]] for i in range(3)]
+        assert back == list(d), (d, d0, code)
+
+
+@pytest.mark.parametrize("L,kappa", [(3, 5.0), (4, 0.0), (5, 12.0), (6, 3.0)])
+def test_offset_spectrum_equals_permuted_canonical_spectrum(L, kappa):
+    """D_delta at every stored position = the canonical spectrum D_delta0 read
+    at the position the tables name (pair k', swapped or not), as the M2L
+    kernels read it."""
+    P = 2 * L - 1
+    slices, cap, freq, perm = defmm.fourier_layout(L)
+    h = 0.37
+    rng = np.random.default_rng(L)
+    offsets = [(2, -3, 1), (-2, 0, 3), (0, 0, -2), (3, 3, -3), (-4, 1, 1)]
+    offsets += [tuple(int(x) for x in rng.integers(-5, 6, 3)) for _ in range(6)]
+    for d in offsets:
+        if max(abs(x) for x in d) < 2:
+            continue
+        d0, code = defmm.canonical_offset(d)
+        D = spectrum(L, h, d, kappa)
+        D0 = spectrum(L, h, d0, kappa)
+        scale = np.abs(D).max()
+        for s in range(slices):
+            for k in range(cap):
+                for side in (0, 1):
+                    p = 2 * (s * cap + k) + side
+                    if freq[p] < 0:
+                        continue
+                    e = int(perm[s, code, k])
+                    q = 2 * (s * cap + (e & 127)) + (side ^ (e >> 7))
+                    assert freq[q] >= 0
+                    got = flat_value(D0, P, freq[q])
+                    want = flat_value(D, P, freq[p])
+                    assert abs(got - want) <= 1e-12 * scale, (d, s, k, side)
+
+
+def test_plan_stores_one_spectrum_per_symmetry_class():
+    X = W.GENERATORS["sphere"](6000, 3)
+    p = defmm.Plan.inspect(X, None, 40.0, defmm.Params(order_L=4, ncrit=16))
+    st = p.stats()
+    m = p.m2l()
+    keys = {(int(l),) + tuple(sorted(abs(int(x)) for x in d)) for l, d in zip(m["level"], m["delta"])}
+    assert st["spectra"] == len(keys)
+    assert st["unique_offsets"] == len({(int(l),) + tuple(int(x) for x in d) for l, d in zip(m["level"], m["delta"])})
+    assert st["spectra"] * 10 < st["unique_offsets"]
