@@ -51,6 +51,12 @@ typedef enum {
 typedef enum { DEFMM_M2L_AUTO = 0, DEFMM_M2L_FFT = 1, DEFMM_M2L_DENSE = 2 } defmm_m2l_mode;
 
 #define DEFMM_SAME_POINTS 1u /* X and Y are the same set: one tree; q and p share its order */
+/* Store one M2L spectrum per class of (level, offset) under the 48 signed
+   axis permutations (Sec. 4.3) and read it through a frequency permutation,
+   instead of one per distinct (level, offset): 20-40x less spectrum memory,
+   a slower Fourier-path M2L.  Plans whose per-offset table would exceed
+   8 GiB use this form whatever the flag. */
+#define DEFMM_COMPRESS_SPECTRA 2u
 
 typedef struct {
   int32_t order_L;      /* interpolation nodes per dimension, 2..8 (padded FFT length 2L-1) */
@@ -61,7 +67,7 @@ typedef struct {
   int32_t dir_refine;   /* extra 4-fold refinements of the cube-face direction set, 0..4 */
   int32_t precision;    /* defmm_precision */
   int32_t m2l_mode;     /* defmm_m2l_mode */
-  uint32_t flags;       /* DEFMM_SAME_POINTS */
+  uint32_t flags;       /* DEFMM_SAME_POINTS | DEFMM_COMPRESS_SPECTRA */
 } defmm_params;
 
 typedef struct defmm_plan defmm_plan;           /* opaque */
@@ -80,9 +86,11 @@ typedef struct {
   int64_t unique_offsets;     /* distinct (level, offset) pairs of the M2L lists */
   int32_t m2l_mode_per_level[32]; /* DEFMM_M2L_DENSE where the plan holds dense M2L
                                      matrices for that level, else DEFMM_M2L_FFT */
-  int64_t spectra;            /* stored Fourier-domain M2L spectra: one per class of
-                                 (level, offset) under the 48 signed axis permutations
+  int64_t spectra;            /* stored Fourier-domain M2L spectra: unique_offsets, or,
+                                 for a compressed plan, one per class of (level,
+                                 offset) under the 48 signed axis permutations
                                  (Sec. 4.3), i.e. per (level, sorted |offset|) */
+  int32_t compressed_spectra; /* 1 if the plan reads spectra through the symmetry */
 } defmm_stats;
 
 /* Writes the default parameters: L=5, ncrit=64, eta=1, hf_threshold=2,

@@ -175,6 +175,7 @@ static defmm_status plan_build(defmm_plan* plan, const double* X, int64_t nx, co
   bp.same_points = same;
   bp.kappa = kappa;
   bp.dense_tables = prm->m2l_mode != DEFMM_M2L_FFT;
+  bp.compress_spectra = (prm->flags & DEFMM_COMPRESS_SPECTRA) != 0;
   if (host_pointers) {
     for (int64_t i = 0; i < 3 * nx; ++i)
       if (!std::isfinite(X[i])) return fail(DEFMM_ERR_INVALID_ARG, "non-finite coordinate in X");
@@ -349,21 +350,24 @@ defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int
     P.nwi = (int64_t)H.wi_blk.size();
     P.seg_first = upload(P, H.seg_first);
     P.seg_count = upload(P, H.seg_count);
-    // Fourier layout and one spectrum per canonical (level, sorted |delta|),
-    // computed on the device in FP64
+    // Fourier layout and the spectra, computed on the device in FP64: one per
+    // distinct (level, delta), or, compressed, one per canonical (level,
+    // sorted |delta|) in two rows (layout order, pair members exchanged)
     {
       FourierLayout F = make_fourier_layout(P.L, m2l_slices(P.L), fourier_cap(P.L));
       if (F.row != fourier_row(P.L)) throw std::logic_error("fourier layout: row length mismatch");
       P.freq = upload(P, F.freq);
       P.perm = upload(P, F.perm);
     }
-    P.n_spec = (int64_t)H.canon.size();
+    P.sym = H.compressed;
+    const std::vector<Offset>& spec = P.sym ? H.canon : H.offsets;
+    P.n_spec = (int64_t)spec.size();
     if (P.n_spec > 0) {
-      P.spectra = dalloc(P, (size_t)2 * P.n_spec * fourier_row(P.L) * csize(P));
+      P.spectra = dalloc(P, (size_t)(P.sym ? 2 : 1) * P.n_spec * fourier_row(P.L) * csize(P));
       std::vector<int32_t> lev(P.n_spec), dl(3 * P.n_spec);
       for (int64_t i = 0; i < P.n_spec; ++i) {
-        lev[i] = H.canon[i].level;
-        for (int d = 0; d < 3; ++d) dl[3 * i + d] = H.canon[i].d[d];
+        lev[i] = spec[i].level;
+        for (int d = 0; d < 3; ++d) dl[3 * i + d] = spec[i].d[d];
       }
       int32_t* dlev = upload(P, lev);
       int32_t* ddl = upload(P, dl);
@@ -420,7 +424,8 @@ defmm_status defmm_plan_stats(const defmm_plan* plan, defmm_stats* out) {
   out->eff_expansions = H.tx.nexp() + (P.same ? 0 : H.ty->nexp());
   out->m2l_expansions = (int64_t)H.m2f_exp.size() + (int64_t)H.m2l_tgt.size();
   out->unique_offsets = (int64_t)H.offsets.size();
-  out->spectra = (int64_t)H.canon.size();
+  out->spectra = (int64_t)(H.compressed ? H.canon.size() : H.offsets.size());
+  out->compressed_spectra = H.compressed ? 1 : 0;
   for (int l = 0; l < 32; ++l)
     out->m2l_mode_per_level[l] =
         (l < (int)P.dense_ok.size() && P.dense_ok[l]) ? DEFMM_M2L_DENSE : DEFMM_M2L_FFT;
@@ -808,7 +813,7 @@ defmm_status defmm_workspace_pass_work(const defmm_workspace* ws, double* bytes,
   const double m2f_per_row = 8 * (Pp * L * L * L + Pp * Pp * L * L + P3 * L);
   const int nlev = (int)H.lvl_m2f.size() - 1;
   std::vector<double> n_spec(nlev > 0 ? nlev : 0, 0.0);
-  for (const Offset& o : H.canon)
+  for (const Offset& o : (P.sym ? H.canon : H.offsets))
     if (o.level >= 0 && o.level < nlev) n_spec[o.level] += 1;
   for (int l = 0; l < nlev; ++l) {
     const double n_src = (double)(H.lvl_m2f[l + 1] - H.lvl_m2f[l]);

@@ -12,17 +12,6 @@
 
 namespace defmm {
 
-// Frequency slices of the M2L kernels (a multiple of 8: one set per XCD) and
-// the Fourier-domain row: frequencies stored as (xi, -xi) pairs, grouped
-// into m2l_slices(L) slices of fourier_cap(L) pairs, each slice closed under
-// the 48 symmetries of the spectra (the packing of the symmetry orbits that
-// make_fourier_layout builds fits these capacities).
-__host__ __device__ constexpr int m2l_slices(int L) { return L <= 5 ? 8 : (L == 6 ? 16 : 32); }
-__host__ __device__ constexpr int fourier_cap(int L) {
-  return L == 2 ? 6 : L == 3 ? 12 : L == 4 ? 24 : L == 5 ? 48 : L == 6 ? 48 : L == 7 ? 36 : 60;
-}
-__host__ __device__ constexpr int fourier_row(int L) { return 2 * m2l_slices(L) * fourier_cap(L); }
-
 // Dense M2L: L^3 padded to a multiple of 16 (the MFMA tile edge).
 __host__ __device__ constexpr int dense_pad(int L) { return ((L * L * L + 15) / 16) * 16; }
 
@@ -105,9 +94,10 @@ struct DevPlan {
   int32_t *wi_blk = nullptr, *wi_seg_begin = nullptr;
   int64_t nwi = 0;
   int32_t *seg_first = nullptr, *seg_count = nullptr;
-  void* spectra = nullptr;  // n_spec canonical spectra x 2 rows (layout order, pairs exchanged) x fourier_row(L)
-                            // complex (plan precision), scaled by 1/P^3
+  void* spectra = nullptr;  // n_spec x fourier_row(L) complex (plan precision), scaled by 1/P^3; compressed
+                            // (sym): n_spec canonical spectra x 2 rows (layout order, pair members exchanged)
   int64_t n_spec = 0;
+  bool sym = false;
   int32_t* freq = nullptr;  // Fourier layout: frequency at each row position (-1 = padding)
   uint8_t* perm = nullptr;  // Fourier layout: [slices][48][64] pair permutation per symmetry code
   std::vector<void*> allocs;

@@ -143,13 +143,14 @@ __global__ void k_zero(int64_t n, C2<R>* __restrict__ a) {
 // Fourier-domain M2L diagonal (eq. FourierDiagonal) for each canonical
 // (level, delta): the kernel on the (2L-1)^3 difference grid (eq.
 // CirculantKernel), a 3D DFT in FP64, scaled by 1/P^3 so that F2L is a plain
-// inverse sum.  Two rows per spectrum: row 2o in the order of the Fourier
-// layout (freq), row 2o+1 with the two members of every pair exchanged, so
-// that a permuted read never needs to swap values after the load.
+// inverse sum, in the order of the Fourier layout (freq).  With nrow = 2
+// (compressed spectra) a second row holds the two members of every pair
+// exchanged, so that a permuted read never swaps values after the load.
 template <typename R, int L>
 __global__ __launch_bounds__(256) void k_spectra(int64_t n, const int32_t* __restrict__ lev,
                                                  const int32_t* __restrict__ delta, double kappa, double D,
-                                                 const int32_t* __restrict__ freq, C2<R>* __restrict__ S) {
+                                                 const int32_t* __restrict__ freq, int nrow,
+                                                 C2<R>* __restrict__ S) {
   constexpr int P = 2 * L - 1, P3 = P * P * P;
   __shared__ C2<double> a[P3];
   __shared__ C2<double> W[P];
@@ -200,10 +201,10 @@ __global__ __launch_bounds__(256) void k_spectra(int64_t n, const int32_t* __res
     __syncthreads();
   }
   const double scale = 1.0 / (double)P3;
-  for (int p = tid; p < 2 * fourier_row(L); p += blockDim.x) {
+  for (int p = tid; p < nrow * fourier_row(L); p += blockDim.x) {
     const int q = p < fourier_row(L) ? p : (p - fourier_row(L)) ^ 1;
     const int f = freq[q];
-    S[2 * o * fourier_row(L) + p] = f >= 0 ? C2<R>{(R)(a[f].x * scale), (R)(a[f].y * scale)} : C2<R>{(R)0, (R)0};
+    S[nrow * o * fourier_row(L) + p] = f >= 0 ? C2<R>{(R)(a[f].x * scale), (R)(a[f].y * scale)} : C2<R>{(R)0, (R)0};
   }
 }
 
@@ -326,6 +327,10 @@ __global__ __launch_bounds__(round64(L* L* L)) void k_m2m(int64_t n, const int32
 }
 
 // ------------------------------------------------------------------ M2F
+// Expansions per workgroup of M2F and F2L: the layout's frequency table is
+// staged in LDS once for all of them.
+constexpr int kFourierItems = 4;
+
 // M~ = DFT_P(pad(M)): three pruned 1D DFT passes (x, y, z) in LDS; only the
 // L nonzero inputs of each line enter the sums.  The row is written in the
 // order of the Fourier layout (freq), padding as zeros.
@@ -338,38 +343,44 @@ __global__ __launch_bounds__(256) void k_m2f(int64_t n, const int32_t* __restric
   __shared__ C2<R> a[L3];
   __shared__ C2<R> b[P * L * L];
   __shared__ C2<R> c[P * P * L];
-  int64_t item = blockIdx.x;
-  if (item >= n) return;
-  int e = src[item];
+  __shared__ int32_t fq[fourier_row(L)];
+  const int64_t i0 = (int64_t)blockIdx.x * kFourierItems;
+  if (i0 >= n) return;
+  const int64_t i1 = min(n, i0 + kFourierItems);
   int tid = threadIdx.x;
   if (tid < P) W[tid] = expi<R>(-2.0 * M_PI * (double)tid / (double)P);
-  for (int i = tid; i < L3; i += 256) a[i] = M[(int64_t)e * L3 + i];
-  __syncthreads();
-  for (int i = tid; i < P * L * L; i += 256) {
-    int xi = i % P, rest = i / P;
-    C2<R> s = {(R)0, (R)0};
+  for (int p = tid; p < fourier_row(L); p += 256) fq[p] = freq[p];
+  for (int64_t item = i0; item < i1; ++item) {
+    int e = src[item];
+    for (int i = tid; i < L3; i += 256) a[i] = M[(int64_t)e * L3 + i];
+    __syncthreads();
+    for (int i = tid; i < P * L * L; i += 256) {
+      int xi = i % P, rest = i / P;
+      C2<R> s = {(R)0, (R)0};
 #pragma unroll
-    for (int r = 0; r < L; ++r) cfma(s, a[r + L * rest], W[(xi * r) % P]);
-    b[i] = s;
-  }
-  __syncthreads();
-  for (int i = tid; i < P * P * L; i += 256) {
-    int xi = i % P, yi = (i / P) % P, rz = i / (P * P);
-    C2<R> s = {(R)0, (R)0};
-#pragma unroll
-    for (int r = 0; r < L; ++r) cfma(s, b[xi + P * (r + L * rz)], W[(yi * r) % P]);
-    c[i] = s;
-  }
-  __syncthreads();
-  for (int p = tid; p < fourier_row(L); p += 256) {
-    const int i = freq[p];
-    C2<R> s = {(R)0, (R)0};
-    if (i >= 0) {
-      int xy = i % (P * P), zi = i / (P * P);
-#pragma unroll
-      for (int r = 0; r < L; ++r) cfma(s, c[xy + P * P * r], W[(zi * r) % P]);
+      for (int r = 0; r < L; ++r) cfma(s, a[r + L * rest], W[(xi * r) % P]);
+      b[i] = s;
     }
-    Mt[item * fourier_row(L) + p] = s;
+    __syncthreads();
+    for (int i = tid; i < P * P * L; i += 256) {
+      int xi = i % P, yi = (i / P) % P, rz = i / (P * P);
+      C2<R> s = {(R)0, (R)0};
+#pragma unroll
+      for (int r = 0; r < L; ++r) cfma(s, b[xi + P * (r + L * rz)], W[(yi * r) % P]);
+      c[i] = s;
+    }
+    __syncthreads();
+    for (int p = tid; p < fourier_row(L); p += 256) {
+      const int i = fq[p];
+      C2<R> s = {(R)0, (R)0};
+      if (i >= 0) {
+        int xy = i % (P * P), zi = i / (P * P);
+#pragma unroll
+        for (int r = 0; r < L; ++r) cfma(s, c[xy + P * P * r], W[(zi * r) % P]);
+      }
+      Mt[item * fourier_row(L) + p] = s;
+    }
+    __syncthreads();
   }
 }
 
@@ -386,7 +397,7 @@ template <typename R, int L>
 __global__ __launch_bounds__(256) void k_m2l(int64_t ntgt, const int32_t* __restrict__ tgt,
                                              const int32_t* __restrict__ begin, const int2* __restrict__ pairs,
                                              const int32_t* __restrict__ freq, const uint8_t* __restrict__ perm,
-                                             const C2<R>* __restrict__ Mt, const C2<R>* __restrict__ S,
+                                             int sym, const C2<R>* __restrict__ Mt, const C2<R>* __restrict__ S,
                                              C2<R>* __restrict__ Lx) {
   constexpr int P = 2 * L - 1, P3 = P * P * P, L3 = L * L * L, RW = fourier_row(L), SL = 2 * fourier_cap(L);
   constexpr int NT = 256, NF = (RW + NT - 1) / NT;
@@ -411,13 +422,13 @@ __global__ __launch_bounds__(256) void k_m2l(int64_t ntgt, const int32_t* __rest
   for (int k = kb; k < ke; ++k) {
     const int2 pr = pairs[k];
     const C2<R>* ms = Mt + (int64_t)pr.x * RW;
-    const C2<R>* ds = S + (int64_t)(2 * (pr.y >> 6)) * RW;
+    const C2<R>* ds = S + (int64_t)((sym ? 2 : 1) * (pr.y >> 6)) * RW;
     const int r64 = (pr.y & 63) * 64;
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       int p = tid + f * NT;
       if (p < RW) {
-        const int pe = perm[pb[f] + r64];
+        const int pe = sym ? perm[pb[f] + r64] : (p % SL) / 2;
         cfma(acc[f], ds[qb[f] + 2 * (pe & 127) + (sd[f] ^ (pe >> 7))], ms[p]);
       }
     }
@@ -475,18 +486,24 @@ __device__ __forceinline__ const uint8_t* load_slice_perm(const uint8_t* __restr
   return reinterpret_cast<const uint8_t*>(lds);
 }
 
-// The spectrum values of a lane's pair (xi, -xi) for spectrum code e: one
-// 16-byte (complex64) load from the canonical spectrum, from its pair-swapped
-// row when the symmetry maps xi onto the second member of a pair.
-template <typename R>
+// The spectrum values of a lane's pair (xi, -xi) for spectrum code e, one
+// 16-byte (complex64) load.  Per-offset spectra (SYM false): the lane's own
+// pair of row e >> 6.  Compressed spectra: the pair of canonical spectrum
+// e >> 6 that the slice's permutation table names for symmetry e & 63, from
+// the pair-exchanged row when the symmetry maps xi onto a second member.
+template <bool SYM, typename R>
 __device__ __forceinline__ C2x2<R> spectrum_pair(const C2<R>* __restrict__ S, int e, int row, int slice_start,
-                                                 const uint8_t* pt, int lane) {
-  const int pe = pt[(e & 63) * 64 + lane];
-  return *reinterpret_cast<const C2x2<R>*>(S + (int64_t)(2 * (e >> 6) + (pe >> 7)) * row + slice_start +
-                                           2 * (pe & 127));
+                                                 const uint8_t* pt, int lane, int fl) {
+  if constexpr (SYM) {
+    const int pe = pt[(e & 63) * 64 + lane];
+    return *reinterpret_cast<const C2x2<R>*>(S + (int64_t)(2 * (e >> 6) + (pe >> 7)) * row + slice_start +
+                                             2 * (pe & 127));
+  } else {
+    return *reinterpret_cast<const C2x2<R>*>(S + (int64_t)(e >> 6) * row + fl);
+  }
 }
 
-template <typename R, int L, int NSL>
+template <typename R, int L, int NSL, bool SYM>
 __global__ __launch_bounds__(64) void k_m2l_slice(int64_t ntgt, const int32_t* __restrict__ begin,
                                                   const int2* __restrict__ pairs, const uint8_t* __restrict__ perm,
                                                   const C2<R>* __restrict__ Mt, const C2<R>* __restrict__ S,
@@ -503,7 +520,7 @@ __global__ __launch_bounds__(64) void k_m2l_slice(int64_t ntgt, const int32_t* _
   const int slice = xcd + 8 * (int)(j / ntgt);
   const int64_t i = j % ntgt;
   const int lane = threadIdx.x;
-  const uint8_t* pt = load_slice_perm(perm, slice, ptab);
+  const uint8_t* pt = SYM ? load_slice_perm(perm, slice, ptab) : nullptr;
   const bool ok = lane < NP;
   const int s0 = slice * SL;
   const int fl = ok ? s0 + 2 * lane : s0;
@@ -518,7 +535,7 @@ __global__ __launch_bounds__(64) void k_m2l_slice(int64_t ntgt, const int32_t* _
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       mv[u] = *reinterpret_cast<const C2x2<R>*>(Mt + (int64_t)pr[u].x * P3R + fl);
-      dv[u] = spectrum_pair(S, pr[u].y, P3R, s0, pt, lane);
+      dv[u] = spectrum_pair<SYM>(S, pr[u].y, P3R, s0, pt, lane, fl);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -529,7 +546,7 @@ __global__ __launch_bounds__(64) void k_m2l_slice(int64_t ntgt, const int32_t* _
   for (; k < ke; ++k) {
     const int2 pr = pairs[k];
     const C2x2<R> m = *reinterpret_cast<const C2x2<R>*>(Mt + (int64_t)pr.x * P3R + fl);
-    const C2x2<R> d = spectrum_pair(S, pr.y, P3R, s0, pt, lane);
+    const C2x2<R> d = spectrum_pair<SYM>(S, pr.y, P3R, s0, pt, lane, fl);
     cfma(acc0, d.a, m.a);
     cfma(acc1, d.b, m.b);
   }
@@ -543,7 +560,7 @@ __global__ __launch_bounds__(64) void k_m2l_slice(int64_t ntgt, const int32_t* _
 // interacts with it, so one source load feeds several targets.  All branches
 // depend only on the run records (uniform), accumulators sit at fixed
 // register indices.  Every load of a batch is issued before the first wait.
-template <typename R, int L, int NSL>
+template <typename R, int L, int NSL, bool SYM>
 __global__ __launch_bounds__(64) void k_m2l_runs(int64_t ngrp, const int32_t* __restrict__ grp_tfirst,
                                                  const int32_t* __restrict__ grp_tcount,
                                                  const int32_t* __restrict__ run_begin, const int32_t* __restrict__ runs,
@@ -559,7 +576,7 @@ __global__ __launch_bounds__(64) void k_m2l_runs(int64_t ngrp, const int32_t* __
   const int slice = xcd + 8 * (int)(j / ngrp);
   const int64_t g = j % ngrp;
   const int lane = threadIdx.x;
-  const uint8_t* pt = load_slice_perm(perm, slice, ptab);
+  const uint8_t* pt = SYM ? load_slice_perm(perm, slice, ptab) : nullptr;
   const bool ok = lane < NP;
   const int s0 = slice * SL;
   const int fl = ok ? s0 + 2 * lane : s0;
@@ -597,7 +614,7 @@ __global__ __launch_bounds__(64) void k_m2l_runs(int64_t ngrp, const int32_t* __
 #pragma unroll
       for (int t = 0; t < G; ++t) {
         if (rec[u][1 + t] < 0) continue;
-        dv[u][t] = spectrum_pair(S, rec[u][1 + t], P3R, s0, pt, lane);
+        dv[u][t] = spectrum_pair<SYM>(S, rec[u][1 + t], P3R, s0, pt, lane, fl);
       }
     }
 #pragma unroll
@@ -628,37 +645,46 @@ __global__ __launch_bounds__(256) void k_f2l(int64_t ntgt, const int32_t* __rest
   __shared__ C2<R> B1[P * P * L];
   __shared__ C2<R> B2[P * L * L];
   __shared__ C2<R> W[P];
-  int64_t i = xcd_item(ntgt);
-  if (i >= ntgt) return;
+  __shared__ int32_t fq[fourier_row(L)];
+  const int64_t nch = (ntgt + kFourierItems - 1) / kFourierItems;
+  const int64_t ch = xcd_item(nch);
+  if (ch >= nch) return;
+  const int64_t i1 = min(ntgt, (ch + 1) * kFourierItems);
   int tid = threadIdx.x;
-  for (int p = tid; p < fourier_row(L); p += NT) {
-    const int f = freq[p];
-    if (f >= 0) A[f] = Lt[i * fourier_row(L) + p];
-  }
+  for (int p = tid; p < fourier_row(L); p += NT) fq[p] = freq[p];
   if (tid < P) W[tid] = expi<R>(2.0 * M_PI * (double)tid / (double)P);
   __syncthreads();
-  for (int j = tid; j < P * P * L; j += NT) {
-    int xy = j % (P * P), kz = j / (P * P);
-    C2<R> s = {(R)0, (R)0};
+  for (int64_t i = ch * kFourierItems; i < i1; ++i) {
+    for (int p = tid; p < fourier_row(L); p += NT) {
+      const int f = fq[p];
+      const C2<R> v = Lt[i * fourier_row(L) + p];
+      if (f >= 0) A[f] = v;
+    }
+    __syncthreads();
+    for (int j = tid; j < P * P * L; j += NT) {
+      int xy = j % (P * P), kz = j / (P * P);
+      C2<R> s = {(R)0, (R)0};
 #pragma unroll
-    for (int m = 0; m < P; ++m) cfma(s, A[xy + P * P * m], W[(m * kz) % P]);
-    B1[j] = s;
-  }
-  __syncthreads();
-  for (int j = tid; j < P * L * L; j += NT) {
-    int xi = j % P, ky = (j / P) % L, kz = j / (P * L);
-    C2<R> s = {(R)0, (R)0};
+      for (int m = 0; m < P; ++m) cfma(s, A[xy + P * P * m], W[(m * kz) % P]);
+      B1[j] = s;
+    }
+    __syncthreads();
+    for (int j = tid; j < P * L * L; j += NT) {
+      int xi = j % P, ky = (j / P) % L, kz = j / (P * L);
+      C2<R> s = {(R)0, (R)0};
 #pragma unroll
-    for (int m = 0; m < P; ++m) cfma(s, B1[xi + P * m + P * P * kz], W[(m * ky) % P]);
-    B2[j] = s;
-  }
-  __syncthreads();
-  for (int j = tid; j < L3; j += NT) {
-    int kx = j % L, kyz = j / L;
-    C2<R> s = {(R)0, (R)0};
+      for (int m = 0; m < P; ++m) cfma(s, B1[xi + P * m + P * P * kz], W[(m * ky) % P]);
+      B2[j] = s;
+    }
+    __syncthreads();
+    for (int j = tid; j < L3; j += NT) {
+      int kx = j % L, kyz = j / L;
+      C2<R> s = {(R)0, (R)0};
 #pragma unroll
-    for (int m = 0; m < P; ++m) cfma(s, B2[m + P * kyz], W[(m * kx) % P]);
-    Lx[(int64_t)tgt[i] * L3 + j] = s;
+      for (int m = 0; m < P; ++m) cfma(s, B2[m + P * kyz], W[(m * kx) % P]);
+      Lx[(int64_t)tgt[i] * L3 + j] = s;
+    }
+    __syncthreads();
   }
 }
 
@@ -1161,7 +1187,7 @@ template <typename R>
 static hipError_t spectra_impl(DevPlan& P, const int32_t* lev, const int32_t* delta, hipStream_t s) {
   if (P.n_spec == 0) return hipSuccess;
   DEFMM_L_SWITCH(P.L, hipLaunchKernelGGL((k_spectra<R, LL>), dim3((unsigned)P.n_spec), dim3(256), 0, s, P.n_spec,
-                                         lev, delta, P.kappa, P.D, P.freq, (C2<R>*)P.spectra));
+                                         lev, delta, P.kappa, P.D, P.freq, P.sym ? 2 : 1, (C2<R>*)P.spectra));
   return hipGetLastError();
 }
 
@@ -1316,7 +1342,8 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
   for (int k = 0; k < nfr; ++k) {
     const int64_t rb = P.lvl_m2f[fr_lo[k]], nr = P.lvl_m2f[fr_hi[k]] - rb;
     if (nr == 0) continue;
-    DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2f<R, LL>), dim3((unsigned)nr), dim3(256), 0, s, nr, P.m2f_exp + rb,
+    DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2f<R, LL>), dim3((unsigned)((nr + kFourierItems - 1) / kFourierItems)),
+                                         dim3(256), 0, s, nr, P.m2f_exp + rb,
                                          P.freq, (const C2<R>*)M, Mt + rb * P3R));
   }
   tm.end();
@@ -1343,17 +1370,33 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
     if (nt == 0) continue;
     if (W.m2l_variant == 0) {
       DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l<R, LL>), dim3(xcd_grid(nt)), dim3(256), 0, s, nt, P.m2l_tgt + tb,
-                                           P.m2l_begin + tb, (const int2*)P.m2l_pair, P.freq, P.perm,
+                                           P.m2l_begin + tb, (const int2*)P.m2l_pair, P.freq, P.perm, P.sym ? 1 : 0,
                                            (const C2<R>*)Mt, S, Lx));
     } else if (W.m2l_variant == 2) {
       const int64_t gb = P.lvl_grp[fr_lo[k]], ng = P.lvl_grp[fr_hi[k]] - gb;
-      DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_runs<R, LL, m2l_slices(LL)>), dim3((unsigned)(m2l_slices(LL) * ng)),
-                                           dim3(64), 0, s, ng, P.grp_tfirst + gb, P.grp_tcount + gb,
-                                           P.grp_run_begin + gb, P.runs, P.perm, (const C2<R>*)Mt, S, Lt));
+      if (P.sym) {
+        DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_runs<R, LL, m2l_slices(LL), true>),
+                                             dim3((unsigned)(m2l_slices(LL) * ng)), dim3(64), 0, s, ng,
+                                             P.grp_tfirst + gb, P.grp_tcount + gb, P.grp_run_begin + gb, P.runs,
+                                             P.perm, (const C2<R>*)Mt, S, Lt));
+      } else {
+        DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_runs<R, LL, m2l_slices(LL), false>),
+                                             dim3((unsigned)(m2l_slices(LL) * ng)), dim3(64), 0, s, ng,
+                                             P.grp_tfirst + gb, P.grp_tcount + gb, P.grp_run_begin + gb, P.runs,
+                                             P.perm, (const C2<R>*)Mt, S, Lt));
+      }
     } else {
-      DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_slice<R, LL, m2l_slices(LL)>), dim3((unsigned)(m2l_slices(LL) * nt)),
-                                           dim3(64), 0, s, nt, P.m2l_begin + tb, (const int2*)P.m2l_pair, P.perm,
-                                           (const C2<R>*)Mt, S, Lt + tb * P3R));
+      if (P.sym) {
+        DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_slice<R, LL, m2l_slices(LL), true>),
+                                             dim3((unsigned)(m2l_slices(LL) * nt)), dim3(64), 0, s, nt,
+                                             P.m2l_begin + tb, (const int2*)P.m2l_pair, P.perm, (const C2<R>*)Mt, S,
+                                             Lt + tb * P3R));
+      } else {
+        DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_slice<R, LL, m2l_slices(LL), false>),
+                                             dim3((unsigned)(m2l_slices(LL) * nt)), dim3(64), 0, s, nt,
+                                             P.m2l_begin + tb, (const int2*)P.m2l_pair, P.perm, (const C2<R>*)Mt, S,
+                                             Lt + tb * P3R));
+      }
     }
   }
   tm.end();
@@ -1362,7 +1405,8 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
     for (int k = 0; k < nfr; ++k) {
       const int64_t tb = P.m2l_level_tgt[fr_lo[k]], nt = P.m2l_level_tgt[fr_hi[k]] - tb;
       if (nt == 0) continue;
-      DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_f2l<R, LL>), dim3(xcd_grid(nt)), dim3(256), 0, s, nt, P.m2l_tgt + tb,
+      DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_f2l<R, LL>), dim3(xcd_grid((nt + kFourierItems - 1) / kFourierItems)),
+                                           dim3(256), 0, s, nt, P.m2l_tgt + tb,
                                            P.freq, (const C2<R>*)(Lt + tb * P3R), Lx));
     }
   tm.end();

@@ -15,6 +15,18 @@ constexpr int kP2PBlock = 64;  // target points per P2P block
 constexpr int kP2PChunk = 2048;  // source points per P2P work item (balance)
 constexpr int kL2PChunk = 256;   // target points per L2P work item
 constexpr int kMaxSegPerItem = 64;  // source segments per P2P work item (one wave-wide scan)
+constexpr double kMaxSpectraBytes = 8.0 * (1ull << 30);  // per-offset spectra beyond this are compressed
+
+// Frequency slices of the M2L kernels (a multiple of 8: one set per XCD) and
+// the Fourier-domain row: frequencies stored as (xi, -xi) pairs, grouped
+// into m2l_slices(L) slices of fourier_cap(L) pairs, each slice closed under
+// the 48 symmetries of the spectra (the packing of the symmetry orbits that
+// make_fourier_layout builds fits these capacities).
+constexpr int m2l_slices(int L) { return L <= 5 ? 8 : (L == 6 ? 16 : 32); }
+constexpr int fourier_cap(int L) {
+  return L == 2 ? 6 : L == 3 ? 12 : L == 4 ? 24 : L == 5 ? 48 : L == 6 ? 48 : L == 7 ? 36 : 60;
+}
+constexpr int fourier_row(int L) { return 2 * m2l_slices(L) * fourier_cap(L); }
 
 struct BuildParams {
   int L = 5;
@@ -25,6 +37,7 @@ struct BuildParams {
   bool same_points = false;
   double kappa = 0.0;
   bool dense_tables = true;  // build the dense M2L index tables (the M2L mode may use them)
+  bool compress_spectra = false;  // one spectrum per symmetry class (also forced past kMaxSpectraBytes)
 };
 
 // One 2^d-tree over a point set, level-major, Morton order inside a level.
@@ -79,8 +92,10 @@ struct HostPlan {
   struct M2L { int32_t t, s, off; };
   std::vector<M2L> m2l;
   std::vector<Offset> offsets;
-  // one spectrum per canonical (level, sorted |delta|); per offset id the
-  // spectrum code (canonical id << 6) | symmetry code
+  // spectra: compressed, one per canonical (level, sorted |delta|) and per
+  // offset id the code (canonical id << 6) | symmetry code; otherwise one per
+  // offset id and the code (offset id << 6)
+  bool compressed = false;
   std::vector<Offset> canon;
   std::vector<int32_t> off_spec;
   std::vector<int32_t> p2p_t, p2p_s;

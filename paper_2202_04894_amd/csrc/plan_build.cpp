@@ -366,6 +366,9 @@ void build_tables(HostPlan& hp) {
     std::map<std::array<int32_t, 4>, int32_t> cid;
     hp.canon.clear();
     hp.off_spec.resize(hp.offsets.size());
+    hp.compressed = hp.prm.compress_spectra ||
+                    (double)hp.offsets.size() * fourier_row(hp.prm.L) * 16.0 > kMaxSpectraBytes ||
+                    hp.offsets.size() >= (size_t(1) << 22);
     for (size_t i = 0; i < hp.offsets.size(); ++i) {
       const Offset& o = hp.offsets[i];
       int32_t d0[3];
@@ -376,7 +379,7 @@ void build_tables(HostPlan& hp) {
         it = cid.emplace(key, (int32_t)hp.canon.size()).first;
         hp.canon.push_back(Offset{o.level, {d0[0], d0[1], d0[2]}, -1});
       }
-      hp.off_spec[i] = (it->second << 6) | code;
+      hp.off_spec[i] = hp.compressed ? (it->second << 6) | code : (int32_t)(i << 6);
     }
     if (hp.canon.size() >= (size_t(1) << 22)) throw std::runtime_error("too many distinct spectra");
   }

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libdefmm.so")
 C128, C64 = 0, 1
 M2L_AUTO, M2L_FFT, M2L_DENSE = 0, 1, 2
 SAME_POINTS = 1
+COMPRESS_SPECTRA = 2
 NUM_PASSES = 12
 
 
@@ -45,7 +46,7 @@ class _Stats(ctypes.Structure):
                 ("p2p_cell_pairs", ctypes.c_int64), ("p2p_point_pairs", ctypes.c_int64),
                 ("eff_expansions", ctypes.c_int64), ("m2l_expansions", ctypes.c_int64),
                 ("unique_offsets", ctypes.c_int64), ("m2l_mode_per_level", ctypes.c_int32 * 32),
-                ("spectra", ctypes.c_int64)]
+                ("spectra", ctypes.c_int64), ("compressed_spectra", ctypes.c_int32)]
 
 
 EXPORTS = ["defmm_default_params", "defmm_plan_create", "defmm_plan_inspect_create", "defmm_plan_footprint", "defmm_plan_stats",

@@ -104,10 +104,13 @@ def test_offset_spectrum_equals_permuted_canonical_spectrum(L, kappa):
 
 def test_plan_stores_one_spectrum_per_symmetry_class():
     X = W.GENERATORS["sphere"](6000, 3)
-    p = defmm.Plan.inspect(X, None, 40.0, defmm.Params(order_L=4, ncrit=16))
+    p = defmm.Plan.inspect(X, None, 40.0, defmm.Params(order_L=4, ncrit=16, flags=defmm.COMPRESS_SPECTRA))
     st = p.stats()
     m = p.m2l()
     keys = {(int(l),) + tuple(sorted(abs(int(x)) for x in d)) for l, d in zip(m["level"], m["delta"])}
-    assert st["spectra"] == len(keys)
+    assert st["compressed_spectra"] == 1 and st["spectra"] == len(keys)
     assert st["unique_offsets"] == len({(int(l),) + tuple(int(x) for x in d) for l, d in zip(m["level"], m["delta"])})
     assert st["spectra"] * 10 < st["unique_offsets"]
+    # default: one spectrum per distinct (level, offset)
+    st = defmm.Plan.inspect(X, None, 40.0, defmm.Params(order_L=4, ncrit=16)).stats()
+    assert st["compressed_spectra"] == 0 and st["spectra"] == st["unique_offsets"]

@@ -102,6 +102,29 @@ def test_c64_matches_oracle(geom, n, kappa, kw):
     assert rel(p, ref) < 2e-5, rel(p, ref)
 
 
+@pytest.mark.parametrize("geom,n,kappa,kw", FMM_CASES)
+def test_compressed_spectra_match_oracle(geom, n, kappa, kw):
+    """One spectrum per symmetry class (Sec. 4.3), read through the frequency
+    permutation, in all three Fourier M2L variants: complex128 to rounding
+    against the oracle, complex64 within the c64 bound; the plan stores fewer
+    spectra than distinct offsets."""
+    defmm = _defmm()
+    X = W.GENERATORS[geom](n, 101)
+    q = W.charges(n, 102)
+    ref = oracle.FMM(X, None, kappa, oracle_params(defmm.Params(**kw))).apply(q)
+    for prec, tol in ((defmm.C128, 1e-11), (defmm.C64, 2e-5)):
+        prm = defmm.Params(precision=prec, flags=defmm.COMPRESS_SPECTRA, **kw)
+        plan = defmm.Plan(X, None, kappa, prm)
+        st = plan.stats()
+        assert st["compressed_spectra"] == 1 and st["spectra"] < st["unique_offsets"]
+        ws = defmm.Workspace(plan)
+        qt = torch.as_tensor(q, device="cuda").to(plan.cdtype)
+        for variant in (0, 1, 2):
+            ws.set_tuning(overlap=0, p2p_waves_per_cu=2, m2l_variant=variant, dense_levels=0)
+            p = ws.matvec(qt).cpu().numpy().astype(np.complex128)
+            assert rel(p, ref) < tol, (prec, variant, rel(p, ref))
+
+
 DENSE_CASES = [
     ("sphere", 3000, 24.0, dict(order_L=5, ncrit=24, eta=0.5, hf_threshold=2.0, dir_refine=1)),
     ("cube_volume", 3000, 12.0, dict(order_L=4, ncrit=40)),
