@@ -192,7 +192,9 @@ defmm_status defmm_workspace_set_timing(defmm_workspace* ws, int32_t enable);
 /* Execution choices of a workspace (results are the same to rounding; the
    near-field split never changes a bit):
    overlap          1: near field on the workspace's own stream, concurrently
-                    with the far field; 0: every pass in sequence;
+                    with the far field, forked after the charge gather;
+                    2: the same, forked after M2F (the upward pass runs
+                    alone); 0: every pass in sequence;
    p2p_waves_per_cu persistent near-field workgroups (one wave) per compute
                     unit when overlapped, 1..32;
    m2l_variant      0: Hadamard fused with F2L per target; 1: frequency-sliced
@@ -213,18 +215,20 @@ typedef struct {
    and `reps` matvecs of q into p on hip_stream; host-synchronous) and keeps
    the fastest: the Fourier-path M2L variant in sequence first, then, level by
    level, the dense MFMA M2L where the plan holds its matrices, then the
-   overlapped near field with 2, 3, 4 and 6 waves per CU.  q and p as in defmm_matvec; p holds
-   a valid result afterwards.  chosen (optional) receives the choice. */
+   overlapped near field forked early or after M2F, with 2, 3, 4 and 6 waves
+   per CU.  q and p as in defmm_matvec; p holds a valid result afterwards.
+   chosen (optional) receives the choice. */
 defmm_status defmm_workspace_autotune(defmm_plan* plan, defmm_workspace* ws, const void* q, void* p,
                                       void* hip_stream, int32_t reps, defmm_tuning* chosen);
 defmm_status defmm_workspace_get_tuning(const defmm_workspace* ws, defmm_tuning* out);
 defmm_status defmm_workspace_set_tuning(defmm_workspace* ws, const defmm_tuning* t);
 
 /* Overlap (default on): the near field (P2P) runs on a stream owned by the
-   workspace, forked after the charge gather and joined before L2P, as a
-   persistent kernel that leaves wave slots to the far field.  Off: every pass
-   runs in sequence on the caller's stream at full occupancy (used to time
-   each kernel alone).  Results are bitwise identical either way. */
+   workspace, forked after the charge gather (enable = 1; enable = 2: after
+   M2F) and joined before L2P, as a persistent kernel that leaves wave slots
+   to the far field.  Off (0): every pass runs in sequence on the caller's
+   stream at full occupancy (used to time each kernel alone).  Results are
+   bitwise identical either way. */
 defmm_status defmm_workspace_set_overlap(defmm_workspace* ws, int32_t enable);
 defmm_status defmm_workspace_pass_times(defmm_workspace* ws, double* pass_ms, int64_t* calls);
 const char* defmm_pass_name(int32_t i);

@@ -632,14 +632,14 @@ defmm_status defmm_workspace_set_timing(defmm_workspace* ws, int32_t enable) {
 
 defmm_status defmm_workspace_set_overlap(defmm_workspace* ws, int32_t enable) {
   if (!ws) return fail(DEFMM_ERR_INVALID_ARG, "workspace is NULL");
-  ws->impl.overlap = enable != 0;
+  ws->impl.overlap = enable == 2 ? 2 : (enable != 0 ? 1 : 0);
   ws->impl.graph_stale = true;
   return DEFMM_OK;
 }
 
 defmm_status defmm_workspace_get_tuning(const defmm_workspace* ws, defmm_tuning* out) {
   if (!ws || !out) return fail(DEFMM_ERR_INVALID_ARG, "NULL argument");
-  out->overlap = ws->impl.overlap ? 1 : 0;
+  out->overlap = ws->impl.overlap;
   out->p2p_waves_per_cu = ws->impl.p2p_waves;
   out->m2l_variant = ws->impl.m2l_variant;
   out->dense_levels = 0;
@@ -651,10 +651,11 @@ defmm_status defmm_workspace_get_tuning(const defmm_workspace* ws, defmm_tuning*
 
 defmm_status defmm_workspace_set_tuning(defmm_workspace* ws, const defmm_tuning* t) {
   if (!ws || !t) return fail(DEFMM_ERR_INVALID_ARG, "NULL argument");
-  if (t->p2p_waves_per_cu < 1 || t->p2p_waves_per_cu > 32 || t->m2l_variant < 0 || t->m2l_variant > 2)
+  if (t->p2p_waves_per_cu < 1 || t->p2p_waves_per_cu > 32 || t->m2l_variant < 0 || t->m2l_variant > 2 ||
+      t->overlap < 0 || t->overlap > 2)
     return fail(DEFMM_ERR_INVALID_ARG, "tuning out of range");
   ws->impl.graph_stale = true;
-  ws->impl.overlap = t->overlap != 0;
+  ws->impl.overlap = t->overlap;
   ws->impl.p2p_waves = t->p2p_waves_per_cu;
   ws->impl.m2l_variant = t->m2l_variant;
   const DevPlan& P = *ws->impl.plan;
@@ -679,7 +680,7 @@ defmm_status defmm_workspace_autotune(defmm_plan* plan, defmm_workspace* ws, con
   W.timing = false;
   W.graph_stale = true;
   auto apply = [&](const defmm_tuning& t) {
-    W.overlap = t.overlap != 0;
+    W.overlap = t.overlap;
     W.p2p_waves = t.p2p_waves_per_cu;
     W.m2l_variant = t.m2l_variant;
     for (size_t l = 0; l < W.dense_level.size(); ++l)
@@ -721,14 +722,16 @@ defmm_status defmm_workspace_autotune(defmm_plan* plan, defmm_workspace* ws, con
     if (err != hipSuccess) break;
     if (t.ms < best.ms) best = t;
   }
-  // near field overlapped with the far field, with a few wave budgets
-  for (int w : {2, 3, 4, 6}) {
-    if (err != hipSuccess) break;
-    defmm_tuning t{1, w, best.m2l_variant, best.dense_levels, 0.0};
-    err = measure(t, &t.ms);
-    if (err != hipSuccess) break;
-    if (t.ms < best.ms) best = t;
-  }
+  // near field overlapped with the far field, forked early or after M2F,
+  // with a few wave budgets
+  for (int ov : {1, 2})
+    for (int w : {2, 3, 4, 6}) {
+      if (err != hipSuccess) break;
+      defmm_tuning t{ov, w, best.m2l_variant, best.dense_levels, 0.0};
+      err = measure(t, &t.ms);
+      if (err != hipSuccess) break;
+      if (t.ms < best.ms) best = t;
+    }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   W.timing = timing;

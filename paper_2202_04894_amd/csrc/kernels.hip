@@ -1276,30 +1276,37 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
 
   // Near field on the workspace's side stream, concurrently with the far
   // field (the ALU-bound P2P overlaps the L2-bound M2L); joined before L2P.
+  // Forked after the charge gather (overlap 1) or after M2F (overlap 2, so
+  // the short upward-pass kernels do not compete with the persistent P2P).
   hipStream_t s2 = (W.side && W.overlap) ? W.side : s;
-  if (s2 != s) {
-    hipError_t e = hipEventRecord(W.ev_fork, s);
-    if (e == hipSuccess) e = hipStreamWaitEvent(s2, W.ev_fork, 0);
-    if (e != hipSuccess) return e;
-  }
-  if (P.nx > 0) hipLaunchKernelGGL((k_zero<R>), dim3(blocks_for(P.nx, 256)), dim3(256), 0, s2, P.nx, ps);
-  tm.begin(kPassP2P, s2);
-  if (P.nwi > 0) {
-    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s2, 8, W.queue);
-    const int wpc = (s2 != s) ? W.p2p_waves : 8;  // alone: fill every wave slot
-    const unsigned nb = (unsigned)std::min<int64_t>(P.nwi, (int64_t)P.num_cu * wpc);
-    hipLaunchKernelGGL((k_p2p<R>), dim3(nb), dim3(64), 0, s2, P.nwi, W.queue, P.wi_blk, P.wi_seg_begin,
-                       P.seg_first, P.seg_count, P.blk_first, P.blk_count, P.tx.soa, P.tx.n, P.ty.soa, P.ty.n,
-                       (const C2<R>*)qs, part, P.kappa, P.tau * P.tau);
-  }
-  tm.end();
-  tm.begin(kPassP2PRed, s2);
-  if (P.nblk > 0)
-    hipLaunchKernelGGL((k_p2p_reduce<R>), dim3((unsigned)P.nblk), dim3(64), 0, s2, P.nblk, P.blk_first,
-                       P.blk_count, P.blk_wi_begin, (const C2<R>*)part, ps);
-  tm.end();
-  if (s2 != s) {
-    hipError_t e = hipEventRecord(W.ev_join, s2);
+  auto launch_near = [&]() -> hipError_t {
+    if (s2 != s) {
+      hipError_t e = hipEventRecord(W.ev_fork, s);
+      if (e == hipSuccess) e = hipStreamWaitEvent(s2, W.ev_fork, 0);
+      if (e != hipSuccess) return e;
+    }
+    if (P.nx > 0) hipLaunchKernelGGL((k_zero<R>), dim3(blocks_for(P.nx, 256)), dim3(256), 0, s2, P.nx, ps);
+    tm.begin(kPassP2P, s2);
+    if (P.nwi > 0) {
+      hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s2, 8, W.queue);
+      const int wpc = (s2 != s) ? W.p2p_waves : 8;  // alone: fill every wave slot
+      const unsigned nb = (unsigned)std::min<int64_t>(P.nwi, (int64_t)P.num_cu * wpc);
+      hipLaunchKernelGGL((k_p2p<R>), dim3(nb), dim3(64), 0, s2, P.nwi, W.queue, P.wi_blk, P.wi_seg_begin,
+                         P.seg_first, P.seg_count, P.blk_first, P.blk_count, P.tx.soa, P.tx.n, P.ty.soa, P.ty.n,
+                         (const C2<R>*)qs, part, P.kappa, P.tau * P.tau);
+    }
+    tm.end();
+    tm.begin(kPassP2PRed, s2);
+    if (P.nblk > 0)
+      hipLaunchKernelGGL((k_p2p_reduce<R>), dim3((unsigned)P.nblk), dim3(64), 0, s2, P.nblk, P.blk_first,
+                         P.blk_count, P.blk_wi_begin, (const C2<R>*)part, ps);
+    tm.end();
+    if (s2 != s) return hipEventRecord(W.ev_join, s2);
+    return hipSuccess;
+  };
+  const bool fork_late = s2 != s && W.overlap == 2;
+  if (!fork_late) {
+    hipError_t e = launch_near();
     if (e != hipSuccess) return e;
   }
 
@@ -1347,6 +1354,10 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
                                          P.freq, (const C2<R>*)M, Mt + rb * P3R));
   }
   tm.end();
+  if (fork_late) {
+    hipError_t e = launch_near();
+    if (e != hipSuccess) return e;
+  }
 
   tm.begin(kPassM2LDense);
   for (int l = 0; l < nlev; ++l) {

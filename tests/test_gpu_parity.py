@@ -206,6 +206,9 @@ def test_overlap_and_variants_are_bitwise_identical():
     ws.set_overlap(False)
     b = ws.matvec(qt).cpu().numpy()
     assert np.array_equal(a, b)
+    ws.set_tuning(overlap=2, p2p_waves_per_cu=3, m2l_variant=2, dense_levels=0)  # forked after M2F
+    c = ws.matvec(qt).cpu().numpy()
+    assert np.array_equal(a, c)
     outs = []
     for v in ("0", "1", "2"):
         os.environ["DEFMM_M2L_VARIANT"] = v
@@ -234,7 +237,7 @@ def test_autotune_keeps_a_valid_choice():
     qt = torch.as_tensor(q, device="cuda").to(plan.cdtype)
     ref = ws.matvec(qt).cpu().numpy().astype(np.complex128)
     t = ws.autotune(qt, reps=2)
-    assert t["m2l_variant"] in (1, 2) and t["overlap"] in (0, 1) and t["ms"] > 0
+    assert t["m2l_variant"] in (1, 2) and t["overlap"] in (0, 1, 2) and t["ms"] > 0
     assert t["dense_levels"] & ~capable == 0
     assert ws.tuning() == {**t, "ms": 0.0}
     got = ws.matvec(qt).cpu().numpy().astype(np.complex128)
