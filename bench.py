@@ -354,6 +354,10 @@ def main():
         "sequential_ms_per_step": round(ms_seq, 4),
         "tuning": tuned,
         "passes_ms_per_step": {n: round(float(v), 4) for n, v in zip(names, per_step)},
+        # per pass: compulsory bytes / time against the HBM peak, flops / time
+        "passes_roofline": {n: {"GBps": round(b / (t / 1e3) / 1e9, 1), "frac_hbm": round(b / (t / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                                "TFLOPs": round(f / (t / 1e3) / 1e12, 3)}
+                            for n, t, b, f in zip(names, per_step, bytes_, flops) if t > 0.005},
         "stats": st,
         "roofline": roof,
         "p2p": p2p,
