@@ -38,6 +38,13 @@ __device__ __forceinline__ void cfma(C2<R>& acc, C2<R> a, C2<R> b) {
   acc.y = fma(a.x, b.y, fma(a.y, b.x, acc.y));
 }
 
+// acc += a * w for a real weight w (two multiply-adds, not four).
+template <typename R>
+__device__ __forceinline__ void cfma_r(C2<R>& acc, C2<R> a, R w) {
+  acc.x = fma(a.x, w, acc.x);
+  acc.y = fma(a.y, w, acc.y);
+}
+
 template <typename R>
 __device__ __forceinline__ C2<R> cscale(C2<R> a, R s) {
   return {a.x * s, a.y * s};
@@ -242,7 +249,7 @@ __global__ __launch_bounds__(round64(L* L* L)) void k_p2m(int64_t n, const int32
     __syncthreads();
     int m = min(PT, cnt - base);
     if (tid < L3)
-      for (int k = 0; k < m; ++k) cfma(acc, qq[k], {w[k][0][rx] * w[k][1][ry] * w[k][2][rz], (R)0});
+      for (int k = 0; k < m; ++k) cfma_r(acc, qq[k], w[k][0][rx] * w[k][1][ry] * w[k][2][rz]);
     __syncthreads();
   }
   if (tid < L3) {
@@ -304,20 +311,20 @@ __global__ __launch_bounds__(round64(L* L* L)) void k_m2m(int64_t n, const int32
     if (tid < L3) {
       C2<R> s = {(R)0, (R)0};
 #pragma unroll
-      for (int r = 0; r < L; ++r) cfma(s, b0[r + L * ly + L * L * lz], {A[b[0]][lx][r], (R)0});
+      for (int r = 0; r < L; ++r) cfma_r(s, b0[r + L * ly + L * L * lz], A[b[0]][lx][r]);
       b1[tid] = s;
     }
     __syncthreads();
     if (tid < L3) {
       C2<R> s = {(R)0, (R)0};
 #pragma unroll
-      for (int r = 0; r < L; ++r) cfma(s, b1[lx + L * r + L * L * lz], {A[b[1]][ly][r], (R)0});
+      for (int r = 0; r < L; ++r) cfma_r(s, b1[lx + L * r + L * L * lz], A[b[1]][ly][r]);
       b0[tid] = s;
     }
     __syncthreads();
     if (tid < L3) {
 #pragma unroll
-      for (int r = 0; r < L; ++r) cfma(acc, b0[lx + L * ly + L * L * r], {A[b[2]][lz][r], (R)0});
+      for (int r = 0; r < L; ++r) cfma_r(acc, b0[lx + L * ly + L * L * r], A[b[2]][lz][r]);
     }
   }
   if (tid < L3) {
@@ -863,21 +870,21 @@ __global__ __launch_bounds__(round64(L* L* L)) void k_l2l(int64_t n, const int32
     if (tid < L3) {  // (hx, ky, kz)
       C2<R> s = {(R)0, (R)0};
 #pragma unroll
-      for (int kk = 0; kk < L; ++kk) cfma(s, b0[kk + L * hy + L * L * hz], {A[b[0]][kk][hx], (R)0});
+      for (int kk = 0; kk < L; ++kk) cfma_r(s, b0[kk + L * hy + L * L * hz], A[b[0]][kk][hx]);
       b1[tid] = s;
     }
     __syncthreads();
     if (tid < L3) {  // (hx, hy, kz)
       C2<R> s = {(R)0, (R)0};
 #pragma unroll
-      for (int kk = 0; kk < L; ++kk) cfma(s, b1[hx + L * kk + L * L * hz], {A[b[1]][kk][hy], (R)0});
+      for (int kk = 0; kk < L; ++kk) cfma_r(s, b1[hx + L * kk + L * L * hz], A[b[1]][kk][hy]);
       b0[tid] = s;
     }
     __syncthreads();
     if (tid < L3) {
       C2<R> s = {(R)0, (R)0};
 #pragma unroll
-      for (int kk = 0; kk < L; ++kk) cfma(s, b0[hx + L * hy + L * L * kk], {A[b[2]][kk][hz], (R)0});
+      for (int kk = 0; kk < L; ++kk) cfma_r(s, b0[hx + L * hy + L * L * kk], A[b[2]][kk][hz]);
       C2<R> t = cmul(cmul(s, pho[0][hx]), cmul(pho[1][hy], pho[2][hz]));
       acc.x += t.x;
       acc.y += t.y;
@@ -935,10 +942,10 @@ __global__ __launch_bounds__(64) void k_l2p(int64_t n, const int32_t* __restrict
           for (int ky = 0; ky < L; ++ky) {
             C2<R> sx = {(R)0, (R)0};
 #pragma unroll
-            for (int kx = 0; kx < L; ++kx) cfma(sx, Lp[kx + L * ky + L * L * kz], {wx[kx], (R)0});
-            cfma(sy, sx, {wy[ky], (R)0});
+            for (int kx = 0; kx < L; ++kx) cfma_r(sx, Lp[kx + L * ky + L * L * kz], wx[kx]);
+            cfma_r(sy, sx, wy[ky]);
           }
-          cfma(sz, sy, {wz[kz], (R)0});
+          cfma_r(sz, sy, wz[kz]);
         }
         cfma(acc[q], sz, expi<R>(g.kappa * (ux * d0 + uy * d1 + uz * d2)));
       }
