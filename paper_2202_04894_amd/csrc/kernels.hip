@@ -898,65 +898,86 @@ __global__ __launch_bounds__(round64(L* L* L)) void k_l2l(int64_t n, const int32
 
 // ------------------------------------------------------------------ L2P
 // p(x) += sum_u exp(ik<x - a, u>) sum_h S_h(x) exp(-ik<x_h - a, u>) L^u(x_h).
+// One wave per work item (a leaf and <= 256 of its points, 64 at a time, one
+// point per lane).  The interpolation weights of a point are computed once;
+// the leaf's expansions are staged one by one in LDS with their node phases,
+// the next expansion's values being loaded while the current one is summed.
 template <typename R, int L>
 __global__ __launch_bounds__(64) void k_l2p(int64_t n, const int32_t* __restrict__ cell,
                                             const int32_t* __restrict__ pfirst, const int32_t* __restrict__ pcount,
                                             TreeView T, Geo g, const C2<R>* __restrict__ Lx,
                                             C2<R>* __restrict__ ps) {
-  constexpr int L3 = L * L * L, PER = 4;  // up to 256 points per item
-  __shared__ C2<R> Lp[L3];
-  int64_t item = blockIdx.x;
+  constexpr int L3 = L * L * L, NV = (L3 + 63) / 64;
+  __shared__ C2<R> lp[L3];
+  const int64_t item = blockIdx.x;
   if (item >= n) return;
-  int c = cell[item];
-  double h = ldexp(g.D, -T.level[c]);
-  double ax = g.ox + h * T.ijk[3 * c], ay = g.oy + h * T.ijk[3 * c + 1], az = g.oz + h * T.ijk[3 * c + 2];
-  int first = pfirst[item], cnt = pcount[item];
-  int tid = threadIdx.x;
-  C2<R> acc[PER];
+  const int c = cell[item];
+  const double h = ldexp(g.D, -T.level[c]);
+  const double ax = g.ox + h * T.ijk[3 * c], ay = g.oy + h * T.ijk[3 * c + 1], az = g.oz + h * T.ijk[3 * c + 2];
+  const int first = pfirst[item], cnt = pcount[item];
+  const int lane = threadIdx.x;
+  const int e0 = T.exp_begin[c], e1 = T.exp_begin[c + 1];
+  const double kh = g.kappa * h / (double)(L - 1);
+  int kx_[NV], ky_[NV], kz_[NV];
 #pragma unroll
-  for (int q = 0; q < PER; ++q) acc[q] = {(R)0, (R)0};
-  for (int e = T.exp_begin[c]; e < T.exp_begin[c + 1]; ++e) {
-    double ux = T.exp_u[3 * e], uy = T.exp_u[3 * e + 1], uz = T.exp_u[3 * e + 2];
-    __syncthreads();
-    for (int i = tid; i < L3; i += 64) {
-      int kx = i % L, ky = (i / L) % L, kz = i / (L * L);
-      double arg = -g.kappa * h / (double)(L - 1) * (ux * kx + uy * ky + uz * kz);
-      Lp[i] = cmul(Lx[(int64_t)e * L3 + i], expi<R>(arg));
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      int j = tid + 64 * q;
-      if (j < cnt) {
-        int64_t pi = first + j;
-        double d0 = T.soa[pi] - ax, d1 = T.soa[T.n + pi] - ay, d2 = T.soa[2 * T.n + pi] - az;
-        R wx[L], wy[L], wz[L];
-        lagrange<R, L>((R)(d0 / h), wx);
-        lagrange<R, L>((R)(d1 / h), wy);
-        lagrange<R, L>((R)(d2 / h), wz);
-        C2<R> sz = {(R)0, (R)0};
-#pragma unroll
-        for (int kz = 0; kz < L; ++kz) {
-          C2<R> sy = {(R)0, (R)0};
-#pragma unroll
-          for (int ky = 0; ky < L; ++ky) {
-            C2<R> sx = {(R)0, (R)0};
-#pragma unroll
-            for (int kx = 0; kx < L; ++kx) cfma_r(sx, Lp[kx + L * ky + L * L * kz], wx[kx]);
-            cfma_r(sy, sx, wy[ky]);
-          }
-          cfma_r(sz, sy, wz[kz]);
-        }
-        cfma(acc[q], sz, expi<R>(g.kappa * (ux * d0 + uy * d1 + uz * d2)));
-      }
-    }
+  for (int v = 0; v < NV; ++v) {
+    const int i = min(lane + 64 * v, L3 - 1);
+    kx_[v] = i % L;
+    ky_[v] = (i / L) % L;
+    kz_[v] = i / (L * L);
   }
+  for (int base = 0; base < cnt; base += 64) {
+    const int j = base + lane;
+    const bool on = j < cnt;
+    double d0 = 0, d1 = 0, d2 = 0;
+    if (on) {
+      const int64_t pi = first + j;
+      d0 = T.soa[pi] - ax;
+      d1 = T.soa[T.n + pi] - ay;
+      d2 = T.soa[2 * T.n + pi] - az;
+    }
+    R wx[L], wy[L], wz[L];
+    lagrange<R, L>((R)(d0 / h), wx);
+    lagrange<R, L>((R)(d1 / h), wy);
+    lagrange<R, L>((R)(d2 / h), wz);
+    C2<R> acc = {(R)0, (R)0};
+    C2<R> nxt[NV];
+    if (e0 < e1) {
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    int j = tid + 64 * q;
-    if (j < cnt) {
+      for (int v = 0; v < NV; ++v)
+        nxt[v] = lane + 64 * v < L3 ? Lx[(int64_t)e0 * L3 + lane + 64 * v] : C2<R>{(R)0, (R)0};
+    }
+    for (int e = e0; e < e1; ++e) {
+      const double ux = T.exp_u[3 * e], uy = T.exp_u[3 * e + 1], uz = T.exp_u[3 * e + 2];
+      __syncthreads();
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        if (lane + 64 * v < L3)
+          lp[lane + 64 * v] = cmul(nxt[v], expi<R>(-kh * (ux * kx_[v] + uy * ky_[v] + uz * kz_[v])));
+      __syncthreads();
+      if (e + 1 < e1) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+          nxt[v] = lane + 64 * v < L3 ? Lx[(int64_t)(e + 1) * L3 + lane + 64 * v] : C2<R>{(R)0, (R)0};
+      }
+      C2<R> sz = {(R)0, (R)0};
+#pragma unroll
+      for (int kz = 0; kz < L; ++kz) {
+        C2<R> sy = {(R)0, (R)0};
+#pragma unroll
+        for (int ky = 0; ky < L; ++ky) {
+          C2<R> sx = {(R)0, (R)0};
+#pragma unroll
+          for (int kx = 0; kx < L; ++kx) cfma_r(sx, lp[kx + L * ky + L * L * kz], wx[kx]);
+          cfma_r(sy, sx, wy[ky]);
+        }
+        cfma_r(sz, sy, wz[kz]);
+      }
+      cfma(acc, sz, expi<R>(g.kappa * (ux * d0 + uy * d1 + uz * d2)));
+    }
+    if (on) {
       C2<R> cur = ps[first + j];
-      ps[first + j] = {cur.x + acc[q].x, cur.y + acc[q].y};
+      ps[first + j] = {cur.x + acc.x, cur.y + acc.y};
     }
   }
 }
