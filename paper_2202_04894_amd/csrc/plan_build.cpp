@@ -9,6 +9,7 @@
 // be compiled without floating-point contraction.
 #include <algorithm>
 #include <array>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -600,19 +601,30 @@ void build_tables(HostPlan& hp) {
   hp.l2l_par.assign(X.nlevels, {});
   hp.l2l_oct.assign(X.nlevels, {});
   for (int l = 0; l + 1 < X.nlevels; ++l) {
+    // the father's expansions keyed by the son direction they feed (Father(v),
+    // or -1 for a low-frequency son), in expansion order within a key
+    std::vector<std::pair<int32_t, int32_t>> feed;
+    int32_t fed = -1;
     for (int64_t c = X.lev_start[l + 1]; c < X.lev_start[l + 2]; ++c) {
       int32_t p = X.parent[c];
       int oct = (X.ijk[3 * c] - 2 * X.ijk[3 * p]) | ((X.ijk[3 * c + 1] - 2 * X.ijk[3 * p + 1]) << 1) |
                 ((X.ijk[3 * c + 2] - 2 * X.ijk[3 * p + 2]) << 2);
+      if (p != fed) {
+        feed.clear();
+        for (int64_t pe = X.exp_begin[p]; pe < X.exp_begin[p + 1]; ++pe) {
+          int32_t fv = -1;
+          if (hp.hf[l + 1]) fv = (int32_t)hp.father_flat[hp.dir_off[dir_level(hp, l)] + X.exp_dir[pe]];
+          feed.push_back({fv, (int32_t)pe});
+        }
+        std::sort(feed.begin(), feed.end());
+        fed = p;
+      }
       for (int64_t e = X.exp_begin[c]; e < X.exp_begin[c + 1]; ++e) {
         int32_t u = X.exp_dir[e];
         size_t before = hp.l2l_par[l].size();
-        for (int64_t pe = X.exp_begin[p]; pe < X.exp_begin[p + 1]; ++pe) {
-          int32_t v = X.exp_dir[pe];
-          int32_t fv = -1;
-          if (hp.hf[l + 1]) fv = (int32_t)hp.father_flat[hp.dir_off[dir_level(hp, l)] + v];
-          if (fv != u) continue;
-          hp.l2l_par[l].push_back((int32_t)pe);
+        auto it = std::lower_bound(feed.begin(), feed.end(), std::make_pair(u, (int32_t)INT32_MIN));
+        for (; it != feed.end() && it->first == u; ++it) {
+          hp.l2l_par[l].push_back(it->second);
           hp.l2l_oct[l].push_back((int8_t)oct);
         }
         if (hp.l2l_par[l].size() != before) {
