@@ -294,7 +294,16 @@ __global__ __launch_bounds__(round64(L* L* L)) void k_m2m(int64_t n, const int32
   int tid = threadIdx.x;
   int lx = tid % L, ly = (tid / L) % L, lz = tid / (L * L);
   son_matrices<R, L>(A);
+  // every son's value at this thread's node, loaded before the first product
+  // so that the eight loads are in flight together
+  C2<R> sv[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int ce = child[item * 8 + k];
+    sv[k] = (ce >= 0 && tid < L3) ? M[(int64_t)ce * L3 + tid] : C2<R>{(R)0, (R)0};
+  }
   C2<R> acc = {(R)0, (R)0};
+#pragma unroll
   for (int k = 0; k < 8; ++k) {
     int ce = child[item * 8 + k];
     if (ce < 0) break;
@@ -306,7 +315,7 @@ __global__ __launch_bounds__(round64(L* L* L)) void k_m2m(int64_t n, const int32
       ph[d][r] = expi<R>(-g.kappa * hc * v[d] * ((double)b[d] + (double)r / (double)(L - 1)));
     }
     __syncthreads();
-    if (tid < L3) b0[tid] = cmul(cmul(M[(int64_t)ce * L3 + tid], ph[0][lx]), cmul(ph[1][ly], ph[2][lz]));
+    if (tid < L3) b0[tid] = cmul(cmul(sv[k], ph[0][lx]), cmul(ph[1][ly], ph[2][lz]));
     __syncthreads();
     if (tid < L3) {
       C2<R> s = {(R)0, (R)0};
