@@ -91,8 +91,9 @@ __device__ __forceinline__ void lagrange(R t, R* w) {
 
 constexpr int round64(int x) { return ((x + 63) / 64) * 64; }
 
-// Row stride of the Fourier-domain arrays (spectra, M~, L~): fourier_row(L);
-// the padding entries are never read back.
+// Row stride of the Fourier-domain arrays (spectra, M~, L~): fourier_row(L),
+// in the order of the Fourier layout; padding entries hold zeros (spectra,
+// M~) or are never read back (L~).
 
 // XCD-aware block order: the hardware deals consecutive workgroups to the 8
 // XCDs round-robin; remap so each XCD walks a contiguous range of items and
