@@ -86,12 +86,19 @@ def direct_sum_sampled(X, q, kappa, tau, targets):
     return out.cpu().numpy()
 
 
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in ("kernels.hip",):
-        with open(os.path.join(ROOT, "paper_2202_04894_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+def kernel_source_hash(kernel):
+    """Hash of the kernels.hip section (between two section rules) that defines
+    `kernel`: the counters taken for it stay valid while that section is unchanged."""
+    with open(os.path.join(ROOT, "paper_2202_04894_amd", "csrc", "kernels.hip")) as fh:
+        text = fh.read()
+    rule = "// " + "-" * 66
+    at = text.find(f" void {kernel}(")
+    if at < 0:
+        return None
+    a = text.rfind(rule, 0, at)
+    b = text.find(rule, at)
+    sec = text[max(a, 0):b if b >= 0 else len(text)]
+    return hashlib.sha256(sec.encode()).hexdigest()[:16]
 
 
 def load_traffic(kernel, workload):
@@ -100,7 +107,7 @@ def load_traffic(kernel, workload):
         return None
     with open(path) as fh:
         t = json.load(fh)
-    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+    if t.get("kernel_source_sha256_16") != kernel_source_hash(kernel):
         return None
     return t.get("bytes_per_launch")
 
