@@ -682,6 +682,7 @@ static void blank_downward(ofmm* F, otree* T) {
         if (F->hf[l + 1]) {
           int E = dir_level(F, l);
           need_dirs(F, E);
+          need_dirs(F, E - 1); /* the son's own direction set, which its marks index */
           for (int m = 0; m < c->nmark; ++m) add_mark(ch, (int32_t)F->father[E][c->mark[m]]);
         } else {
           add_mark(ch, -1);

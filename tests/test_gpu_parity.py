@@ -125,6 +125,24 @@ def test_compressed_spectra_match_oracle(geom, n, kappa, kw):
             assert rel(p, ref) < tol, (prec, variant, rel(p, ref))
 
 
+@pytest.mark.parametrize("L", [2, 7, 8])
+def test_fourier_path_every_order(L):
+    """The orders outside the main cases (row layouts of 6, 36 and 60 pairs per
+    slice, 8 and 32 slices): complex128 Fourier M2L, per-offset and
+    compressed spectra, against the oracle to rounding."""
+    defmm = _defmm()
+    n = {2: 1500, 7: 800, 8: 600}[L]
+    X = W.sphere(n, 200 + L)
+    q = W.charges(n, 300 + L)
+    kw = dict(order_L=L, ncrit=12, eta=0.7, hf_threshold=1.0)
+    ref = oracle.FMM(X, None, 20.0, oracle_params(defmm.Params(**kw))).apply(q)
+    for flags in (0, defmm.COMPRESS_SPECTRA):
+        prm = defmm.Params(precision=defmm.C128, flags=flags, **kw)
+        p, plan, _ = run_gpu(X, q, 20.0, prm)
+        assert plan.stats()["m2l_pairs"] > 0
+        assert rel(p, ref) < 1e-11, (L, flags, rel(p, ref))
+
+
 DENSE_CASES = [
     ("sphere", 3000, 24.0, dict(order_L=5, ncrit=24, eta=0.5, hf_threshold=2.0, dir_refine=1)),
     ("cube_volume", 3000, 12.0, dict(order_L=4, ncrit=40)),

@@ -490,3 +490,19 @@ def test_mixed_regime_accuracy():
                                                      dir_refine=1), tg)
     assert F.info()["lstar"] == 3 and F.info()["levels_x"] == 5
     assert e < 1.5e-3
+
+
+def test_sons_below_a_level_without_interactions_get_directions(oracle_lib):
+    """A high-frequency level can receive marks only from the blank downward
+    pass (Alg. 3), with no M2L pair of its own; its direction set must still
+    exist.  This point set has such a level: the method runs and stays within
+    its L = 4 accuracy against the direct sum."""
+    import numpy as np
+    from paper_2202_04894_amd import workloads as W
+    X = W.sphere(1500, 207)
+    q = W.charges(1500, 307)
+    F = oracle_lib.FMM(X, None, 20.0, oracle_lib.Params(L=4, ncrit=12, eta=0.7, hf_threshold=1.0))
+    p = F.apply(q)
+    D = F.geometry()[0]
+    d = oracle_lib.direct_sum(X, X, q, 20.0, 1e-12 * D)
+    assert np.linalg.norm(p - d) / np.linalg.norm(d) < 1e-2
