@@ -223,9 +223,9 @@ defmm_status defmm_workspace_autotune(defmm_plan* plan, defmm_workspace* ws, con
 defmm_status defmm_workspace_get_tuning(const defmm_workspace* ws, defmm_tuning* out);
 defmm_status defmm_workspace_set_tuning(defmm_workspace* ws, const defmm_tuning* t);
 
-/* Overlap (default on): the near field (P2P) runs on a stream owned by the
-   workspace, forked after the charge gather (enable = 1; enable = 2: after
-   M2F) and joined before L2P, as a persistent kernel that leaves wave slots
+/* Overlap (new workspaces: 2): the near field (P2P) runs on a stream owned by
+   the workspace, forked after the charge gather (enable = 1; enable = 2:
+   after M2F) and joined before L2P, as a persistent kernel that leaves wave slots
    to the far field.  Off (0): every pass runs in sequence on the caller's
    stream at full occupancy (used to time each kernel alone).  Results are
    bitwise identical either way. */

@@ -117,7 +117,7 @@ struct Workspace {
   int* queue = nullptr;  // 8 work-queue heads of the persistent P2P
   size_t bytes = 0;
   hipStream_t side = nullptr;   // near-field stream (default priority), forked per matvec
-  int overlap = 1;  // 0: in sequence; 1: near field forked after the gather; 2: forked after M2F
+  int overlap = 2;  // 0: in sequence; 1: near field forked after the gather; 2: forked after M2F
   int p2p_waves = 2;     // persistent near-field workgroups (one wave) per CU when overlapped
   int m2l_variant = 2;   // 0: fused per target, 1: sliced per target, 2: sliced per group of 8 (source runs)
   std::vector<char> dense_level;  // per level: use the dense MFMA M2L

@@ -343,7 +343,7 @@ class Workspace:
         _check(lib().defmm_workspace_get_tuning(self.h, ctypes.byref(t)))
         return t.as_dict()
 
-    def set_tuning(self, overlap=1, p2p_waves_per_cu=2, m2l_variant=2, dense_levels=0, **_):
+    def set_tuning(self, overlap=2, p2p_waves_per_cu=2, m2l_variant=2, dense_levels=0, **_):
         t = Tuning(overlap, p2p_waves_per_cu, m2l_variant, dense_levels, 0.0)
         _check(lib().defmm_workspace_set_tuning(self.h, ctypes.byref(t)))
 

@@ -22,7 +22,7 @@ def test_graph_replays_equal_eager(prec_name):
     q = torch.empty(plan.ny, dtype=plan.cdtype, device="cuda")
     p = torch.empty(plan.nx, dtype=plan.cdtype, device="cuda")
     p2 = torch.empty_like(p)
-    for k in range(5):
+    for k in range(6):
         qk = torch.as_tensor(W.charges(plan.ny, 50 + k), device="cuda").to(plan.cdtype)
         with torch.cuda.stream(s):
             q.copy_(qk)
@@ -30,7 +30,9 @@ def test_graph_replays_equal_eager(prec_name):
             if k == 2:
                 wg.set_overlap(False)           # a new execution choice recaptures
             if k == 4:
-                wg.set_overlap(True)
+                wg.set_overlap(True)            # near field forked after the gather
+            if k == 5:                          # ... and after M2F
+                wg.set_tuning(overlap=2, p2p_waves_per_cu=3, m2l_variant=2, dense_levels=0)
             wg.matvec(q, out, stream=s, graph=True)
         s.synchronize()
         ref = we.matvec(qk)
