@@ -7,6 +7,8 @@
  *     p(x) = sum_{y in Y} G(x,y) q(y),   G(x,y) = exp(i kappa |x-y|) / (4 pi |x-y|),
  * for every x in X, with G taken as 0 when |x - y| <= tau = 1e-12 D (the
  * singular pairs of Sec. 5.3; D = side of the bounding cube of X and Y).
+ * With DEFMM_YUKAWA the kernel is the screened one, exp(-kappa |x-y|) /
+ * (4 pi |x-y|), and kappa is its screening constant.
  *
  * The plan (tree, traversal lists, directions, Fourier-domain M2L spectra)
  * is built once per geometry; each matvec then runs entirely on the device.
@@ -57,6 +59,14 @@ typedef enum { DEFMM_M2L_AUTO = 0, DEFMM_M2L_FFT = 1, DEFMM_M2L_DENSE = 2 } defm
    a slower Fourier-path M2L.  Plans whose per-offset table would exceed
    8 GiB use this form whatever the flag. */
 #define DEFMM_COMPRESS_SPECTRA 2u
+/* Screened (Yukawa, modified Helmholtz) kernel G = exp(-kappa r) / (4 pi r)
+   instead of the Helmholtz one.  It is asymptotically smooth and does not
+   oscillate, so the interpolation framework (Sec. 1, Sec. 2) applies without
+   directional expansions: every level is low-frequency, the MAC is the plain
+   one (eq. macdirref with kappa w replaced by 0), and P2P, the spectra and
+   the dense M2L matrices evaluate the screened kernel.  kappa = 0 gives the
+   Laplace kernel either way. */
+#define DEFMM_YUKAWA 4u
 
 typedef struct {
   int32_t order_L;      /* interpolation nodes per dimension, 2..8 (padded FFT length 2L-1) */
@@ -67,7 +77,8 @@ typedef struct {
   int32_t dir_refine;   /* extra 4-fold refinements of the cube-face direction set, 0..4 */
   int32_t precision;    /* defmm_precision */
   int32_t m2l_mode;     /* defmm_m2l_mode */
-  uint32_t flags;       /* DEFMM_SAME_POINTS | DEFMM_COMPRESS_SPECTRA */
+  uint32_t flags;       /* DEFMM_SAME_POINTS | DEFMM_COMPRESS_SPECTRA | DEFMM_YUKAWA;
+                           other bits: DEFMM_ERR_INVALID_ARG */
 } defmm_params;
 
 typedef struct defmm_plan defmm_plan;           /* opaque */
@@ -102,7 +113,8 @@ defmm_status defmm_default_params(defmm_params* out);
    synchronous: X and Y may be freed when it returns.  hip_stream: the stream
    used for the device work of the build (NULL = default stream).
    Errors: DEFMM_ERR_INVALID_ARG for NULL out/prm/X, n < 0, L outside 2..8,
-   ncrit < 1, kappa < 0 or non-finite, eta <= 0, non-finite coordinates.
+   ncrit < 1, kappa < 0 or non-finite, eta <= 0, unknown flag bits, non-finite
+   coordinates.
    nx = 0 or ny = 0 is valid (every potential is then 0). */
 defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int64_t ny,
                                double kappa, const defmm_params* prm, void* hip_stream,

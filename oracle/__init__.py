@@ -40,14 +40,14 @@ def lib():
         L = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
         i64, i32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
-        L.oracle_direct_sum.argtypes = [P, i64, P, i64, P, f64, f64, P, i64, P]
+        L.oracle_direct_sum.argtypes = [P, i64, P, i64, P, f64, f64, P, i64, P, i32]
         L.oracle_direct_sum.restype = None
         L.oracle_lagrange_1d.argtypes = [i32, f64, P]
         L.oracle_directions.argtypes = [i32, P, P]
         L.oracle_directions.restype = i64
-        L.oracle_spectrum.argtypes = [f64, f64, i32, P, P]
-        L.oracle_m2l_fft.argtypes = [f64, f64, i32, P, P, P]
-        L.oracle_m2l_dense.argtypes = [f64, f64, i32, P, P, P]
+        L.oracle_spectrum.argtypes = [f64, f64, i32, P, P, i32]
+        L.oracle_m2l_fft.argtypes = [f64, f64, i32, P, P, P, i32]
+        L.oracle_m2l_dense.argtypes = [f64, f64, i32, P, P, P, i32]
         L.oracle_dft3.argtypes = [i32, P, P, i32]
         L.oracle_p2m.argtypes = [f64, i32, P, f64, P, i64, P, P, P]
         L.oracle_m2m.argtypes = [f64, i32, P, f64, P, P, f64, P, P]
@@ -79,9 +79,16 @@ def _ptr(a):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
 
+# The kernel G(r), r = |x - y|: HELMHOLTZ = exp(i kappa r) / (4 pi r) (the paper's),
+# YUKAWA = exp(-kappa r) / (4 pi r) (screened, non-oscillatory: every level is
+# low-frequency).
+HELMHOLTZ, YUKAWA = 0, 1
+
+
 class _Params(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("ncrit", ctypes.c_int32), ("eta", ctypes.c_double),
-                ("hf_threshold", ctypes.c_double), ("dir_refine", ctypes.c_int32)]
+                ("hf_threshold", ctypes.c_double), ("dir_refine", ctypes.c_int32),
+                ("kernel", ctypes.c_int32)]
 
 
 @dataclass
@@ -91,12 +98,13 @@ class Params:
     eta: float = 1.0
     hf_threshold: float = 2.0
     dir_refine: int = 0
+    kernel: int = HELMHOLTZ
 
     def c(self):
-        return _Params(self.L, self.ncrit, self.eta, self.hf_threshold, self.dir_refine)
+        return _Params(self.L, self.ncrit, self.eta, self.hf_threshold, self.dir_refine, self.kernel)
 
 
-def direct_sum(X, Y, q, kappa, tau, targets=None):
+def direct_sum(X, Y, q, kappa, tau, targets=None, kernel=HELMHOLTZ):
     X = np.ascontiguousarray(X, dtype=np.float64)
     Y = np.ascontiguousarray(Y, dtype=np.float64)
     q = np.ascontiguousarray(q, dtype=np.complex128)
@@ -108,7 +116,7 @@ def direct_sum(X, Y, q, kappa, tau, targets=None):
         nt = tg.shape[0]
     p = np.zeros(nt, dtype=np.complex128)
     lib().oracle_direct_sum(_ptr(X), X.shape[0], _ptr(Y), Y.shape[0], _ptr(q), float(kappa),
-                            float(tau), _ptr(tg), nt, _ptr(p))
+                            float(tau), _ptr(tg), nt, _ptr(p), int(kernel))
     return p
 
 
@@ -126,27 +134,27 @@ def directions(E):
     return d, f
 
 
-def spectrum(kappa, h, L, delta):
+def spectrum(kappa, h, L, delta, kernel=HELMHOLTZ):
     P = 2 * L - 1
     D = np.zeros(P ** 3, dtype=np.complex128)
     dl = np.ascontiguousarray(delta, dtype=np.int32)
-    lib().oracle_spectrum(float(kappa), float(h), L, _ptr(dl), _ptr(D))
+    lib().oracle_spectrum(float(kappa), float(h), L, _ptr(dl), _ptr(D), int(kernel))
     return D.reshape(P, P, P)  # index [mz, my, mx]
 
 
-def m2l_fft(kappa, h, L, delta, M):
+def m2l_fft(kappa, h, L, delta, M, kernel=HELMHOLTZ):
     M = np.ascontiguousarray(M, dtype=np.complex128)
     out = np.zeros(L ** 3, dtype=np.complex128)
     dl = np.ascontiguousarray(delta, dtype=np.int32)
-    lib().oracle_m2l_fft(float(kappa), float(h), L, _ptr(dl), _ptr(M), _ptr(out))
+    lib().oracle_m2l_fft(float(kappa), float(h), L, _ptr(dl), _ptr(M), _ptr(out), int(kernel))
     return out
 
 
-def m2l_dense(kappa, h, L, delta, M):
+def m2l_dense(kappa, h, L, delta, M, kernel=HELMHOLTZ):
     M = np.ascontiguousarray(M, dtype=np.complex128)
     out = np.zeros(L ** 3, dtype=np.complex128)
     dl = np.ascontiguousarray(delta, dtype=np.int32)
-    lib().oracle_m2l_dense(float(kappa), float(h), L, _ptr(dl), _ptr(M), _ptr(out))
+    lib().oracle_m2l_dense(float(kappa), float(h), L, _ptr(dl), _ptr(M), _ptr(out), int(kernel))
     return out
 
 

@@ -17,7 +17,8 @@
  *    (eq. DFTformula up to the normalisation constant).
  *  - w in the MAC (eq. macdirref) is half the cell side; dist(t,s) is the
  *    distance between the two cubes; equality is admissible.
- *  - a level is high-frequency iff kappa*w > hf_threshold.
+ *  - a level is high-frequency iff kappa*w > hf_threshold (never for the
+ *    screened kernel, which does not oscillate).
  *  - directions: projected centres of the faces of the cube (Sec. 4.1.2),
  *    6 * 4^E of them at direction level E, E = 0 at the deepest high-
  *    frequency level, plus dir_refine extra subdivisions.
@@ -53,8 +54,12 @@ static double wall_seconds(void) {
   return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
 }
 
-/* Helmholtz kernel (Sec. 1): G = exp(i kappa r) / (4 pi r). */
-static cplx kernel_G(double r, double kappa) {
+/* The kernel G(r), r = |x - y|:
+     ORACLE_HELMHOLTZ  exp(i kappa r) / (4 pi r)   (Sec. 1, the paper's kernel);
+     ORACLE_YUKAWA     exp(-kappa r) / (4 pi r)    (screened: one of the asymptotically
+                       smooth kernels the interpolation framework covers, Sec. 1). */
+static cplx kernel_G(double r, double kappa, int kernel) {
+  if (kernel == ORACLE_YUKAWA) return exp(-kappa * r) / (4.0 * PI * r);
   return cexp(I * kappa * r) / (4.0 * PI * r);
 }
 
@@ -63,7 +68,7 @@ static cplx kernel_G(double r, double kappa) {
 /* ------------------------------------------------------------------ */
 void oracle_direct_sum(const double* X, int64_t nx, const double* Y, int64_t ny,
                        const double* q, double kappa, double tau,
-                       const int64_t* targets, int64_t nt, double* p) {
+                       const int64_t* targets, int64_t nt, double* p, int32_t kernel) {
   const cplx* qc = (const cplx*)q;
   cplx* pc = (cplx*)p;
   (void)nx;
@@ -76,7 +81,7 @@ void oracle_direct_sum(const double* X, int64_t nx, const double* Y, int64_t ny,
       double dy = X[3 * i + 1] - Y[3 * j + 1];
       double dz = X[3 * i + 2] - Y[3 * j + 2];
       double r = sqrt(dx * dx + dy * dy + dz * dz);
-      if (r > tau) acc += kernel_G(r, kappa) * qc[j];
+      if (r > tau) acc += kernel_G(r, kappa, kernel) * qc[j];
     }
     pc[a] = acc;
   }
@@ -177,7 +182,7 @@ void oracle_dft3(int32_t P, const double* in_, double* out_, int32_t sign) {
 
 /* First column of the circulant embedding (eq. CirculantKernel):
    c[j mod P] = G(h delta + (h/(L-1)) j), j in [-(L-1), L-1]^3. */
-static void circulant_column(double kappa, double h, int L, const int32_t* delta, cplx* c) {
+static void circulant_column(double kappa, int kernel, double h, int L, const int32_t* delta, cplx* c) {
   int P = 2 * L - 1;
   for (int jz = -(L - 1); jz <= L - 1; ++jz)
     for (int jy = -(L - 1); jy <= L - 1; ++jy)
@@ -187,23 +192,23 @@ static void circulant_column(double kappa, double h, int L, const int32_t* delta
         for (int d = 0; d < 3; ++d) z[d] = h * (double)delta[d] + (h / (double)(L - 1)) * (double)j[d];
         double r = sqrt(z[0] * z[0] + z[1] * z[1] + z[2] * z[2]);
         int mx = (jx + P) % P, my = (jy + P) % P, mz = (jz + P) % P;
-        c[mx + P * my + P * P * mz] = kernel_G(r, kappa);
+        c[mx + P * my + P * P * mz] = kernel_G(r, kappa, kernel);
       }
 }
 
 /* Diagonal of the Fourier-domain M2L operator (eq. FourierDiagonal). */
-void oracle_spectrum(double kappa, double h, int32_t L, const int32_t* delta, double* D) {
+void oracle_spectrum(double kappa, double h, int32_t L, const int32_t* delta, double* D, int32_t kernel) {
   int P = 2 * L - 1;
   int64_t n = (int64_t)P * P * P;
   cplx* c = (cplx*)malloc(sizeof(cplx) * n);
-  circulant_column(kappa, h, L, delta, c);
+  circulant_column(kappa, kernel, h, L, delta, c);
   oracle_dft3(P, (const double*)c, D, -1);
   free(c);
 }
 
 /* M2L through the circulant embedding: crop(ifftn(D * fftn(pad(M)))). */
 void oracle_m2l_fft(double kappa, double h, int32_t L, const int32_t* delta,
-                    const double* M_, double* Lout_) {
+                    const double* M_, double* Lout_, int32_t kernel) {
   const cplx* M = (const cplx*)M_;
   cplx* Lout = (cplx*)Lout_;
   int P = 2 * L - 1;
@@ -212,7 +217,7 @@ void oracle_m2l_fft(double kappa, double h, int32_t L, const int32_t* delta,
   cplx* pad = (cplx*)calloc(n, sizeof(cplx));
   cplx* Mt = (cplx*)malloc(sizeof(cplx) * n);
   cplx* back = (cplx*)malloc(sizeof(cplx) * n);
-  oracle_spectrum(kappa, h, L, delta, (double*)D);
+  oracle_spectrum(kappa, h, L, delta, (double*)D, kernel);
   for (int k = 0; k < L * L * L; ++k) {
     int kx = k % L, ky = (k / L) % L, kz = k / (L * L);
     pad[kx + P * ky + P * P * kz] = M[k];
@@ -229,7 +234,7 @@ void oracle_m2l_fft(double kappa, double h, int32_t L, const int32_t* delta,
 
 /* M2L by definition: L(x_k) = sum_l G(x_k - y_l) M(y_l). */
 void oracle_m2l_dense(double kappa, double h, int32_t L, const int32_t* delta,
-                      const double* M_, double* Lout_) {
+                      const double* M_, double* Lout_, int32_t kernel) {
   const cplx* M = (const cplx*)M_;
   cplx* Lout = (cplx*)Lout_;
   int n = L * L * L;
@@ -242,7 +247,7 @@ void oracle_m2l_dense(double kappa, double h, int32_t L, const int32_t* delta,
       for (int d = 0; d < 3; ++d)
         z[d] = h * (double)delta[d] + (h / (double)(L - 1)) * (double)(kk[d] - ll[d]);
       double r = sqrt(z[0] * z[0] + z[1] * z[1] + z[2] * z[2]);
-      acc += kernel_G(r, kappa) * M[l];
+      acc += kernel_G(r, kappa, kernel) * M[l];
     }
     Lout[k] = acc;
   }
@@ -750,9 +755,12 @@ void* oracle_fmm_create(const double* X, int64_t nx, const double* Y, int64_t ny
   F->lstar = -1;
   for (int l = 0; l <= MAXLEV; ++l) {
     double w = ldexp(D, -(l + 1));
-    F->hf[l] = (kappa * w > prm->hf_threshold) ? 1 : 0;
+    /* A screened kernel does not oscillate: every level is low-frequency and
+       the MAC is the plain one (kappa w replaced by 0). */
+    const double kw = prm->kernel == ORACLE_YUKAWA ? 0.0 : kappa * w;
+    F->hf[l] = (kw > prm->hf_threshold) ? 1 : 0;
     if (F->hf[l]) F->lstar = l;
-    double a = fmax(kappa * w, 2.0) / (2.0 * prm->eta);
+    double a = fmax(kw, 2.0) / (2.0 * prm->eta);
     F->thr[l] = a * a;
   }
   F->maxE = -1;
@@ -769,7 +777,7 @@ void* oracle_fmm_create(const double* X, int64_t nx, const double* Y, int64_t ny
     omemo* e = &F->memo.m[i];
     if (F->hf[e->level]) e->dir = best_direction(F, dir_level(F, e->level), e->d);
     e->D = (cplx*)malloc(sizeof(cplx) * P3);
-    oracle_spectrum(kappa, level_h(F, e->level), L, e->d, (double*)e->D);
+    oracle_spectrum(kappa, level_h(F, e->level), L, e->d, (double*)e->D, prm->kernel);
   }
   /* Marks (Alg. 2) then the blank downward pass (Alg. 3). */
   for (int64_t i = 0; i < F->nm2l; ++i) {
@@ -1019,7 +1027,7 @@ static void op_p2p(ofmm* F, const cplx* qs, cplx* ps) {
             const double* y = TY->spts + 3 * j;
             double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
             double r = sqrt(dx * dx + dy * dy + dz * dz);
-            if (r > F->tau) acc += kernel_G(r, F->kappa) * qs[j];
+            if (r > F->tau) acc += kernel_G(r, F->kappa, F->prm.kernel) * qs[j];
           }
         }
       }

@@ -16,28 +16,31 @@
 extern "C" {
 #endif
 
+enum { ORACLE_HELMHOLTZ = 0, ORACLE_YUKAWA = 1 }; /* G = e^{i kappa r}/(4 pi r) or e^{-kappa r}/(4 pi r) */
+
 typedef struct {
   int32_t L;            /* interpolation nodes per dimension (P = 2L-1)            */
   int32_t ncrit;        /* a cell is a leaf iff it holds <= ncrit points             */
   double eta;           /* MAC constant (eq. macdirref)                              */
   double hf_threshold;  /* level is high-frequency iff kappa * w > hf_threshold      */
   int32_t dir_refine;   /* extra 4-fold refinements of the cube-face direction set   */
+  int32_t kernel;       /* ORACLE_HELMHOLTZ or ORACLE_YUKAWA (all levels low-frequency) */
 } oracle_params;
 
 /* Ground truth (eq. fmmsum): p(x_i) = sum_y G(x_i,y) q(y), G(x,y)=0 if |x-y|<=tau. */
 void oracle_direct_sum(const double* X, int64_t nx, const double* Y, int64_t ny,
                        const double* q, double kappa, double tau,
-                       const int64_t* targets, int64_t nt, double* p);
+                       const int64_t* targets, int64_t nt, double* p, int32_t kernel);
 
 /* Building blocks (each pinned on its own by the CPU tests). */
 void oracle_lagrange_1d(int32_t L, double t, double* out);           /* l_m(t), m<L   */
 int64_t oracle_directions(int32_t E, double* dirs, int64_t* father); /* 6*4^E dirs     */
 void oracle_spectrum(double kappa, double h, int32_t L, const int32_t* delta,
-                     double* D);                                        /* fftn(c), P^3 */
+                     double* D, int32_t kernel);                        /* fftn(c), P^3 */
 void oracle_m2l_fft(double kappa, double h, int32_t L, const int32_t* delta,
-                    const double* M, double* Lout);                     /* circulant M2L */
+                    const double* M, double* Lout, int32_t kernel);     /* circulant M2L */
 void oracle_m2l_dense(double kappa, double h, int32_t L, const int32_t* delta,
-                      const double* M, double* Lout);                   /* dense M2L     */
+                      const double* M, double* Lout, int32_t kernel);   /* dense M2L     */
 void oracle_dft3(int32_t P, const double* in, double* out, int32_t sign);
 
 /* Single-expansion operators (Sec. 2.2); u/v = unit direction or NULL.

@@ -153,6 +153,8 @@ static defmm_status validate(const double* X, int64_t nx, const double* Y, int64
     return fail(DEFMM_ERR_INVALID_ARG, "unknown precision");
   if (prm->m2l_mode != DEFMM_M2L_AUTO && prm->m2l_mode != DEFMM_M2L_FFT && prm->m2l_mode != DEFMM_M2L_DENSE)
     return fail(DEFMM_ERR_INVALID_ARG, "unknown m2l_mode");
+  if (prm->flags & ~(DEFMM_SAME_POINTS | DEFMM_COMPRESS_SPECTRA | DEFMM_YUKAWA))
+    return fail(DEFMM_ERR_INVALID_ARG, "unknown flag bits");
   return DEFMM_OK;
 }
 
@@ -176,6 +178,7 @@ static defmm_status plan_build(defmm_plan* plan, const double* X, int64_t nx, co
   bp.kappa = kappa;
   bp.dense_tables = prm->m2l_mode != DEFMM_M2L_FFT;
   bp.compress_spectra = (prm->flags & DEFMM_COMPRESS_SPECTRA) != 0;
+  bp.screened = (prm->flags & DEFMM_YUKAWA) != 0;
   if (host_pointers) {
     for (int64_t i = 0; i < 3 * nx; ++i)
       if (!std::isfinite(X[i])) return fail(DEFMM_ERR_INVALID_ARG, "non-finite coordinate in X");
@@ -190,6 +193,7 @@ static defmm_status plan_build(defmm_plan* plan, const double* X, int64_t nx, co
   P.L = bp.L;
   P.precision = prm->precision;
   P.kappa = kappa;
+  P.screened = bp.screened;
   P.D = H.D;
   for (int d = 0; d < 3; ++d) P.origin[d] = H.origin[d];
   P.tau = H.tau;

@@ -61,6 +61,7 @@ struct DevPlan {
   int num_cu = 256;           // compute units of the device (hipDeviceProp)
   int p2p_waves_per_cu = 2;   // default for new workspaces (see Workspace::p2p_waves)
   double kappa = 0.0, D = 0.0, origin[3] = {0, 0, 0}, tau = 0.0;
+  bool screened = false;  // kernel exp(-kappa r)/(4 pi r) instead of exp(i kappa r)/(4 pi r)
   DevTree tx, ty;
   bool same = false;
   bool host_only = false;  // built by defmm_plan_inspect_create: no device data

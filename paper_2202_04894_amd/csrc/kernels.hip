@@ -148,6 +148,16 @@ __global__ void k_zero(int64_t n, C2<R>* __restrict__ a) {
 }
 
 // ------------------------------------------------------------------ spectra
+// The kernel G(r) in FP64: exp(i kappa r) / (4 pi r), or, screened,
+// exp(-kappa r) / (4 pi r).
+__device__ __forceinline__ C2<double> kernel_fp64(double r, double kappa, int screened) {
+  const double g = 1.0 / (4.0 * M_PI * r);
+  if (screened) return {exp(-kappa * r) * g, 0.0};
+  double s, c;
+  sincos(kappa * r, &s, &c);
+  return {c * g, s * g};
+}
+
 // Fourier-domain M2L diagonal (eq. FourierDiagonal) for each canonical
 // (level, delta): the kernel on the (2L-1)^3 difference grid (eq.
 // CirculantKernel), a 3D DFT in FP64, scaled by 1/P^3 so that F2L is a plain
@@ -156,8 +166,8 @@ __global__ void k_zero(int64_t n, C2<R>* __restrict__ a) {
 // exchanged, so that a permuted read never swaps values after the load.
 template <typename R, int L>
 __global__ __launch_bounds__(256) void k_spectra(int64_t n, const int32_t* __restrict__ lev,
-                                                 const int32_t* __restrict__ delta, double kappa, double D,
-                                                 const int32_t* __restrict__ freq, int nrow,
+                                                 const int32_t* __restrict__ delta, double kappa, int screened,
+                                                 double D, const int32_t* __restrict__ freq, int nrow,
                                                  C2<R>* __restrict__ S) {
   constexpr int P = 2 * L - 1, P3 = P * P * P;
   __shared__ C2<double> a[P3];
@@ -180,11 +190,7 @@ __global__ __launch_bounds__(256) void k_spectra(int64_t n, const int32_t* __res
     double z0 = h * dx + (h / (double)(L - 1)) * (double)j0;
     double z1 = h * dy + (h / (double)(L - 1)) * (double)j1;
     double z2 = h * dz + (h / (double)(L - 1)) * (double)j2;
-    double r = sqrt(z0 * z0 + z1 * z1 + z2 * z2);
-    double s, c;
-    sincos(kappa * r, &s, &c);
-    double g = 1.0 / (4.0 * M_PI * r);
-    a[i] = {c * g, s * g};
+    a[i] = kernel_fp64(sqrt(z0 * z0 + z1 * z1 + z2 * z2), kappa, screened);
   }
   __syncthreads();
   const int stride[3] = {1, P, P * P};
@@ -717,7 +723,7 @@ __global__ __launch_bounds__(256) void k_f2l(int64_t ntgt, const int32_t* __rest
 // of an MFMA A-fragment are contiguous), zero-padded to dense_pad(L).
 template <typename R, int L>
 __global__ __launch_bounds__(256) void k_dense_K(int64_t n, const int32_t* __restrict__ delta, double kappa,
-                                                 double h, C2<R>* __restrict__ Kt) {
+                                                 int screened, double h, C2<R>* __restrict__ Kt) {
   constexpr int L3 = L * L * L, NP = dense_pad(L);
   int64_t o = blockIdx.x;
   if (o >= n) return;
@@ -730,11 +736,8 @@ __global__ __launch_bounds__(256) void k_dense_K(int64_t n, const int32_t* __res
       int rx = r % L, ry = (r / L) % L, rz = r / (L * L);
       int cx = c % L, cy = (c / L) % L, cz = c / (L * L);
       double z0 = h * dx + s * (double)(rx - cx), z1 = h * dy + s * (double)(ry - cy), z2 = h * dz + s * (double)(rz - cz);
-      double rr = sqrt(z0 * z0 + z1 * z1 + z2 * z2);
-      double sn, cs;
-      sincos(kappa * rr, &sn, &cs);
-      double g = 1.0 / (4.0 * M_PI * rr);
-      v = {(R)(cs * g), (R)(sn * g)};
+      const C2<double> g = kernel_fp64(sqrt(z0 * z0 + z1 * z1 + z2 * z2), kappa, screened);
+      v = {(R)g.x, (R)g.y};
     }
     Kt[o * NP * NP + i] = v;
   }
@@ -998,14 +1001,18 @@ __global__ __launch_bounds__(64) void k_l2p(int64_t n, const int32_t* __restrict
 // Lanes are (target, sub-stream) pairs; sources are staged through LDS in
 // tiles of 256; differences are formed in FP64 (coordinates are FP64), the
 // rest in R.  Partial sums per work item are reduced in a fixed order.
-template <typename R>
+
+// One (target, source) term.  kscale is kappa / (2 pi) (Helmholtz: the
+// phase in revolutions for v_sin/v_cos) or kappa log2(e) (screened: the
+// exponent for v_exp) on the complex64 path; the complex128 path uses kappa.
+template <typename R, bool SCREENED>
 __device__ __forceinline__ void p2p_pair(C2<R>& acc, double x0, double x1, double x2, double y0, double y1,
-                                         double y2, C2<R> q, R kap2pi, R kappa, R tau2);
+                                         double y2, C2<R> q, R kscale, R kappa, R tau2);
 
 template <>
-__device__ __forceinline__ void p2p_pair<float>(C2<float>& acc, double x0, double x1, double x2, double y0,
-                                                double y1, double y2, C2<float> q, float kap2pi, float,
-                                                float tau2) {
+__device__ __forceinline__ void p2p_pair<float, false>(C2<float>& acc, double x0, double x1, double x2, double y0,
+                                                       double y1, double y2, C2<float> q, float kap2pi, float,
+                                                       float tau2) {
   float dx = (float)(x0 - y0), dy = (float)(x1 - y1), dz = (float)(x2 - y2);
   float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
   float rinv = __builtin_amdgcn_rsqf(r2);
@@ -1020,9 +1027,23 @@ __device__ __forceinline__ void p2p_pair<float>(C2<float>& acc, double x0, doubl
 }
 
 template <>
-__device__ __forceinline__ void p2p_pair<double>(C2<double>& acc, double x0, double x1, double x2, double y0,
-                                                 double y1, double y2, C2<double> q, double, double kappa,
-                                                 double tau2) {
+__device__ __forceinline__ void p2p_pair<float, true>(C2<float>& acc, double x0, double x1, double x2, double y0,
+                                                      double y1, double y2, C2<float> q, float klog2e, float,
+                                                      float tau2) {
+  float dx = (float)(x0 - y0), dy = (float)(x1 - y1), dz = (float)(x2 - y2);
+  float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+  float rinv = __builtin_amdgcn_rsqf(r2);
+  rinv = r2 > tau2 ? rinv : 0.0f;
+  float r = r2 * rinv;
+  float g = __builtin_amdgcn_exp2f(-r * klog2e) * rinv;  // exp(-kappa r) / r
+  acc.x = fmaf(g, q.x, acc.x);
+  acc.y = fmaf(g, q.y, acc.y);
+}
+
+template <>
+__device__ __forceinline__ void p2p_pair<double, false>(C2<double>& acc, double x0, double x1, double x2, double y0,
+                                                        double y1, double y2, C2<double> q, double, double kappa,
+                                                        double tau2) {
   double dx = x0 - y0, dy = x1 - y1, dz = x2 - y2;
   double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
   if (r2 > tau2) {
@@ -1036,7 +1057,21 @@ __device__ __forceinline__ void p2p_pair<double>(C2<double>& acc, double x0, dou
   }
 }
 
-template <typename R>
+template <>
+__device__ __forceinline__ void p2p_pair<double, true>(C2<double>& acc, double x0, double x1, double x2, double y0,
+                                                       double y1, double y2, C2<double> q, double, double kappa,
+                                                       double tau2) {
+  double dx = x0 - y0, dy = x1 - y1, dz = x2 - y2;
+  double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+  if (r2 > tau2) {
+    double r = sqrt(r2);
+    double g = exp(-kappa * r) / r;
+    acc.x = fma(g, q.x, acc.x);
+    acc.y = fma(g, q.y, acc.y);
+  }
+}
+
+template <typename R, bool SCREENED>
 __device__ __forceinline__ void p2p_item(int64_t w, const int32_t* __restrict__ wi_blk,
                                             const int32_t* __restrict__ wi_seg, const int32_t* __restrict__ seg_first,
                                             const int32_t* __restrict__ seg_count, const int32_t* __restrict__ blk_first,
@@ -1084,7 +1119,7 @@ __device__ __forceinline__ void p2p_item(int64_t w, const int32_t* __restrict__ 
   __syncthreads();
   const int total = pre[ns];
   const R inv4pi = (R)(1.0 / (4.0 * M_PI));
-  const R kap2pi = (R)(kappa / (2.0 * M_PI));
+  const R kscale = (R)(SCREENED ? kappa * 1.4426950408889634 : kappa / (2.0 * M_PI));  // log2(e), 1/(2 pi)
   auto locate = [&](int pos) {
     int lo = 0, hi = ns - 1;
     while (lo < hi) {
@@ -1128,8 +1163,8 @@ __device__ __forceinline__ void p2p_item(int64_t w, const int32_t* __restrict__ 
       for (int k = sub; k < m; k += S) {
         double y0 = sx[k], y1 = sy[k], y2 = sz[k];
         C2<R> q = sq[k];
-        p2p_pair<R>(acca, xa0, xa1, xa2, y0, y1, y2, q, kap2pi, (R)kappa, (R)tau2);
-        p2p_pair<R>(accb, xb0, xb1, xb2, y0, y1, y2, q, kap2pi, (R)kappa, (R)tau2);
+        p2p_pair<R, SCREENED>(acca, xa0, xa1, xa2, y0, y1, y2, q, kscale, (R)kappa, (R)tau2);
+        p2p_pair<R, SCREENED>(accb, xb0, xb1, xb2, y0, y1, y2, q, kscale, (R)kappa, (R)tau2);
       }
     }
     __syncthreads();
@@ -1156,7 +1191,7 @@ __device__ __forceinline__ void p2p_item(int64_t w, const int32_t* __restrict__ 
 // keeping neighbouring items in one L2), then help the other queues.  The
 // free wave slots stay available to the far-field kernels on the other
 // stream.  Every workgroup leaves once all queues are drained.
-template <typename R>
+template <typename R, bool SCREENED>
 __global__ __launch_bounds__(64) void k_p2p(int64_t nwi, int* __restrict__ queue, const int32_t* __restrict__ wi_blk,
                                             const int32_t* __restrict__ wi_seg, const int32_t* __restrict__ seg_first,
                                             const int32_t* __restrict__ seg_count, const int32_t* __restrict__ blk_first,
@@ -1181,7 +1216,7 @@ __global__ __launch_bounds__(64) void k_p2p(int64_t nwi, int* __restrict__ queue
       const int64_t w = lo + next;
       __syncthreads();
       if (w >= hi) break;
-      p2p_item<R>(w, wi_blk, wi_seg, seg_first, seg_count, blk_first, blk_count, X, nx, Y, ny, qs, part, kappa,
+      p2p_item<R, SCREENED>(w, wi_blk, wi_seg, seg_first, seg_count, blk_first, blk_count, X, nx, Y, ny, qs, part, kappa,
                   tau2, sx, sy, sz, sq, red, pre, sfirst);
     }
   }
@@ -1225,7 +1260,8 @@ template <typename R>
 static hipError_t spectra_impl(DevPlan& P, const int32_t* lev, const int32_t* delta, hipStream_t s) {
   if (P.n_spec == 0) return hipSuccess;
   DEFMM_L_SWITCH(P.L, hipLaunchKernelGGL((k_spectra<R, LL>), dim3((unsigned)P.n_spec), dim3(256), 0, s, P.n_spec,
-                                         lev, delta, P.kappa, P.D, P.freq, P.sym ? 2 : 1, (C2<R>*)P.spectra));
+                                         lev, delta, P.kappa, P.screened ? 1 : 0, P.D, P.freq, P.sym ? 2 : 1,
+                                         (C2<R>*)P.spectra));
   return hipGetLastError();
 }
 
@@ -1235,7 +1271,7 @@ static hipError_t dense_K_impl(DevPlan& P, int l, const int32_t* delta, hipStrea
   if (n == 0) return hipSuccess;
   double h = std::ldexp(P.D, -l);
   DEFMM_L_SWITCH(P.L, hipLaunchKernelGGL((k_dense_K<R, LL>), dim3((unsigned)n), dim3(256), 0, s, n, delta, P.kappa,
-                                         h, (C2<R>*)P.dense_K[l]));
+                                         P.screened ? 1 : 0, h, (C2<R>*)P.dense_K[l]));
   return hipGetLastError();
 }
 
@@ -1329,9 +1365,14 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
       hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s2, 8, W.queue);
       const int wpc = (s2 != s) ? W.p2p_waves : 8;  // alone: fill every wave slot
       const unsigned nb = (unsigned)std::min<int64_t>(P.nwi, (int64_t)P.num_cu * wpc);
-      hipLaunchKernelGGL((k_p2p<R>), dim3(nb), dim3(64), 0, s2, P.nwi, W.queue, P.wi_blk, P.wi_seg_begin,
-                         P.seg_first, P.seg_count, P.blk_first, P.blk_count, P.tx.soa, P.tx.n, P.ty.soa, P.ty.n,
-                         (const C2<R>*)qs, part, P.kappa, P.tau * P.tau);
+      if (P.screened)
+        hipLaunchKernelGGL((k_p2p<R, true>), dim3(nb), dim3(64), 0, s2, P.nwi, W.queue, P.wi_blk, P.wi_seg_begin,
+                           P.seg_first, P.seg_count, P.blk_first, P.blk_count, P.tx.soa, P.tx.n, P.ty.soa, P.ty.n,
+                           (const C2<R>*)qs, part, P.kappa, P.tau * P.tau);
+      else
+        hipLaunchKernelGGL((k_p2p<R, false>), dim3(nb), dim3(64), 0, s2, P.nwi, W.queue, P.wi_blk, P.wi_seg_begin,
+                           P.seg_first, P.seg_count, P.blk_first, P.blk_count, P.tx.soa, P.tx.n, P.ty.soa, P.ty.n,
+                           (const C2<R>*)qs, part, P.kappa, P.tau * P.tau);
     }
     tm.end();
     tm.begin(kPassP2PRed, s2);

@@ -38,6 +38,7 @@ struct BuildParams {
   double kappa = 0.0;
   bool dense_tables = true;  // build the dense M2L index tables (the M2L mode may use them)
   bool compress_spectra = false;  // one spectrum per symmetry class (also forced past kMaxSpectraBytes)
+  bool screened = false;  // G = exp(-kappa r)/(4 pi r): no oscillation, every level low-frequency
 };
 
 // One 2^d-tree over a point set, level-major, Morton order inside a level.

@@ -733,9 +733,11 @@ void set_regimes(HostPlan& hp) {
   hp.lstar = -1;
   for (int l = 0; l <= kMaxLevel; ++l) {
     double w = std::ldexp(hp.D, -(l + 1));
-    hp.hf[l] = (hp.prm.kappa * w > hp.prm.hf_threshold) ? 1 : 0;
+    // the screened kernel does not oscillate: the plain MAC at every level
+    const double kw = hp.prm.screened ? 0.0 : hp.prm.kappa * w;
+    hp.hf[l] = (kw > hp.prm.hf_threshold) ? 1 : 0;
     if (hp.hf[l]) hp.lstar = l;
-    double a = std::fmax(hp.prm.kappa * w, 2.0) / (2.0 * hp.prm.eta);
+    double a = std::fmax(kw, 2.0) / (2.0 * hp.prm.eta);
     hp.thr[l] = a * a;
   }
 }

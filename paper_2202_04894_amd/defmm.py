@@ -19,6 +19,7 @@ C128, C64 = 0, 1
 M2L_AUTO, M2L_FFT, M2L_DENSE = 0, 1, 2
 SAME_POINTS = 1
 COMPRESS_SPECTRA = 2
+YUKAWA = 4  # screened kernel exp(-kappa r) / (4 pi r); every level low-frequency
 NUM_PASSES = 12
 
 

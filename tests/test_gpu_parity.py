@@ -41,8 +41,10 @@ def run_gpu(X, q, kappa, prm, Y=None, qY=None, repeat=1):
 
 
 def oracle_params(prm):
+    defmm = _defmm()
     return oracle.Params(L=prm.order_L, ncrit=prm.ncrit, eta=prm.eta, hf_threshold=prm.hf_threshold,
-                         dir_refine=prm.dir_refine)
+                         dir_refine=prm.dir_refine,
+                         kernel=oracle.YUKAWA if prm.flags & defmm.YUKAWA else oracle.HELMHOLTZ)
 
 
 def test_root_leaf_equals_direct_sum():

@@ -39,6 +39,8 @@ CASES = [
     ("ellipsoid", 4000, 64.0, dict(L=5, ncrit=24, hf_threshold=1.0, dir_refine=1, eta=0.5)),
     ("cube_surface", 3000, 0.0, dict(L=3, ncrit=10)),
     ("cube_volume", 2000, 25.0, dict(L=6, ncrit=20, eta=0.7)),
+    # screened kernel at a screening that would make Helmholtz levels high-frequency
+    ("sphere", 3000, 40.0, dict(L=4, ncrit=16, kernel=oracle.YUKAWA)),
 ]
 
 
@@ -46,8 +48,10 @@ CASES = [
 def test_lists_match_oracle(geom, n, kappa, kw):
     X = W.GENERATORS[geom](n, 77)
     o = oracle.FMM(X, None, kappa, oracle.Params(**kw))
+    screened = kw.get("kernel", oracle.HELMHOLTZ) == oracle.YUKAWA
     prm = defmm.Params(order_L=kw["L"], ncrit=kw["ncrit"], eta=kw.get("eta", 1.0),
-                       hf_threshold=kw.get("hf_threshold", 2.0), dir_refine=kw.get("dir_refine", 0))
+                       hf_threshold=kw.get("hf_threshold", 2.0), dir_refine=kw.get("dir_refine", 0),
+                       flags=defmm.YUKAWA if screened else 0)
     p = defmm.Plan.inspect(X, None, kappa, prm)
     D, org = p.geometry()
     Do, oo = o.geometry()
@@ -68,6 +72,8 @@ def test_lists_match_oracle(geom, n, kappa, kw):
     assert st["eff_expansions"] == info["exp_x"]
     assert st["unique_offsets"] == info["unique_offsets"]
     assert st["levels"] == info["levels_x"]
+    if screened:
+        assert st["hf_levels"] == 0 and info["lstar"] == -1
 
 
 def test_lists_match_oracle_distinct_sets():
@@ -92,7 +98,8 @@ def test_lists_match_oracle_distinct_sets():
 def test_invalid_arguments_are_rejected():
     X = W.sphere(100, 1)
     bad = [(dict(order_L=1), 0.0), (dict(order_L=9), 0.0), (dict(ncrit=0), 0.0), (dict(eta=0.0), 0.0),
-           (dict(), -1.0), (dict(), float("nan")), (dict(precision=7), 0.0), (dict(m2l_mode=5), 0.0)]
+           (dict(), -1.0), (dict(), float("nan")), (dict(precision=7), 0.0), (dict(m2l_mode=5), 0.0),
+           (dict(flags=8), 0.0), (dict(flags=defmm.YUKAWA), -2.0)]
     for kw, kappa in bad:
         with pytest.raises(defmm.DefmmError, match="invalid argument"):
             defmm.Plan.inspect(X, None, kappa, defmm.Params(**kw))
