@@ -64,10 +64,10 @@ def parse():
 ACCURATE = {"sphere1m": (0.35, 0.5, 2)}
 
 KNOBS = {"sphere8k": (1.0, 2.0, 0), "sphere1m": (1.0, 2.0, 0), "ellipsoid2m": (1.0, 2.0, 0),
-         "cube8m": (1.0, 2.0, 0)}
+         "cube8m": (1.0, 2.0, 0), "sphere1m_yukawa": (1.0, 2.0, 0)}
 
 
-def direct_sum_sampled(X, q, kappa, tau, targets):
+def direct_sum_sampled(X, q, kappa, tau, targets, screened=False):
     """FP64 direct sum on sampled targets (torch on the device, chunked over sources),
     used only to report the method's error."""
     import torch
@@ -81,7 +81,8 @@ def direct_sum_sampled(X, q, kappa, tau, targets):
         r = torch.sqrt(((xs[:, None, :] - y[None, :, :]) ** 2).sum(-1))
         mask = r > tau
         rr = torch.where(mask, r, torch.ones_like(r))
-        g = torch.where(mask, torch.exp(1j * kappa * rr) / (4 * np.pi * rr), torch.zeros_like(rr, dtype=torch.complex128))
+        k = torch.exp(-kappa * rr) + 0j if screened else torch.exp(1j * kappa * rr)
+        g = torch.where(mask, k / (4 * np.pi * rr), torch.zeros_like(rr, dtype=torch.complex128))
         out += g @ qt[j:j + chunk]
     return out.cpu().numpy()
 
@@ -145,14 +146,16 @@ def cpu_baseline(wl, X, kappa, knobs, perm, n_sample):
     Xs = X[idx]
     q = wl.charges(0)[idx]
     eta, hf, e0 = knobs
+    kern = oracle.YUKAWA if wl.kernel == "yukawa" else oracle.HELMHOLTZ
     F = oracle.FMM(Xs, None, kappa, oracle.Params(L=wl.L, ncrit=wl.ncrit, eta=eta, hf_threshold=hf,
-                                                  dir_refine=e0))
+                                                  dir_refine=e0, kernel=kern))
     F.apply(q)
     secs = F.last_seconds
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": round(n_sample / secs / 1e6, 6), "unit": "Mpoints/s", "cores": cores, "kind": "oracle",
             "sample": f"first {n_sample} of {wl.n} points in Morton order (a patch of the {wl.geometry} at "
-                      f"full density), kappa*D={wl.kappa_d}, L={wl.L}, ncrit={wl.ncrit}; one FP64 matvec "
+                      f"full density), {wl.kernel} kernel, kappa*D={wl.kappa_d}, L={wl.L}, ncrit={wl.ncrit}; "
+                      f"one FP64 matvec "
                       f"(setup excluded) took {secs:.2f} s"}
 
 
@@ -242,6 +245,7 @@ def main():
     if args.e0 is not None:
         e0 = args.e0
     X = wl.points()
+    kflag = defmm.YUKAWA if wl.kernel == "yukawa" else 0
     nsteps = max(args.steps, 1)
     nq = min(nsteps + args.warmup, 64)
 
@@ -249,7 +253,7 @@ def main():
         t0 = time.perf_counter()
         plan = defmm.Plan(X, None, wl.kappa, defmm.Params(order_L=wl.L, ncrit=wl.ncrit, eta=eta,
                                                             hf_threshold=hf, dir_refine=e0, precision=prec,
-                                                            m2l_mode=defmm.M2L_AUTO))
+                                                            m2l_mode=defmm.M2L_AUTO, flags=kflag))
         torch.cuda.synchronize()
         setup = time.perf_counter() - t0
         return plan, defmm.Workspace(plan), setup
@@ -292,7 +296,7 @@ def main():
 
     D, _ = plan64.geometry()
     tg = W.sample_targets(wl.n, args.check_targets, 3000 + wl.seed)
-    pd = direct_sum_sampled(X, wl.charges(0), wl.kappa, 1e-12 * D, tg)
+    pd = direct_sum_sampled(X, wl.charges(0), wl.kappa, 1e-12 * D, tg, screened=bool(kflag))
     rel_direct = float(np.linalg.norm(p128[tg] - pd) / np.linalg.norm(pd))
     rel_direct64 = float(np.linalg.norm(p64[tg] - pd) / np.linalg.norm(pd))
 
@@ -352,7 +356,8 @@ def main():
         "dtype": "c64",
         "data": "synthetic",
         "config": {"workload": f"{wl.name}: {wl.n} points uniform on the unit {wl.geometry}, "
-                               f"kappa*D={wl.kappa_d}, L={wl.L}, leaf<={wl.ncrit}, complex N(0,1) charges",
+                               + (f"screened kernel exp(-kappa r)/(4 pi r), " if kflag else "")
+                               + f"kappa*D={wl.kappa_d}, L={wl.L}, leaf<={wl.ncrit}, complex N(0,1) charges",
                    "eta": eta, "hf_threshold": hf, "dir_refine": e0},
         "p50_ms": round(float(np.percentile(lat64, 50)), 4),
         "p99_ms": round(float(np.percentile(lat64, 99)), 4),

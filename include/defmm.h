@@ -251,8 +251,8 @@ const char* defmm_pass_name(int32_t i);
    written once; e.g. Fourier M2L: each distinct spectrum and each source row of
    (2L-1)^3 values read once, each target row written once; dense M2L: each
    level-local matrix, source and target expansion once), flops[i] = real
-   floating-point
-   operations (a complex multiply-add counts 8).  Either pointer may be NULL;
+   floating-point operations (a complex multiply-add counts 8; a near-field
+   pair counts 23, 17 for the screened kernel).  Either pointer may be NULL;
    each holds DEFMM_NUM_PASSES entries. */
 defmm_status defmm_workspace_pass_work(const defmm_workspace* ws, double* bytes, double* flops);
 

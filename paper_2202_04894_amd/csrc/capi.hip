@@ -855,7 +855,10 @@ defmm_status defmm_workspace_pass_work(const defmm_workspace* ws, double* bytes,
   for (const auto& v : H.l2l_ch) nl2l_ch += (double)v.size();
   b[kPassL2L] = (nl2l + 2 * nl2l_ch) * cs * L3;
   f[kPassL2L] = nl2l * 8 * (3 * L3 * L + 3 * L3);
-  f[kPassP2P] = 23.0 * (double)H.p2p_point_pairs;
+  // per pair: 3 differences, 5 for r^2, rsqrt, r, kappa r, then sin, cos, 2 scalings
+  // and a complex multiply-add (8), or, screened, exp, 1 scaling and a real-by-
+  // complex multiply-add (4)
+  f[kPassP2P] = (P.screened ? 17.0 : 23.0) * (double)H.p2p_point_pairs;
   double nwi = (double)H.wi_blk.size();
   b[kPassP2P] = nwi * 64 * cs;
   b[kPassP2PRed] = nwi * 64 * cs + (double)P.nx * cs;

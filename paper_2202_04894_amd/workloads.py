@@ -104,6 +104,7 @@ class Workload:
     dir_refine: int = 0
     check_targets: int = 0  # 0: all targets against the direct sum
     extra: dict = field(default_factory=dict)
+    kernel: str = "helmholtz"  # or "yukawa": exp(-kappa r)/(4 pi r), kappa the screening constant
 
     @property
     def kappa(self) -> float:
@@ -130,4 +131,7 @@ WORKLOADS = {
                             check_targets=2048),
     "cube8m": Workload("cube8m", "cube_surface", 8388608, 1024.0, 6, 64, "c64", 5,
                        check_targets=2048),
+    # the screened kernel on the sphere1m points: low-frequency expansions only
+    "sphere1m_yukawa": Workload("sphere1m_yukawa", "sphere", 1048576, 16.0, 5, 64, "c64", 2,
+                                check_targets=2048, kernel="yukawa"),
 }
