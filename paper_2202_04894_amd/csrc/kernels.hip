@@ -106,6 +106,18 @@ __device__ __forceinline__ int64_t xcd_item(int64_t n) {
 
 static inline unsigned xcd_grid(int64_t n) { return (unsigned)(8 * ((n + 7) / 8)); }
 
+// Work item (slice, i) of nsl frequency slices x n items, in slice-major
+// order through xcd_item: each XCD walks a contiguous share of the list, so
+// its L2 holds one slice (two at a share boundary) of the rows its items
+// touch.  Launch xcd_grid(nsl * n) blocks; false for the padding blocks.
+__device__ __forceinline__ bool slice_item(int nsl, int64_t n, int& slice, int64_t& i) {
+  const int64_t w = xcd_item((int64_t)nsl * n);
+  if (w >= (int64_t)nsl * n) return false;
+  slice = (int)(w / n);
+  i = w % n;
+  return true;
+}
+
 struct TreeView {
   int64_t n;
   const double* soa;
@@ -488,12 +500,11 @@ __global__ __launch_bounds__(256) void k_m2l(int64_t ntgt, const int32_t* __rest
   }
 }
 
-// M2L Hadamard accumulate, frequency-sliced: the P^3 frequencies are split
-// into 8 slices and workgroup b handles slice b % 8 of target b / 8.  The
-// hardware deals workgroups to the 8 XCDs round-robin, so XCD j only ever
-// touches slice j of every spectrum and every Fourier-domain multipole: each
-// XCD's L2 holds 1/8 of the operands.  One wave per workgroup; the pair loop
-// is unrolled by 4 so each lane keeps 8*NF loads in flight.
+// M2L Hadamard accumulate, frequency-sliced: the row's frequency pairs are
+// split into slices of up to 64 (one per lane) and the (slice, target) items
+// are dealt to the XCDs in contiguous slice-major shares (slice_item), so
+// each XCD's L2 holds one slice of the spectra and Fourier-domain multipoles
+// its targets read.  One wave per workgroup.
 template <typename R>
 struct alignas(2 * sizeof(C2<R>)) C2x2 {
   C2<R> a, b;
@@ -531,17 +542,14 @@ __global__ __launch_bounds__(64) void k_m2l_slice(int64_t ntgt, const int32_t* _
                                                   const int2* __restrict__ pairs, const uint8_t* __restrict__ perm,
                                                   const C2<R>* __restrict__ Mt, const C2<R>* __restrict__ S,
                                                   C2<R>* __restrict__ Lt) {
-  // NSL slices (a multiple of 8): XCD j gets slices j, j+8, ...; the block
-  // order walks all targets of one slice before the next on each XCD.
-  // Each lane owns one frequency pair (xi, -xi) of the slice.
+  // NSL slices; each XCD walks a contiguous share of the slice-major list
+  // (slice_item).  Each lane owns one frequency pair (xi, -xi) of the slice.
   constexpr int P3R = fourier_row(L), SL = P3R / NSL, NP = SL / 2, U = 8;
   static_assert(SL % 2 == 0 && NP <= 64, "a slice holds at most 64 frequency pairs");
   __shared__ uint32_t ptab[48 * 16];
-  const int64_t b = blockIdx.x;
-  const int xcd = (int)(b % 8);
-  const int64_t j = b / 8;
-  const int slice = xcd + 8 * (int)(j / ntgt);
-  const int64_t i = j % ntgt;
+  int slice;
+  int64_t i;
+  if (!slice_item(NSL, ntgt, slice, i)) return;
   const int lane = threadIdx.x;
   const uint8_t* pt = SYM ? load_slice_perm(perm, slice, ptab) : nullptr;
   const bool ok = lane < NP;
@@ -593,11 +601,9 @@ __global__ __launch_bounds__(64) void k_m2l_runs(int64_t ngrp, const int32_t* __
   static_assert(SL % 2 == 0 && NP <= 64, "a slice holds at most 64 frequency pairs");
   constexpr int U = sizeof(R) == 4 ? 2 : 1;  // runs per batch
   __shared__ uint32_t ptab[48 * 16];
-  const int64_t b = blockIdx.x;
-  const int xcd = (int)(b % 8);
-  const int64_t j = b / 8;
-  const int slice = xcd + 8 * (int)(j / ngrp);
-  const int64_t g = j % ngrp;
+  int slice;
+  int64_t g;
+  if (!slice_item(NSL, ngrp, slice, g)) return;
   const int lane = threadIdx.x;
   const uint8_t* pt = SYM ? load_slice_perm(perm, slice, ptab) : nullptr;
   const bool ok = lane < NP;
@@ -1466,24 +1472,24 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
       const int64_t gb = P.lvl_grp[fr_lo[k]], ng = P.lvl_grp[fr_hi[k]] - gb;
       if (P.sym) {
         DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_runs<R, LL, m2l_slices(LL), true>),
-                                             dim3((unsigned)(m2l_slices(LL) * ng)), dim3(64), 0, s, ng,
+                                             dim3(xcd_grid(m2l_slices(LL) * ng)), dim3(64), 0, s, ng,
                                              P.grp_tfirst + gb, P.grp_tcount + gb, P.grp_run_begin + gb, P.runs,
                                              P.perm, (const C2<R>*)Mt, S, Lt));
       } else {
         DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_runs<R, LL, m2l_slices(LL), false>),
-                                             dim3((unsigned)(m2l_slices(LL) * ng)), dim3(64), 0, s, ng,
+                                             dim3(xcd_grid(m2l_slices(LL) * ng)), dim3(64), 0, s, ng,
                                              P.grp_tfirst + gb, P.grp_tcount + gb, P.grp_run_begin + gb, P.runs,
                                              P.perm, (const C2<R>*)Mt, S, Lt));
       }
     } else {
       if (P.sym) {
         DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_slice<R, LL, m2l_slices(LL), true>),
-                                             dim3((unsigned)(m2l_slices(LL) * nt)), dim3(64), 0, s, nt,
+                                             dim3(xcd_grid(m2l_slices(LL) * nt)), dim3(64), 0, s, nt,
                                              P.m2l_begin + tb, (const int2*)P.m2l_pair, P.perm, (const C2<R>*)Mt, S,
                                              Lt + tb * P3R));
       } else {
         DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_slice<R, LL, m2l_slices(LL), false>),
-                                             dim3((unsigned)(m2l_slices(LL) * nt)), dim3(64), 0, s, nt,
+                                             dim3(xcd_grid(m2l_slices(LL) * nt)), dim3(64), 0, s, nt,
                                              P.m2l_begin + tb, (const int2*)P.m2l_pair, P.perm, (const C2<R>*)Mt, S,
                                              Lt + tb * P3R));
       }

@@ -17,15 +17,17 @@ constexpr int kL2PChunk = 256;   // target points per L2P work item
 constexpr int kMaxSegPerItem = 64;  // source segments per P2P work item (one wave-wide scan)
 constexpr double kMaxSpectraBytes = 8.0 * (1ull << 30);  // per-offset spectra beyond this are compressed
 
-// Frequency slices of the M2L kernels (a multiple of 8: one set per XCD) and
-// the Fourier-domain row: frequencies stored as (xi, -xi) pairs, grouped
-// into m2l_slices(L) slices of fourier_cap(L) pairs, each slice closed under
-// the 48 symmetries of the spectra (the packing of the symmetry orbits that
-// make_fourier_layout builds fits these capacities).
-constexpr int m2l_slices(int L) { return L <= 5 ? 8 : (L == 6 ? 16 : 32); }
-constexpr int fourier_cap(int L) {
-  return L == 2 ? 6 : L == 3 ? 12 : L == 4 ? 24 : L == 5 ? 48 : L == 6 ? 48 : L == 7 ? 36 : 60;
+// Frequency slices of the M2L kernels and the Fourier-domain row:
+// frequencies stored as (xi, -xi) pairs, grouped into m2l_slices(L) slices of
+// fourier_cap(L) pairs, each slice closed under the 48 symmetries of the
+// spectra.  A wave's lane owns one pair of a slice, so 64-pair slices keep
+// every lane of a load busy; the counts are the fewest slices into which
+// make_fourier_layout's packing of the symmetry orbits fits (95 % full at
+// L >= 5).
+constexpr int m2l_slices(int L) {
+  return L <= 3 ? 1 : L == 4 ? 3 : L == 5 ? 6 : L == 6 ? 11 : L == 7 ? 18 : 28;
 }
+constexpr int fourier_cap(int L) { return L == 2 ? 14 : 64; }
 constexpr int fourier_row(int L) { return 2 * m2l_slices(L) * fourier_cap(L); }
 
 struct BuildParams {

@@ -129,8 +129,8 @@ def test_compressed_spectra_match_oracle(geom, n, kappa, kw):
 
 @pytest.mark.parametrize("L", [2, 7, 8])
 def test_fourier_path_every_order(L):
-    """The orders outside the main cases (row layouts of 6, 36 and 60 pairs per
-    slice, 8 and 32 slices): complex128 Fourier M2L, per-offset and
+    """The orders outside the main cases (one slice of 14 pairs at L = 2, 18 and 28
+    slices of 64 at L = 7 and 8): complex128 Fourier M2L, per-offset and
     compressed spectra, against the oracle to rounding."""
     defmm = _defmm()
     n = {2: 1500, 7: 800, 8: 600}[L]
