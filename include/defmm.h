@@ -45,7 +45,8 @@ typedef enum {
    the same L^3 x L^3 interpolated kernel matrix per (level, offset) directly):
      DEFMM_M2L_FFT    circulant embedding + FFT-diagonal product at every level;
      DEFMM_M2L_DENSE  dense matrix-matrix products on the matrix cores at every
-                      level whose matrices fit (<= 2 GiB per level, 8 GiB in all),
+                      level whose matrices fit (<= 2 GiB per level, 8 GiB in all)
+                      and whose per-pair products fit the workspace (<= 8 GiB),
                       Fourier form elsewhere;
      DEFMM_M2L_AUTO   the plan builds the dense matrices where they fit, the
                       workspace starts on the Fourier form and

@@ -301,6 +301,10 @@ defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int
           if (noff == 0) continue;
           size_t bytes = (size_t)noff * per_off;
           if (bytes > (2ull << 30) || total + bytes > (8ull << 30)) continue;
+          // the workspace holds one product per pair of the largest dense level
+          const size_t slot_bytes = (size_t)(P.dns_pair_begin[l + 1] - P.dns_pair_begin[l]) *
+                                    (size_t)(P.L * P.L * P.L) * csize(P);
+          if (slot_bytes > kMaxDenseSlotBytes) continue;
           std::vector<int32_t> dl(3 * noff);
           for (int64_t i = 0; i < noff; ++i)
             for (int d = 0; d < 3; ++d) dl[3 * i + d] = H.offsets[H.dns_off[P.dns_off_begin[l] + i]].d[d];
@@ -393,11 +397,16 @@ defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int
   }
 }
 
+// Device bytes of one workspace: exactly the buffers workspace creation
+// allocates (charges, potentials, expansions, Fourier rows, near-field
+// partials, dense-M2L slots, work counters).
 static size_t workspace_bytes(const DevPlan& P) {
   size_t cs = csize(P);
   int L3 = P.L * P.L * P.L, P3 = fourier_row(P.L);
   return cs * ((size_t)P.ny + (size_t)P.nx + (size_t)P.ty.nexp * L3 + (size_t)P.tx.nexp * L3 +
-               (size_t)P.n_m2f * P3 + (size_t)P.nwi * 64 + (size_t)P.n_m2l_tgt * P3);
+               (size_t)P.n_m2f * P3 + (size_t)P.nwi * 64 + (size_t)P.n_m2l_tgt * P3 +
+               (size_t)P.dense_slots_max * L3) +
+         8 * sizeof(int);
 }
 
 defmm_status defmm_plan_footprint(const defmm_plan* plan, size_t* resident, size_t* ws) {

@@ -16,6 +16,7 @@ constexpr int kP2PChunk = 2048;  // source points per P2P work item (balance)
 constexpr int kL2PChunk = 256;   // target points per L2P work item
 constexpr int kMaxSegPerItem = 64;  // source segments per P2P work item (one wave-wide scan)
 constexpr double kMaxSpectraBytes = 8.0 * (1ull << 30);  // per-offset spectra beyond this are compressed
+constexpr size_t kMaxDenseSlotBytes = 8ull << 30;  // dense-M2L per-pair products of one level, at most
 
 // Frequency slices of the M2L kernels and the Fourier-domain row:
 // frequencies stored as (xi, -xi) pairs, grouped into m2l_slices(L) slices of
