@@ -177,6 +177,7 @@ static defmm_status plan_build(defmm_plan* plan, const double* X, int64_t nx, co
   bp.same_points = same;
   bp.kappa = kappa;
   bp.dense_tables = prm->m2l_mode != DEFMM_M2L_FFT;
+  bp.csize = prm->precision == DEFMM_C128 ? 16 : 8;
   bp.compress_spectra = (prm->flags & DEFMM_COMPRESS_SPECTRA) != 0;
   bp.screened = (prm->flags & DEFMM_YUKAWA) != 0;
   if (host_pointers) {
@@ -294,17 +295,13 @@ defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int
       P.dense_ok.assign(nl, 0);
       P.m2l_mode = prm->m2l_mode;
       if (prm->m2l_mode != DEFMM_M2L_FFT) {
+        // the builder packed tables only for the levels whose matrices and
+        // per-pair products fit (dense_level_fits)
         const size_t per_off = (size_t)dense_pad(P.L) * dense_pad(P.L) * csize(P);
-        size_t total = 0;
         for (int l = 0; l < nl; ++l) {
           int64_t noff = P.dns_off_begin[l + 1] - P.dns_off_begin[l];
           if (noff == 0) continue;
-          size_t bytes = (size_t)noff * per_off;
-          if (bytes > (2ull << 30) || total + bytes > (8ull << 30)) continue;
-          // the workspace holds one product per pair of the largest dense level
-          const size_t slot_bytes = (size_t)(P.dns_pair_begin[l + 1] - P.dns_pair_begin[l]) *
-                                    (size_t)(P.L * P.L * P.L) * csize(P);
-          if (slot_bytes > kMaxDenseSlotBytes) continue;
+          const size_t bytes = (size_t)noff * per_off;
           std::vector<int32_t> dl(3 * noff);
           for (int64_t i = 0; i < noff; ++i)
             for (int d = 0; d < 3; ++d) dl[3 * i + d] = H.offsets[H.dns_off[P.dns_off_begin[l] + i]].d[d];
@@ -312,7 +309,6 @@ defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int
           int32_t* ddl = upload(P, dl);
           check(compute_dense_K(P, l, ddl, s), "dense K launch");
           P.dense_ok[l] = 1;
-          total += bytes;
           P.dense_slots_max = std::max<int64_t>(P.dense_slots_max, P.dns_pair_begin[l + 1] - P.dns_pair_begin[l]);
         }
         check(hipStreamSynchronize(s), "dense K");

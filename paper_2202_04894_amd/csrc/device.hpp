@@ -12,8 +12,6 @@
 
 namespace defmm {
 
-// Dense M2L: L^3 padded to a multiple of 16 (the MFMA tile edge).
-__host__ __device__ constexpr int dense_pad(int L) { return ((L * L * L + 15) / 16) * 16; }
 
 // Pass indices for timing and work accounting.
 enum Pass {

@@ -16,7 +16,19 @@ constexpr int kP2PChunk = 2048;  // source points per P2P work item (balance)
 constexpr int kL2PChunk = 256;   // target points per L2P work item
 constexpr int kMaxSegPerItem = 64;  // source segments per P2P work item (one wave-wide scan)
 constexpr double kMaxSpectraBytes = 8.0 * (1ull << 30);  // per-offset spectra beyond this are compressed
-constexpr size_t kMaxDenseSlotBytes = 8ull << 30;  // dense-M2L per-pair products of one level, at most
+
+// Dense M2L: L^3 padded to a multiple of 16 (the MFMA tile edge).
+constexpr int dense_pad(int L) { return ((L * L * L + 15) / 16) * 16; }
+
+// Whether a level may run the dense M2L: its noff matrices (dense_pad(L)^2
+// complex of cs bytes each) fit 2 GiB and what is left of 8 GiB after the
+// matrices of the dense levels below (used), and one product per pair
+// (npairs x L^3 complex, the workspace's slots) fits 8 GiB.
+inline bool dense_level_fits(int L, size_t cs, int64_t noff, int64_t npairs, size_t used) {
+  const size_t mat = (size_t)noff * dense_pad(L) * dense_pad(L) * cs;
+  const size_t slots = (size_t)npairs * (size_t)(L * L * L) * cs;
+  return noff > 0 && mat <= (2ull << 30) && used + mat <= (8ull << 30) && slots <= (8ull << 30);
+}
 
 // Frequency slices of the M2L kernels and the Fourier-domain row:
 // frequencies stored as (xi, -xi) pairs, grouped into m2l_slices(L) slices of
@@ -40,6 +52,7 @@ struct BuildParams {
   bool same_points = false;
   double kappa = 0.0;
   bool dense_tables = true;  // build the dense M2L index tables (the M2L mode may use them)
+  int csize = 8;             // bytes of one complex value of the matvec (8: complex64, 16: complex128)
   bool compress_spectra = false;  // one spectrum per symmetry class (also forced past kMaxSpectraBytes)
   bool screened = false;  // G = exp(-kappa r)/(4 pi r): no oscillation, every level low-frequency
 };

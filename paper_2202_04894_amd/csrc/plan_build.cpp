@@ -554,24 +554,37 @@ void build_tables(HostPlan& hp) {
       hp.lvl_m2f[l + 1] += hp.lvl_m2f[l];
     }
     if ((int)hp.m2l_level_tgt.size() < nl + 1) hp.m2l_level_tgt.resize(nl + 1, hp.m2l_level_tgt.back());
-    // dense M2L tables, offset-major per level (only when the M2L mode may use them)
+    // dense M2L tables, offset-major per level (only when the M2L mode may use
+    // them, and only for the levels whose matrices and products fit)
     hp.dns_off_begin.assign(1, 0);
     hp.dns_pair_begin.assign(1, 0);
     hp.dns_tile_begin.assign(1, 0);
     std::vector<int32_t> local(hp.prm.dense_tables ? hp.offsets.size() : 0, -1);
+    size_t dense_used = 0;
     for (int l = 0; l < nl; ++l) {
-      if (!hp.prm.dense_tables) {
-        hp.dns_off_begin.push_back(0);
-        hp.dns_pair_begin.push_back(0);
-        hp.dns_tile_begin.push_back(0);
-        continue;
-      }
       int32_t tb = hp.m2l_level_tgt[l], te = hp.m2l_level_tgt[l + 1];
       int32_t kb = hp.m2l_begin[tb], ke = hp.m2l_begin[te];
       std::vector<int32_t> offs;
-      for (int32_t k = kb; k < ke; ++k) offs.push_back(hp.m2l_off[k]);
-      std::sort(offs.begin(), offs.end());
-      offs.erase(std::unique(offs.begin(), offs.end()), offs.end());
+      if (hp.prm.dense_tables) {
+        int64_t noff = 0;
+        for (int32_t k = kb; k < ke; ++k)
+          if (local[hp.m2l_off[k]] != -2 - l) {
+            local[hp.m2l_off[k]] = -2 - l;
+            ++noff;
+          }
+        if (dense_level_fits(hp.prm.L, (size_t)hp.prm.csize, noff, ke - kb, dense_used)) {
+          for (int32_t k = kb; k < ke; ++k) offs.push_back(hp.m2l_off[k]);
+          std::sort(offs.begin(), offs.end());
+          offs.erase(std::unique(offs.begin(), offs.end()), offs.end());
+          dense_used += (size_t)noff * dense_pad(hp.prm.L) * dense_pad(hp.prm.L) * (size_t)hp.prm.csize;
+        }
+      }
+      if (offs.empty()) {
+        hp.dns_off_begin.push_back((int32_t)hp.dns_off.size());
+        hp.dns_pair_begin.push_back((int32_t)hp.dns_src.size());
+        hp.dns_tile_begin.push_back((int32_t)hp.dns_tile_off.size());
+        continue;
+      }
       for (size_t i = 0; i < offs.size(); ++i) local[offs[i]] = (int32_t)i;
       std::vector<std::pair<int32_t, int32_t>> pr;  // (local offset, CSR position)
       for (int32_t k = kb; k < ke; ++k) pr.push_back({local[hp.m2l_off[k]], k});
