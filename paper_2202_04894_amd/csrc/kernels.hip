@@ -75,6 +75,34 @@ __device__ __forceinline__ C2<float> expi<float>(double a) {
   return {c, s};
 }
 
+// sin and cos of 2 pi t for t in turns, FP64: reduction to the nearest
+// quarter turn q/4 (g = t - q/4 in [-1/8, 1/8], exact), x = 2 pi g, the Taylor
+// series of sin x to x^17 and of cos x to x^18 (truncation below 1e-19 for
+// |x| <= pi/4), then the rotation by q quarter turns.
+__device__ __forceinline__ void sincos_turns(double t, double& s, double& c) {
+  constexpr double S[9] = {1.0, -1.0 / 6.0, 1.0 / 120.0, -1.0 / 5040.0, 1.0 / 362880.0, -1.0 / 39916800.0,
+                           1.0 / 6227020800.0, -1.0 / 1307674368000.0, 1.0 / 355687428096000.0};
+  constexpr double C[10] = {1.0, -1.0 / 2.0, 1.0 / 24.0, -1.0 / 720.0, 1.0 / 40320.0, -1.0 / 3628800.0,
+                            1.0 / 479001600.0, -1.0 / 87178291200.0, 1.0 / 20922789888000.0,
+                            -1.0 / 6402373705728000.0};
+  const double q = rint(4.0 * t);
+  const double x = (t - 0.25 * q) * 6.283185307179586477;
+  const double x2 = x * x;
+  double ps = S[8], pc = C[9];
+#pragma unroll
+  for (int k = 7; k >= 0; --k) ps = fma(ps, x2, S[k]);
+#pragma unroll
+  for (int k = 8; k >= 0; --k) pc = fma(pc, x2, C[k]);
+  const double sn = ps * x;
+  const int qi = (int)((long long)q & 3);
+  s = (qi & 1) ? pc : sn;
+  c = (qi & 1) ? -sn : pc;
+  if (qi & 2) {
+    s = -s;
+    c = -c;
+  }
+}
+
 // Lagrange basis on the L equispaced nodes j/(L-1) of [0,1] (Sec. 2.3).
 template <typename R, int L>
 __device__ __forceinline__ void lagrange(R t, R* w) {
@@ -1008,9 +1036,11 @@ __global__ __launch_bounds__(64) void k_l2p(int64_t n, const int32_t* __restrict
 // tiles of 256; differences are formed in FP64 (coordinates are FP64), the
 // rest in R.  Partial sums per work item are reduced in a fixed order.
 
-// One (target, source) term.  kscale is kappa / (2 pi) (Helmholtz: the
-// phase in revolutions for v_sin/v_cos) or kappa log2(e) (screened: the
-// exponent for v_exp) on the complex64 path; the complex128 path uses kappa.
+// One (target, source) term.  kscale is kappa / (2 pi) for the Helmholtz
+// kernel (the phase in turns: v_sin/v_cos on the complex64 path,
+// sincos_turns on the complex128 path) and kappa log2(e) for the screened
+// one (the exponent for v_exp on the complex64 path; the complex128 path
+// takes exp(-kappa r) from kappa).
 template <typename R, bool SCREENED>
 __device__ __forceinline__ void p2p_pair(C2<R>& acc, double x0, double x1, double x2, double y0, double y1,
                                          double y2, C2<R> q, R kscale, R kappa, R tau2);
@@ -1048,15 +1078,18 @@ __device__ __forceinline__ void p2p_pair<float, true>(C2<float>& acc, double x0,
 
 template <>
 __device__ __forceinline__ void p2p_pair<double, false>(C2<double>& acc, double x0, double x1, double x2, double y0,
-                                                        double y1, double y2, C2<double> q, double, double kappa,
+                                                        double y1, double y2, C2<double> q, double kap2pi, double,
                                                         double tau2) {
   double dx = x0 - y0, dy = x1 - y1, dz = x2 - y2;
   double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
   if (r2 > tau2) {
-    double r = sqrt(r2);
-    double rinv = 1.0 / r;
+    // 1/r from v_rsq_f64 and two Newton steps, y <- y (3 - r2 y^2) / 2
+    double rinv = __builtin_amdgcn_rsq(r2);
+    rinv = rinv * fma(-0.5 * r2, rinv * rinv, 1.5);
+    rinv = rinv * fma(-0.5 * r2, rinv * rinv, 1.5);
+    const double r = r2 * rinv;
     double s, c;
-    sincos(kappa * r, &s, &c);
+    sincos_turns(r * kap2pi, s, c);  // e^{i kappa r}
     double gr = c * rinv, gi = s * rinv;
     acc.x = fma(gr, q.x, fma(-gi, q.y, acc.x));
     acc.y = fma(gr, q.y, fma(gi, q.x, acc.y));
