@@ -50,31 +50,6 @@ __device__ __forceinline__ C2<R> cscale(C2<R> a, R s) {
   return {a.x * s, a.y * s};
 }
 
-// exp(i a) for an FP64 argument.
-template <typename R>
-__device__ __forceinline__ C2<R> expi(double a);
-
-template <>
-__device__ __forceinline__ C2<double> expi<double>(double a) {
-  double s, c;
-  sincos(a, &s, &c);
-  return {c, s};
-}
-
-template <>
-__device__ __forceinline__ C2<float> expi<float>(double a) {
-  // Cody-Waite reduction by 2 pi in FP64 (two-term constant), then float sincos.
-  const double inv2pi = 0.15915494309189533577;
-  const double twopi_hi = 6.283185307179586232;
-  const double twopi_lo = 2.4492935982947064e-16;
-  double k = rint(a * inv2pi);
-  double r = fma(-k, twopi_hi, a);
-  r = fma(-k, twopi_lo, r);
-  float s, c;
-  sincosf((float)r, &s, &c);
-  return {c, s};
-}
-
 // sin and cos of 2 pi t for t in turns, FP64: reduction to the nearest
 // quarter turn q/4 (g = t - q/4 in [-1/8, 1/8], exact), x = 2 pi g, the Taylor
 // series of sin x to x^17 and of cos x to x^18 (truncation below 1e-19 for
@@ -101,6 +76,26 @@ __device__ __forceinline__ void sincos_turns(double t, double& s, double& c) {
     s = -s;
     c = -c;
   }
+}
+
+// exp(i a) for an FP64 argument a (radians), through turns t = a / (2 pi):
+// sincos_turns (complex128), or t reduced in FP64 to its fraction of a turn
+// and passed to v_sin_f32 / v_cos_f32, which take turns (complex64).
+template <typename R>
+__device__ __forceinline__ C2<R> expi(double a);
+
+template <>
+__device__ __forceinline__ C2<double> expi<double>(double a) {
+  double s, c;
+  sincos_turns(a * 0.15915494309189533577, s, c);
+  return {c, s};
+}
+
+template <>
+__device__ __forceinline__ C2<float> expi<float>(double a) {
+  const double t = a * 0.15915494309189533577;
+  const float f = (float)(t - rint(t));
+  return {__builtin_amdgcn_cosf(f), __builtin_amdgcn_sinf(f)};
 }
 
 // Lagrange basis on the L equispaced nodes j/(L-1) of [0,1] (Sec. 2.3).
