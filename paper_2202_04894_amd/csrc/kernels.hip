@@ -408,10 +408,25 @@ __global__ __launch_bounds__(256) void k_m2f(int64_t n, const int32_t* __restric
   int tid = threadIdx.x;
   if (tid < P) W[tid] = expi<R>(-2.0 * M_PI * (double)tid / (double)P);
   for (int p = tid; p < fourier_row(L); p += 256) fq[p] = freq[p];
+  // the next expansion's values are loaded while the current one is transformed
+  constexpr int NV = (L3 + 255) / 256;
+  C2<R> nxt[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int i = tid + 256 * v;
+    nxt[v] = i < L3 ? M[(int64_t)src[i0] * L3 + i] : C2<R>{(R)0, (R)0};
+  }
   for (int64_t item = i0; item < i1; ++item) {
-    int e = src[item];
-    for (int i = tid; i < L3; i += 256) a[i] = M[(int64_t)e * L3 + i];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      if (tid + 256 * v < L3) a[tid + 256 * v] = nxt[v];
     __syncthreads();
+    if (item + 1 < i1) {
+      const int64_t e = src[item + 1];
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        if (tid + 256 * v < L3) nxt[v] = M[e * L3 + tid + 256 * v];
+    }
     for (int i = tid; i < P * L * L; i += 256) {
       int xi = i % P, rest = i / P;
       C2<R> s = {(R)0, (R)0};
@@ -705,14 +720,32 @@ __global__ __launch_bounds__(256) void k_f2l(int64_t ntgt, const int32_t* __rest
   int tid = threadIdx.x;
   for (int p = tid; p < fourier_row(L); p += NT) fq[p] = freq[p];
   if (tid < P) W[tid] = expi<R>(2.0 * M_PI * (double)tid / (double)P);
+  // the next row is loaded while the current one is transformed
+  constexpr int NV = (fourier_row(L) + NT - 1) / NT;
+  C2<R> nxt[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const int p = tid + NT * v;
+    nxt[v] = p < fourier_row(L) ? Lt[ch * kFourierItems * fourier_row(L) + p] : C2<R>{(R)0, (R)0};
+  }
   __syncthreads();
   for (int64_t i = ch * kFourierItems; i < i1; ++i) {
-    for (int p = tid; p < fourier_row(L); p += NT) {
-      const int f = fq[p];
-      const C2<R> v = Lt[i * fourier_row(L) + p];
-      if (f >= 0) A[f] = v;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int p = tid + NT * v;
+      if (p < fourier_row(L)) {
+        const int f = fq[p];
+        if (f >= 0) A[f] = nxt[v];
+      }
     }
     __syncthreads();
+    if (i + 1 < i1) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int p = tid + NT * v;
+        if (p < fourier_row(L)) nxt[v] = Lt[(i + 1) * fourier_row(L) + p];
+      }
+    }
     for (int j = tid; j < P * P * L; j += NT) {
       int xy = j % (P * P), kz = j / (P * P);
       C2<R> s = {(R)0, (R)0};
