@@ -926,9 +926,13 @@ __global__ __launch_bounds__(round64(L* L* L)) void k_l2l(int64_t n, const int32
   double hc = ldexp(g.D, -T.level[c]), hp = 2.0 * hc;
   int tid = threadIdx.x;
   int hx = tid % L, hy = (tid / L) % L, hz = tid / (L * L);
+  // the son's current values and its first father's, loaded before any work
+  const int k0 = begin[item], k1 = begin[item + 1];
+  const C2<R> cur = tid < L3 ? Lx[(int64_t)ce * L3 + tid] : C2<R>{(R)0, (R)0};
+  C2<R> fv = (tid < L3 && k0 < k1) ? Lx[(int64_t)par[k0] * L3 + tid] : C2<R>{(R)0, (R)0};
   son_matrices<R, L>(A);
   C2<R> acc = {(R)0, (R)0};
-  for (int k = begin[item]; k < begin[item + 1]; ++k) {
+  for (int k = k0; k < k1; ++k) {
     int pe = par[k];
     int o = oct[k];
     int b[3] = {o & 1, (o >> 1) & 1, (o >> 2) & 1};
@@ -940,8 +944,9 @@ __global__ __launch_bounds__(round64(L* L* L)) void k_l2l(int64_t n, const int32
       pho[d][r] = expi<R>(g.kappa * hc * v[d] * ((double)b[d] + (double)r / (double)(L - 1)));
     }
     __syncthreads();
-    if (tid < L3) b0[tid] = cmul(cmul(Lx[(int64_t)pe * L3 + tid], phi[0][hx]), cmul(phi[1][hy], phi[2][hz]));
+    if (tid < L3) b0[tid] = cmul(cmul(fv, phi[0][hx]), cmul(phi[1][hy], phi[2][hz]));
     __syncthreads();
+    if (tid < L3 && k + 1 < k1) fv = Lx[(int64_t)par[k + 1] * L3 + tid];
     if (tid < L3) {  // (hx, ky, kz)
       C2<R> s = {(R)0, (R)0};
 #pragma unroll
@@ -965,10 +970,7 @@ __global__ __launch_bounds__(round64(L* L* L)) void k_l2l(int64_t n, const int32
       acc.y += t.y;
     }
   }
-  if (tid < L3) {
-    C2<R> cur = Lx[(int64_t)ce * L3 + tid];
-    Lx[(int64_t)ce * L3 + tid] = {cur.x + acc.x, cur.y + acc.y};
-  }
+  if (tid < L3) Lx[(int64_t)ce * L3 + tid] = {cur.x + acc.x, cur.y + acc.y};
 }
 
 // ------------------------------------------------------------------ L2P
