@@ -61,7 +61,7 @@ def parse():
 # Knobs per workload: (eta, hf_threshold, dir_refine).
 # Knobs (eta, hf_threshold, dir_refine) at which the method error against the
 # FP64 direct sum is below 1e-4 on that workload (found by a sweep on the device).
-ACCURATE = {"sphere1m": (0.3, 0.75, 1)}
+ACCURATE = {"sphere1m": (0.3, 0.75, 1), "ellipsoid2m": (0.3, 0.75, 1)}
 
 KNOBS = {"sphere8k": (1.0, 2.0, 0), "sphere1m": (1.0, 2.0, 0), "ellipsoid2m": (1.0, 2.0, 0),
          "cube8m": (1.0, 2.0, 0), "sphere1m_yukawa": (1.0, 2.0, 0)}
