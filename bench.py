@@ -226,8 +226,8 @@ def run_serving(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is "
-              f"described in DESIGN.md and not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the sharding by target "
+              f"across GPUs is designed but not built", file=sys.stderr)
         sys.exit(2)
     if args.serving:
         run_serving(args)

@@ -32,7 +32,7 @@ typedef enum {
   DEFMM_ERR_INVALID_ARG = 1,   /* bad pointer, size or parameter; nothing allocated */
   DEFMM_ERR_OUT_OF_MEMORY = 2, /* device or host allocation failed; partial state freed */
   DEFMM_ERR_DEVICE = 3,        /* a HIP runtime call failed */
-  DEFMM_ERR_UNSUPPORTED = 4    /* a parameter outside what this build implements */
+  DEFMM_ERR_UNSUPPORTED = 4    /* a parameter outside what the library implements */
 } defmm_status;
 
 typedef enum {
