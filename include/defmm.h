@@ -274,6 +274,15 @@ defmm_status defmm_workspace_pass_work(const defmm_workspace* ws, double* bytes,
 defmm_status defmm_fourier_layout(int32_t L, int32_t* slices, int32_t* cap, int32_t* row, int32_t* freq,
                                   uint8_t* perm);
 
+/* Direction set of direction level E (Sec. 4.1.2, Sec. 2.1), for inspection
+   and tests: *n = 6 * 4^E unit vectors, the projected centres of the cube's
+   face patches when each face is split 2^E x 2^E, index face * 4^E + i * 2^E
+   + j (faces +x, -x, +y, -y, +z, -z), and the index of the father direction
+   at E - 1 (-1 at E = 0).  dirs (optional, [n x 3] FP64) and father
+   (optional, n int64) are host arrays.  Errors: DEFMM_ERR_INVALID_ARG for E
+   outside 0..12 or NULL n. */
+defmm_status defmm_directions(int32_t E, int64_t* n, double* dirs, int64_t* father);
+
 /* Canonical representative of an M2L offset under the 48 signed axis
    permutations (Sec. 4.3), for inspection and tests.  d: 3 integers; d0
    receives the sorted absolute values (ascending) and *code the symmetry

@@ -789,6 +789,22 @@ defmm_status defmm_fourier_layout(int32_t L, int32_t* slices, int32_t* cap, int3
   }
 }
 
+defmm_status defmm_directions(int32_t E, int64_t* n, double* dirs, int64_t* father) {
+  if (E < 0 || E > 12 || !n) return fail(DEFMM_ERR_INVALID_ARG, "bad direction level");
+  *n = num_directions(E);
+  if (!dirs && !father) return DEFMM_OK;
+  try {
+    std::vector<double> d(3 * (size_t)*n);
+    std::vector<int64_t> f((size_t)*n);
+    make_directions(E, d.data(), f.data());
+    if (dirs) std::memcpy(dirs, d.data(), d.size() * sizeof(double));
+    if (father) std::memcpy(father, f.data(), f.size() * sizeof(int64_t));
+    return DEFMM_OK;
+  } catch (const std::exception& e) {
+    return fail(DEFMM_ERR_OUT_OF_MEMORY, e.what());
+  }
+}
+
 defmm_status defmm_canonical_offset(const int32_t* d, int32_t* d0, int32_t* code) {
   if (!d || !d0 || !code) return fail(DEFMM_ERR_INVALID_ARG, "NULL argument");
   *code = canonical_offset(d, d0);

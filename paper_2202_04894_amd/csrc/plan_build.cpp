@@ -197,25 +197,39 @@ struct OffsetMap {
 
 int64_t num_directions(int E) { return 6ll << (2 * E); }
 
-// Projected face-patch centres of the cube (Sec. 4.1.2), index
-// face*4^E + i*2^E + j, father = enclosing patch at E-1.
+// Direction tree (Sec. 4.1.2, Sec. 2.1), built by splitting patches: every face
+// patch of level E-1 splits into its four quarter patches at level E.  Scaled by
+// 2^E, a patch centre has the face coordinate +-2^E and odd free coordinates;
+// splitting maps a free coordinate k of the father to 2k-1 and 2k+1 (k = 0 at
+// E = 0).  The direction is the integer vector n over |n|: every quantity before
+// the square root is an exact integer in FP64 up to E = 25.  Index
+// face*4^E + i*2^E + j (faces +x,-x,+y,-y,+z,-z; i, j along the two free axes in
+// increasing order), father = the patch (i/2, j/2) of the same face at E-1.
 void make_directions(int E, double* dirs, int64_t* father) {
-  int64_t side = 1ll << E;
-  for (int f = 0; f < 6; ++f) {
-    int a = f / 2;
-    double sg = (f % 2 == 0) ? 1.0 : -1.0;
-    int b = (a == 0) ? 1 : 0;
-    int c = (a == 2) ? 1 : 2;
+  std::vector<int64_t> k(1, 0);
+  for (int e = 1; e <= E; ++e) {
+    std::vector<int64_t> split(2 * k.size());
+    for (size_t i = 0; i < k.size(); ++i) {
+      split[2 * i] = 2 * k[i] - 1;
+      split[2 * i + 1] = 2 * k[i] + 1;
+    }
+    k.swap(split);
+  }
+  const int64_t side = (int64_t)k.size();
+  for (int face = 0; face < 6; ++face) {
+    const int axis = face / 2;
+    const int64_t lead = (face % 2 == 0) ? side : -side;
+    const int f0 = axis == 0 ? 1 : 0, f1 = axis == 2 ? 1 : 2;
     for (int64_t i = 0; i < side; ++i)
       for (int64_t j = 0; j < side; ++j) {
-        double p[3];
-        p[a] = sg;
-        p[b] = -1.0 + (double)(2 * i + 1) / (double)side;
-        p[c] = -1.0 + (double)(2 * j + 1) / (double)side;
-        double nr = std::sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
-        int64_t u = (int64_t)f * side * side + i * side + j;
-        for (int d = 0; d < 3; ++d) dirs[3 * u + d] = p[d] / nr;
-        father[u] = (E == 0) ? -1 : (int64_t)f * (side / 2) * (side / 2) + (i >> 1) * (side / 2) + (j >> 1);
+        int64_t n[3];
+        n[axis] = lead;
+        n[f0] = k[i];
+        n[f1] = k[j];
+        const double len = std::sqrt((double)(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]));
+        const int64_t u = (face * side + i) * side + j;
+        for (int d = 0; d < 3; ++d) dirs[3 * u + d] = (double)n[d] / len;
+        father[u] = E == 0 ? -1 : (face * (side / 2) + i / 2) * (side / 2) + j / 2;
       }
   }
 }

@@ -58,7 +58,8 @@ EXPORTS = ["defmm_default_params", "defmm_plan_create", "defmm_plan_inspect_crea
            "defmm_workspace_set_timing", "defmm_workspace_set_overlap", "defmm_workspace_pass_times",
            "defmm_workspace_autotune", "defmm_workspace_get_tuning", "defmm_workspace_set_tuning",
            "defmm_pass_name",
-           "defmm_workspace_pass_work", "defmm_fourier_layout", "defmm_canonical_offset"]
+           "defmm_workspace_pass_work", "defmm_fourier_layout", "defmm_canonical_offset",
+           "defmm_directions"]
 
 _lib = None
 
@@ -101,6 +102,7 @@ def lib():
     L.defmm_workspace_pass_work.argtypes = [P, P, P]
     L.defmm_fourier_layout.argtypes = [i32, P, P, P, P, P]
     L.defmm_canonical_offset.argtypes = [P, P, P]
+    L.defmm_directions.argtypes = [i32, P, P, P]
     for name in EXPORTS:
         if name not in ("defmm_status_string", "defmm_last_error", "defmm_pass_name"):
             getattr(L, name).restype = st
@@ -133,6 +135,17 @@ def canonical_offset(d):
     code = ctypes.c_int32()
     _check(lib().defmm_canonical_offset(_np_ptr(a), _np_ptr(d0), ctypes.byref(code)))
     return d0, code.value
+
+
+def directions(E: int):
+    """The library's direction set at direction level E (host only): unit
+    vectors [6 * 4^E, 3] and father indices (-1 at E = 0)."""
+    n = ctypes.c_int64()
+    _check(lib().defmm_directions(E, ctypes.byref(n), None, None))
+    d = np.zeros((n.value, 3))
+    f = np.zeros(n.value, np.int64)
+    _check(lib().defmm_directions(E, ctypes.byref(n), _np_ptr(d), _np_ptr(f)))
+    return d, f
 
 
 def _np_ptr(a):

@@ -29,6 +29,32 @@ def test_library_exports_every_declared_symbol():
     assert set(defmm.EXPORTS) == declared
 
 
+def test_library_directions_match_the_closed_form():
+    """The library derives its direction set by splitting father patches
+    (Sec. 2.1); the goldens enumerate the closed form of Sec. 4.1.2 (E = 0, 1 as
+    FP64 values, E = 2 as exact integer vectors).  Same vectors bit for bit,
+    same fathers, and at E = 3..6 the same set as the oracle's own derivation."""
+    import os
+    golden = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    rows = np.loadtxt(os.path.join(golden, "directions_E0_E1.txt"))
+    for E in (0, 1):
+        d, f = defmm.directions(E)
+        g = rows[rows[:, 0] == E]
+        np.testing.assert_allclose(d, g[:, 2:5], atol=1e-15)
+        np.testing.assert_array_equal(f, g[:, 5].astype(np.int64))
+    r2 = np.loadtxt(os.path.join(golden, "directions_E2.txt"), dtype=np.int64)
+    d, f = defmm.directions(2)
+    np.testing.assert_array_equal(d, r2[:, 1:4] / np.sqrt(r2[:, 4].astype(np.float64))[:, None])
+    np.testing.assert_array_equal(f, r2[:, 5])
+    for E in range(3, 7):
+        d, f = defmm.directions(E)
+        do, fo = oracle.directions(E)
+        np.testing.assert_array_equal(d, do)
+        np.testing.assert_array_equal(f, fo)
+    with pytest.raises(defmm.DefmmError):
+        defmm.directions(-1)
+
+
 def _sorted_rows(*cols):
     a = np.column_stack([np.asarray(c).astype(np.int64).reshape(len(c), -1) for c in cols])
     return a[np.lexsort(a.T[::-1])] if len(a) else a

@@ -98,6 +98,21 @@ def test_directions_golden_E0_E1():
         np.testing.assert_array_equal(f, g[:, 5].astype(np.int64))
 
 
+def test_directions_golden_E2():
+    """Sec. 4.1.2 at E = 2: every direction is an integer vector (4 on the face
+    axis, odd free coordinates) over its length, with the father patch that
+    contains it.  The golden file is an integer enumeration of the construction,
+    so the FP64 vectors must equal n / sqrt(|n|^2) bit for bit (every quantity
+    before the square root is exact)."""
+    rows = np.loadtxt(os.path.join(GOLDEN, "directions_E2.txt"), dtype=np.int64)
+    d, f = oracle.directions(2)
+    assert d.shape == (96, 3)
+    np.testing.assert_array_equal(rows[:, 0], np.arange(96))
+    expect = rows[:, 1:4].astype(np.float64) / np.sqrt(rows[:, 4].astype(np.float64))[:, None]
+    np.testing.assert_array_equal(d, expect)
+    np.testing.assert_array_equal(f, rows[:, 5])
+
+
 @pytest.mark.parametrize("E", [0, 1, 2, 3, 4])
 def test_direction_tree_nested(E):
     """Sec. 2.1: every direction at level E is the son of exactly one direction at
@@ -256,6 +271,116 @@ def test_traversal_covers_every_pair_exactly_once():
             nvec = np.maximum(np.abs(d) - 1, 0)
             dist = 2 * w * np.linalg.norm(nvec)
             assert max(kappa * w * w, 2 * w) <= prm.eta * dist * (1 + 1e-12)
+
+
+def _mac_holds(kappa, eta, D, level, delta, screened=False):
+    """eq. macdirref written in the paper's form, max{kappa w^2, 2w} <= eta dist,
+    with w the half side and dist the distance between the two cubes; the
+    margin keeps rounding at an exact tie on the admissible side."""
+    w = D / 2 ** (level + 1)
+    nvec = np.maximum(np.abs(np.asarray(delta, dtype=np.float64)) - 1, 0)
+    dist = 2 * w * np.linalg.norm(nvec, axis=-1)
+    k = 0.0 if screened else kappa
+    return np.maximum(k * w * w, 2 * w) <= eta * dist * (1 + 1e-12)
+
+
+def _mac_fails(kappa, eta, D, level, delta, screened=False):
+    w = D / 2 ** (level + 1)
+    nvec = np.maximum(np.abs(np.asarray(delta, dtype=np.float64)) - 1, 0)
+    dist = 2 * w * np.linalg.norm(nvec, axis=-1)
+    k = 0.0 if screened else kappa
+    return np.maximum(k * w * w, 2 * w) > eta * dist * (1 - 1e-12)
+
+
+TRAVERSAL_CASES = [
+    ("sphere", 2500, 0.0, dict(L=3, ncrit=8)),
+    ("sphere", 2500, 60.0, dict(L=4, ncrit=10, hf_threshold=1.0, eta=0.6)),
+    ("ellipsoid", 3000, 120.0, dict(L=4, ncrit=12, eta=0.35, hf_threshold=0.75, dir_refine=1)),
+    ("cube_volume", 2500, 30.0, dict(L=3, ncrit=6, eta=1.5)),
+    ("sphere", 2500, 60.0, dict(L=4, ncrit=10, eta=0.5, kernel=oracle.YUKAWA)),
+]
+
+
+@pytest.mark.parametrize("geom,n,kappa,kw", TRAVERSAL_CASES)
+def test_traversal_p2p_pairs_fail_the_mac_and_hold_a_leaf(geom, n, kappa, kw):
+    """Alg. 1: a pair goes to the near field only when eq. macdirref rejects it
+    and one of the two cells is a leaf; both cells are on the same level."""
+    X = W.GENERATORS[geom](n, 31)
+    prm = oracle.Params(**kw)
+    F = oracle.FMM(X, None, kappa, prm)
+    cells = F.cells(0)
+    D, _ = F.geometry()
+    pp = F.p2p()
+    t, s = pp["t"], pp["s"]
+    assert len(t) > 0
+    lev = cells["level"]
+    assert (lev[t] == lev[s]).all()
+    leaf = cells["is_leaf"].astype(bool)
+    assert (leaf[t] | leaf[s]).all()
+    delta = cells["ijk"][t] - cells["ijk"][s]
+    screened = prm.kernel == oracle.YUKAWA
+    assert _mac_fails(kappa, prm.eta, D, lev[t], delta, screened).all()
+    # and every M2L pair passes it
+    m = F.m2l()
+    assert _mac_holds(kappa, prm.eta, D, m["level"], m["delta"], screened).all()
+
+
+@pytest.mark.parametrize("geom,n,kappa,kw", TRAVERSAL_CASES)
+def test_traversal_descends_only_through_rejected_non_leaf_pairs(geom, n, kappa, kw):
+    """Alg. 1 recurses into the sons of a pair only when the MAC rejects it and
+    neither cell is a leaf: so the father pair of every M2L or P2P pair below
+    the root is such a pair (no interaction is emitted below an admissible or
+    leaf ancestor pair)."""
+    X = W.GENERATORS[geom](n, 32)
+    prm = oracle.Params(**kw)
+    F = oracle.FMM(X, None, kappa, prm)
+    cells = F.cells(0)
+    D, _ = F.geometry()
+    lev, ijk = cells["level"], cells["ijk"]
+    leaf = cells["is_leaf"].astype(bool)
+    index = {(int(l), *map(int, c)): i for i, (l, c) in enumerate(zip(lev, ijk))}
+    parent = np.array([index[(int(l) - 1, *map(int, c >> 1))] if l > 0 else -1
+                       for l, c in zip(lev, ijk)])
+    m, pp = F.m2l(), F.p2p()
+    t = np.concatenate([m["t"], pp["t"]])
+    s = np.concatenate([m["s"], pp["s"]])
+    below = lev[t] > 0
+    assert below.any()
+    pt, ps = parent[t[below]], parent[s[below]]
+    assert (~leaf[pt] & ~leaf[ps]).all()
+    screened = prm.kernel == oracle.YUKAWA
+    assert _mac_fails(kappa, prm.eta, D, lev[pt], ijk[pt] - ijk[ps], screened).all()
+
+
+@pytest.mark.parametrize("geom,n,kappa,kw", [c for c in TRAVERSAL_CASES if c[2] > 0
+                                               and c[3].get("kernel", 0) == oracle.HELMHOLTZ])
+def test_best_direction_is_the_argmax(geom, n, kappa, kw):
+    """Alg. 2: an M2L pair of a high-frequency level carries the direction of
+    level E = l* - l + E0 closest to its offset, argmax <v, delta> (numpy), the
+    first index within 1e-12 |delta| of the maximum; low-frequency pairs carry
+    none, and a level is high-frequency iff kappa w > c_HF."""
+    X = W.GENERATORS[geom](n, 33)
+    prm = oracle.Params(**kw)
+    F = oracle.FMM(X, None, kappa, prm)
+    D, _ = F.geometry()
+    info = F.info()
+    m = F.m2l()
+    hf = kappa * D / 2.0 ** (m["level"] + 1) > prm.hf_threshold
+    assert hf.any()
+    assert (m["dir"][~hf] == -1).all()
+    lstar = max(l for l in range(40) if kappa * D / 2.0 ** (l + 1) > prm.hf_threshold)
+    assert info["lstar"] == lstar
+    for lev in np.unique(m["level"][hf]):
+        sel = hf & (m["level"] == lev)
+        V, _ = oracle.directions(lstar - int(lev) + prm.dir_refine)
+        d = m["delta"][sel].astype(np.float64)
+        dots = d @ V.T
+        mx = dots.max(axis=1)
+        tol = 1e-12 * np.linalg.norm(d, axis=1)
+        u = m["dir"][sel]
+        assert (dots[np.arange(len(u)), u] >= mx - 1.01 * tol).all()
+        earlier = np.arange(V.shape[0])[None, :] < u[:, None]
+        assert not (earlier & (dots >= (mx - 0.99 * tol)[:, None])).any()
 
 
 def test_tree_is_ncrit_morton():
