@@ -2,10 +2,12 @@
 """Benchmark: Mpoints/s per defmm matvec on one MI355X.
 
 Workload (default): 1,048,576 points uniform on the unit sphere (D = 2),
-kappa*D = 256, L = 5, leaves <= 64 points, complex N(0,1) charges; the
-complex64 path is timed (value), the complex128 path is timed beside it.
-A step is one matvec (P2M .. P2P, L2P, scatter) with fresh charges already
-resident in HBM.  Prints one JSON line.
+kappa*D = 256, L = 5, leaves <= 64 points, complex N(0,1) charges, at the
+cheapest knob setting (eta, c_HF, E0) measured within 1e-4 of the FP64 direct
+sum; the complex64 path is timed (value), the complex128 path beside it, and
+the paper-literal setting (eta = 1, c_HF = 2, E0 = 0) after them.  A step is
+one matvec (P2M .. P2P, L2P, scatter) with fresh charges already resident in
+HBM.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -44,8 +46,10 @@ def parse():
     ap.add_argument("--check-targets", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accurate", action="store_true",
-                    help="skip the second complex64 run at the knob setting that reaches 1e-4 against the direct sum")
+                    help="skip the second complex64 run at the paper-literal knobs")
     ap.add_argument("--cpu-sample", type=int, default=0, help="points in the oracle's sample (0: auto)")
+    ap.add_argument("--cpu-single", type=int, default=4096,
+                    help="points in the oracle's one-thread sample (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after timing, run one plain device copy of this size (HBM counter calibration)")
     ap.add_argument("--c64-only", action="store_true", help="skip the complex128 path and the checks")
@@ -58,13 +62,14 @@ def parse():
     return ap.parse_args()
 
 
-# Knobs per workload: (eta, hf_threshold, dir_refine).
-# Knobs (eta, hf_threshold, dir_refine) at which the method error against the
-# FP64 direct sum is below 1e-4 on that workload (found by a sweep on the device).
-ACCURATE = {"sphere1m": (0.3, 0.75, 1), "ellipsoid2m": (0.3, 0.75, 1)}
-
-KNOBS = {"sphere8k": (1.0, 2.0, 0), "sphere1m": (1.0, 2.0, 0), "ellipsoid2m": (1.0, 2.0, 0),
-         "cube8m": (1.0, 2.0, 0), "sphere1m_yukawa": (1.0, 2.0, 0)}
+# Knob settings (eta = MAC constant, hf_threshold = c_HF, dir_refine = E0).
+PAPER_LITERAL = (1.0, 2.0, 0)
+# Per workload, the cheapest setting found by a sweep on the device whose
+# complex64 potentials are within 1e-4 of the FP64 direct sum: the headline is
+# timed there.  None: no setting that fits one GPU reaches it, and the
+# paper-literal setting is timed instead (the error is reported either way).
+ACCURATE = {"sphere1m": (0.3, 0.75, 1), "ellipsoid2m": (0.3, 0.75, 1), "sphere1m_yukawa": (1.0, 2.0, 0),
+            "sphere8k": None, "cube8m": None}
 
 
 def direct_sum_sampled(X, q, kappa, tau, targets, screened=False):
@@ -102,15 +107,20 @@ def kernel_source_hash(kernel):
     return hashlib.sha256(sec.encode()).hexdigest()[:16]
 
 
-def load_traffic(kernel, workload):
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as fh:
-        t = json.load(fh)
-    if t.get("kernel_source_sha256_16") != kernel_source_hash(kernel):
-        return None
-    return t.get("bytes_per_launch")
+def load_traffic(kernel, workload, knobs):
+    """HBM bytes per launch of `kernel` on `workload` at `knobs` from the committed
+    counter summary, or None when there is none or the kernel's source section
+    has changed since the counters were taken."""
+    import glob
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}*.json"))):
+        with open(path) as fh:
+            t = json.load(fh)
+        if t.get("workload") != workload or [float(v) for v in t.get("knobs", [])] != [float(v) for v in knobs]:
+            continue
+        if t.get("kernel_source_sha256_16") != kernel_source_hash(kernel):
+            return None
+        return t.get("bytes_per_launch")
+    return None
 
 
 def time_matvecs(ws, charges, steps, warmup, timing):
@@ -138,25 +148,61 @@ def time_matvecs(ws, charges, steps, warmup, timing):
     return (t1 - t0) * 1e3 / steps, lat, passes
 
 
-def cpu_baseline(wl, X, kappa, knobs, perm, n_sample):
-    """The FP64 oracle on a bounded sample: the first n_sample points in Morton order
-    (a contiguous patch of the same surface at the same density), same kappa/L/ncrit."""
+def _omp():
+    import ctypes
+    try:
+        return ctypes.CDLL("libgomp.so.1")
+    except OSError:
+        return None
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, X, kappa, knobs, perm, n_sample, n_single):
+    """The FP64 oracle on bounded samples of the same workload: the first n_sample
+    points in Morton order (a contiguous patch of the same surface at full
+    density), same kappa/L/ncrit/knobs, on every host thread; then the first
+    n_single points on one thread (a per-core figure).  The whole input at these
+    knobs would take the oracle tens of minutes per matvec."""
     import oracle
-    idx = np.sort(perm[:n_sample])
-    Xs = X[idx]
-    q = wl.charges(0)[idx]
     eta, hf, e0 = knobs
     kern = oracle.YUKAWA if wl.kernel == "yukawa" else oracle.HELMHOLTZ
-    F = oracle.FMM(Xs, None, kappa, oracle.Params(L=wl.L, ncrit=wl.ncrit, eta=eta, hf_threshold=hf,
-                                                  dir_refine=e0, kernel=kern))
-    F.apply(q)
-    secs = F.last_seconds
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": round(n_sample / secs / 1e6, 6), "unit": "Mpoints/s", "cores": cores, "kind": "oracle",
+    q_all = wl.charges(0)
+
+    def run(n):
+        idx = np.sort(perm[:n])
+        F = oracle.FMM(X[idx], None, kappa, oracle.Params(L=wl.L, ncrit=wl.ncrit, eta=eta, hf_threshold=hf,
+                                                          dir_refine=e0, kernel=kern))
+        F.apply(q_all[idx])
+        return F.last_seconds
+
+    omp = _omp()
+    threads = int(omp.omp_get_max_threads()) if omp else int(os.environ.get("OMP_NUM_THREADS", os.cpu_count()))
+    secs = run(n_sample)
+    single = None
+    if omp and n_single:
+        omp.omp_set_num_threads(1)
+        try:
+            s1 = run(n_single)
+        finally:
+            omp.omp_set_num_threads(threads)
+        single = {"value": round(n_single / s1 / 1e6, 6), "unit": "Mpoints/s", "cores": 1,
+                  "sample": f"first {n_single} points in Morton order, one FP64 matvec took {s1:.2f} s"}
+    return {"value": round(n_sample / secs / 1e6, 6), "unit": "Mpoints/s", "cores": threads, "kind": "oracle",
+            "cpu": _cpu_model(),
             "sample": f"first {n_sample} of {wl.n} points in Morton order (a patch of the {wl.geometry} at "
-                      f"full density), {wl.kernel} kernel, kappa*D={wl.kappa_d}, L={wl.L}, ncrit={wl.ncrit}; "
-                      f"one FP64 matvec "
-                      f"(setup excluded) took {secs:.2f} s"}
+                      f"full density), {wl.kernel} kernel, kappa*D={wl.kappa_d}, L={wl.L}, ncrit={wl.ncrit}, "
+                      f"eta={eta}, c_HF={hf}, E0={e0}; one FP64 matvec (setup excluded) took {secs:.2f} s",
+            "single_thread": single}
 
 
 def run_serving(args):
@@ -223,92 +269,12 @@ def run_serving(args):
     print(json.dumps(line), flush=True)
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the sharding by target "
-              f"across GPUs is designed but not built", file=sys.stderr)
-        sys.exit(2)
-    if args.serving:
-        run_serving(args)
-        return
-    import torch
-    from paper_2202_04894_amd import defmm
-    from paper_2202_04894_amd import workloads as W
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    wl = W.WORKLOADS[args.workload]
-    eta, hf, e0 = KNOBS[args.workload]
-    if args.eta is not None:
-        eta = args.eta
-    if args.hf is not None:
-        hf = args.hf
-    if args.e0 is not None:
-        e0 = args.e0
-    X = wl.points()
-    kflag = defmm.YUKAWA if wl.kernel == "yukawa" else 0
-    nsteps = max(args.steps, 1)
-    nq = min(nsteps + args.warmup, 64)
-
-    def make(prec):
-        t0 = time.perf_counter()
-        plan = defmm.Plan(X, None, wl.kappa, defmm.Params(order_L=wl.L, ncrit=wl.ncrit, eta=eta,
-                                                            hf_threshold=hf, dir_refine=e0, precision=prec,
-                                                            m2l_mode=defmm.M2L_AUTO, flags=kflag))
-        torch.cuda.synchronize()
-        setup = time.perf_counter() - t0
-        return plan, defmm.Workspace(plan), setup
-
-    plan64, ws64, setup64 = make(defmm.C64)
-    charges64 = [torch.as_tensor(wl.charges(k, np.complex64), device="cuda") for k in range(nq)]
-    # execution choices (M2L variant, near-field overlap) tuned on this workspace
-    tuned = ws64.autotune(charges64[0], reps=3)
-    # production mode: tuned choices, no per-pass events
-    ms64, lat64, _ = time_matvecs(ws64, charges64, nsteps, args.warmup, timing=False)
-    # the same matvecs in sequence with per-pass HIP events: each kernel's own duration
-    ws64.set_overlap(False)
-    ms_seq, _, passes = time_matvecs(ws64, charges64, nsteps, 1, timing=True)
-    ws64.set_tuning(**tuned)
-    p64 = ws64.matvec(charges64[0]).cpu().numpy().astype(np.complex128)
-    del charges64
-
-    if args.copy_probe_mib:
-        n = args.copy_probe_mib * (1 << 20) // 4
-        a = torch.ones(n, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        torch.cuda.synchronize()
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
-    if args.c64_only:
-        print(json.dumps({"value": round(wl.n / (ms64 / 1e3) / 1e6, 3), "ms_per_step": round(ms64, 4),
-                          "sequential_ms_per_step": round(ms_seq, 4), "tuning": tuned,
-                          "passes_ms_per_step": {defmm.pass_name(i): round(float(v) / nsteps, 4)
-                                                 for i, v in enumerate(passes[0])}}), flush=True)
-        return
-
-    plan128, ws128, setup128 = make(defmm.C128)
-    charges128 = [torch.as_tensor(wl.charges(k), device="cuda") for k in range(min(nq, 8))]
-    ws128.autotune(charges128[0], reps=2)
-    ms128, lat128, _ = time_matvecs(ws128, charges128, max(args.c128_steps, 1), 2, timing=False)
-    p128 = ws128.matvec(charges128[0]).cpu().numpy()
-    del charges128
-    rel_prec = float(np.linalg.norm(p64 - p128) / np.linalg.norm(p128))
-
-    D, _ = plan64.geometry()
-    tg = W.sample_targets(wl.n, args.check_targets, 3000 + wl.seed)
-    pd = direct_sum_sampled(X, wl.charges(0), wl.kappa, 1e-12 * D, tg, screened=bool(kflag))
-    rel_direct = float(np.linalg.norm(p128[tg] - pd) / np.linalg.norm(pd))
-    rel_direct64 = float(np.linalg.norm(p64[tg] - pd) / np.linalg.norm(pd))
-
-    # roofline of the dominant kernel, from per-pass HIP events over the timed region
-    st = plan64.stats()
-    ms_pass, calls = passes
-    names = [defmm.pass_name(i) for i in range(defmm.NUM_PASSES)]
-    bytes_, flops = ws64.pass_work()
-    per_step = ms_pass / nsteps
+def roofline_of(names, per_step, bytes_, flops, tuned, wl_name, knobs):
+    """Roofline of the pass that takes the most time, from per-pass HIP events
+    (average launch duration over the timed matvecs)."""
     dom = int(np.argmax(per_step))
     dname = names[dom]
-    t_launch = per_step[dom] / 1e3  # s per matvec for this pass
+    t_launch = per_step[dom] / 1e3
     kern = KERNEL_OF_PASS.get(dname, dname)
     if dname == "m2l" and tuned["m2l_variant"] == 1:
         kern = "k_m2l_slice"
@@ -327,20 +293,116 @@ def main():
     roof["kernel"] = kern
     roof["avg_launch_ms"] = round(t_launch * 1e3, 4)
     roof["timing"] = "per-pass HIP events, passes in sequence on one stream (near field not overlapped)"
-    roof["traffic"] = load_traffic(kern, wl.name)
+    roof["traffic"] = load_traffic(kern, wl_name, knobs)
+    roof["algorithmic_bytes_per_launch"] = float(bytes_[dom])
+    roof["flops_per_launch"] = float(flops[dom])
     t_floor = max(bytes_[dom] / (HBM_PEAK_GBS * 1e9), flops[dom] / (FP32_PEAK_TFLOPS * 1e12))
     roof["t_floor_ms"] = round(t_floor * 1e3, 4)
     roof["t_over_t_floor"] = round(t_launch / t_floor, 2) if t_floor > 0 else None
     if dname == "m2l":
         # what the caches serve: both operands of every pair, s_c (2L-1)^3 bytes each
-        cs = 8
-        roof["effective_GBps"] = round(flops[dom] * cs / 4 / t_launch / 1e9, 1)
+        roof["effective_GBps"] = round(flops[dom] * 8 / 4 / t_launch / 1e9, 1)
+    return roof
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the sharding by target "
+              f"across GPUs is designed but not built", file=sys.stderr)
+        sys.exit(2)
+    if args.serving:
+        run_serving(args)
+        return
+    import torch
+    from paper_2202_04894_amd import defmm
+    from paper_2202_04894_amd import workloads as W
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    wl = W.WORKLOADS[args.workload]
+    accurate = ACCURATE.get(args.workload)
+    eta, hf, e0 = accurate if accurate else PAPER_LITERAL
+    if args.eta is not None:
+        eta = args.eta
+    if args.hf is not None:
+        hf = args.hf
+    if args.e0 is not None:
+        e0 = args.e0
+    knobs = (eta, hf, e0)
+    X = wl.points()
+    kflag = defmm.YUKAWA if wl.kernel == "yukawa" else 0
+    nsteps = max(args.steps, 1)
+    nq = min(nsteps + args.warmup, 64)
+
+    def make(prec, kn):
+        t0 = time.perf_counter()
+        plan = defmm.Plan(X, None, wl.kappa, defmm.Params(order_L=wl.L, ncrit=wl.ncrit, eta=kn[0],
+                                                            hf_threshold=kn[1], dir_refine=kn[2], precision=prec,
+                                                            m2l_mode=defmm.M2L_AUTO, flags=kflag))
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        return plan, defmm.Workspace(plan), setup
+
+    plan64, ws64, setup64 = make(defmm.C64, knobs)
+    charges64 = [torch.as_tensor(wl.charges(k, np.complex64), device="cuda") for k in range(nq)]
+    # execution choices (M2L variant, dense levels, near-field overlap) tuned on this workspace
+    tuned = ws64.autotune(charges64[0], reps=3)
+    # production mode: tuned choices, no per-pass events
+    ms64, lat64, _ = time_matvecs(ws64, charges64, nsteps, args.warmup, timing=False)
+    # the same matvecs in sequence with per-pass HIP events: each kernel's own duration
+    ws64.set_overlap(False)
+    ms_seq, _, passes = time_matvecs(ws64, charges64, nsteps, 1, timing=True)
+    ws64.set_tuning(**tuned)
+    p64 = ws64.matvec(charges64[0]).cpu().numpy().astype(np.complex128)
+    del charges64
+    names = [defmm.pass_name(i) for i in range(defmm.NUM_PASSES)]
+    ms_pass, _ = passes
+    per_step = ms_pass / nsteps
+
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    if args.c64_only:
+        print(json.dumps({"value": round(wl.n / (ms64 / 1e3) / 1e6, 3), "ms_per_step": round(ms64, 4),
+                          "knobs": knobs, "sequential_ms_per_step": round(ms_seq, 4), "tuning": tuned,
+                          "passes_ms_per_step": {n: round(float(v), 4) for n, v in zip(names, per_step)}}),
+              flush=True)
+        return
+
+    st = plan64.stats()
+    bytes_, flops = ws64.pass_work()
+    roof = roofline_of(names, per_step, bytes_, flops, tuned, wl.name, knobs)
     p2p_i = names.index("p2p")
     t_p2p = per_step[p2p_i] / 1e3
     p2p = {"kernel": "k_p2p", "point_pairs": int(st["p2p_point_pairs"]), "ms": round(t_p2p * 1e3, 4),
            "Gpairs_per_s": round(st["p2p_point_pairs"] / t_p2p / 1e9, 2),
            "TFLOPs_nominal": round(flops[p2p_i] / t_p2p / 1e12, 3),
            "frac_fp32_vector_peak": round(flops[p2p_i] / t_p2p / 1e12 / FP32_PEAK_TFLOPS, 4)}
+    perm = plan64.tree(0)["perm"]
+    D, _ = plan64.geometry()
+    del plan64, ws64
+    torch.cuda.empty_cache()
+
+    # the plain FP64 (complex128) GPU path at the same knobs
+    plan128, ws128, setup128 = make(defmm.C128, knobs)
+    charges128 = [torch.as_tensor(wl.charges(k), device="cuda") for k in range(min(nq, 8))]
+    ws128.autotune(charges128[0], reps=2)
+    ms128, lat128, _ = time_matvecs(ws128, charges128, max(args.c128_steps, 1), 2, timing=False)
+    p128 = ws128.matvec(charges128[0]).cpu().numpy()
+    del charges128, plan128, ws128
+    torch.cuda.empty_cache()
+    rel_prec = float(np.linalg.norm(p64 - p128) / np.linalg.norm(p128))
+
+    tg = W.sample_targets(wl.n, args.check_targets, 3000 + wl.seed)
+    pd = direct_sum_sampled(X, wl.charges(0), wl.kappa, 1e-12 * D, tg, screened=bool(kflag))
+    rel_direct = float(np.linalg.norm(p128[tg] - pd) / np.linalg.norm(pd))
+    rel_direct64 = float(np.linalg.norm(p64[tg] - pd) / np.linalg.norm(pd))
+    setting = ("cheapest setting measured within 1e-4 of the FP64 direct sum" if accurate and knobs == accurate
+               else "paper-literal setting" if knobs == PAPER_LITERAL else "setting given on the command line")
 
     out = {
         "metric": METRIC,
@@ -358,7 +420,7 @@ def main():
         "config": {"workload": f"{wl.name}: {wl.n} points uniform on the unit {wl.geometry}, "
                                + (f"screened kernel exp(-kappa r)/(4 pi r), " if kflag else "")
                                + f"kappa*D={wl.kappa_d}, L={wl.L}, leaf<={wl.ncrit}, complex N(0,1) charges",
-                   "eta": eta, "hf_threshold": hf, "dir_refine": e0},
+                   "eta": eta, "hf_threshold": hf, "dir_refine": e0, "setting": setting},
         "p50_ms": round(float(np.percentile(lat64, 50)), 4),
         "p99_ms": round(float(np.percentile(lat64, 99)), 4),
         "rel_l2_c64_vs_c128": rel_prec,
@@ -373,43 +435,38 @@ def main():
         "tuning": tuned,
         "passes_ms_per_step": {n: round(float(v), 4) for n, v in zip(names, per_step)},
         # per pass: compulsory bytes / time against the HBM peak, flops / time
-        "passes_roofline": {n: {"GBps": round(b / (t / 1e3) / 1e9, 1), "frac_hbm": round(b / (t / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        "passes_roofline": {n: {"GBps": round(b / (t / 1e3) / 1e9, 1),
+                                "frac_hbm": round(b / (t / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
                                 "TFLOPs": round(f / (t / 1e3) / 1e12, 3)}
                             for n, t, b, f in zip(names, per_step, bytes_, flops) if t > 0.005},
         "stats": st,
         "roofline": roof,
         "p2p": p2p,
     }
+
+    if not args.no_accurate and knobs != PAPER_LITERAL:
+        # the same workload at the paper-literal knobs, complex64: throughput and error
+        pl, wsl, setup_l = make(defmm.C64, PAPER_LITERAL)
+        ql = [torch.as_tensor(wl.charges(k, np.complex64), device="cuda") for k in range(nq)]
+        tuned_l = wsl.autotune(ql[0], reps=2)
+        ms_l, lat_l, _ = time_matvecs(wsl, ql, nsteps, args.warmup, timing=False)
+        p_l = wsl.matvec(ql[0]).cpu().numpy().astype(np.complex128)
+        stl = pl.stats()
+        out["paper_literal"] = {
+            "eta": PAPER_LITERAL[0], "hf_threshold": PAPER_LITERAL[1], "dir_refine": PAPER_LITERAL[2],
+            "value": round(wl.n / (ms_l / 1e3) / 1e6, 3), "unit": "Mpoints/s", "ms_per_step": round(ms_l, 4),
+            "p50_ms": round(float(np.percentile(lat_l, 50)), 4), "p99_ms": round(float(np.percentile(lat_l, 99)), 4),
+            "rel_l2_vs_direct_c64": float(np.linalg.norm(p_l[tg] - pd) / np.linalg.norm(pd)),
+            "setup_s": round(setup_l, 3), "m2l_pairs": stl["m2l_pairs"], "eff_expansions": stl["eff_expansions"],
+            "tuning": tuned_l}
+        del pl, wsl, ql
+        torch.cuda.empty_cache()
+
     if not args.no_cpu_baseline:
-        n_s = args.cpu_sample or min(wl.n, 131072)
-        out["cpu_baseline"] = cpu_baseline(wl, X, wl.kappa, (eta, hf, e0), plan64.tree(0)["perm"], n_s)
+        out["cpu_baseline"] = cpu_baseline(wl, X, wl.kappa, knobs, perm, args.cpu_sample or min(wl.n, 16384),
+                                           args.cpu_single or 0)
     else:
         out["cpu_baseline"] = None
-    if not args.no_accurate and wl.name in ACCURATE:
-        # the same workload at the accurate knob setting: error and throughput
-        del plan64, ws64, plan128, ws128
-        torch.cuda.empty_cache()
-        ea, ha, e0a = ACCURATE[wl.name]
-        t0 = time.perf_counter()
-        pa = defmm.Plan(X, None, wl.kappa, defmm.Params(order_L=wl.L, ncrit=wl.ncrit, eta=ea, hf_threshold=ha,
-                                                        dir_refine=e0a, precision=defmm.C64, m2l_mode=defmm.M2L_FFT))
-        torch.cuda.synchronize()
-        setup_a = time.perf_counter() - t0
-        wa = defmm.Workspace(pa)
-        qa = [torch.as_tensor(wl.charges(k, np.complex64), device="cuda") for k in range(4)]
-        tuned_a = wa.autotune(qa[0], reps=2)
-        ms_a, lat_a, _ = time_matvecs(wa, qa, 5, 1, timing=False)
-        p_a = wa.matvec(qa[0]).cpu().numpy().astype(np.complex128)
-        sta = pa.stats()
-        out["accurate_setting"] = {
-            "eta": ea, "hf_threshold": ha, "dir_refine": e0a,
-            "value": round(wl.n / (ms_a / 1e3) / 1e6, 3), "unit": "Mpoints/s", "ms_per_step": round(ms_a, 3),
-            "p50_ms": round(float(np.percentile(lat_a, 50)), 3),
-            "rel_l2_vs_direct_c64": float(np.linalg.norm(p_a[tg] - pd) / np.linalg.norm(pd)),
-            "setup_s": round(setup_a, 2), "m2l_pairs": sta["m2l_pairs"], "eff_expansions": sta["eff_expansions"],
-            "tuning": tuned_a}
-        del pa, wa, qa
-        torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
 

@@ -90,6 +90,8 @@ DevPlan::~DevPlan() {
   for (void* p : allocs) hipFree(p);
 }
 void Workspace::drop_graph() {
+  if (graph_launched && graph_done) (void)hipEventSynchronize(graph_done);
+  graph_launched = false;
   if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
   if (graph) (void)hipGraphDestroy(graph);
   graph_exec = nullptr;
@@ -103,6 +105,7 @@ Workspace::~Workspace() {
   for (hipEvent_t e : ev_pool) hipEventDestroy(e);
   if (ev_fork) hipEventDestroy(ev_fork);
   if (ev_join) hipEventDestroy(ev_join);
+  if (graph_done) hipEventDestroy(graph_done);
   if (side) hipStreamDestroy(side);
 }
 }  // namespace defmm
@@ -314,10 +317,6 @@ defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int
         check(hipStreamSynchronize(s), "dense K");
       }
     }
-    if (const char* e = std::getenv("DEFMM_M2L_VARIANT")) {
-      int v = std::atoi(e);
-      if (v >= 0 && v <= 2) P.m2l_variant = v;
-    }
     {
       int dev = 0;
       hipDeviceProp_t prop;
@@ -325,10 +324,6 @@ defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int
           prop.multiProcessorCount > 0)
         P.num_cu = prop.multiProcessorCount;
       P.p2p_waves_per_cu = 2;
-      if (const char* e = std::getenv("DEFMM_P2P_WAVES_PER_CU")) {
-        int v = std::atoi(e);
-        if (v >= 1 && v <= 32) P.p2p_waves_per_cu = v;
-      }
     }
 
     P.n_m2l = (int64_t)H.m2l_src.size();
@@ -536,6 +531,20 @@ defmm_status defmm_matvec_graph(defmm_plan* plan, defmm_workspace* ws, const voi
   }
   hipError_t e = hipGraphLaunch(W.graph_exec, s);
   if (e != hipSuccess) return fail(DEFMM_ERR_DEVICE, std::string("graph launch: ") + hipGetErrorString(e));
+  if (!W.graph_done) {
+    e = hipEventCreateWithFlags(&W.graph_done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      W.graph_done = nullptr;
+      (void)hipStreamSynchronize(s);  // no event to wait on later: wait now
+      return fail(DEFMM_ERR_DEVICE, std::string("graph event: ") + hipGetErrorString(e));
+    }
+  }
+  e = hipEventRecord(W.graph_done, s);
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(s);
+    return fail(DEFMM_ERR_DEVICE, std::string("graph event record: ") + hipGetErrorString(e));
+  }
+  W.graph_launched = true;
   return DEFMM_OK;
 }
 

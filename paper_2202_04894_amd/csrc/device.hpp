@@ -136,6 +136,10 @@ struct Workspace {
   const void* graph_q = nullptr;
   void* graph_p = nullptr;
   bool graph_stale = true;
+  // recorded after every replay; waited on before the executable is destroyed,
+  // so a recapture or the workspace's end never frees a graph still running
+  hipEvent_t graph_done = nullptr;
+  bool graph_launched = false;
   void drop_graph();
   ~Workspace();
 };

@@ -5,6 +5,9 @@ can compute one by one from the inputs:
   * the traversal lists of the plan (integer-exact, whole problem);
   * sampled multipole expansions: P2M of a leaf from its points and charges,
     and M2M of a father whose sons are leaves (sons recomputed by the oracle);
+  * the downward pass, sampled: local expansions rebuilt by the oracle's M2L
+    and L2L from the library's exported multipoles and father locals, leaf
+    potentials rebuilt by the oracle's L2P and the direct near field;
   * sampled potentials against the direct sum (bounded by the method error of
     the settings, reported in the design notes, not a parity bound);
 and properties that hold at any size: complex64 vs complex128 within the
@@ -16,6 +19,7 @@ import numpy as np
 import pytest
 
 import oracle
+from downward_check import downward_check
 from paper_2202_04894_amd import workloads as W
 
 torch = pytest.importorskip("torch")
@@ -121,6 +125,18 @@ class Run:
                 break
         assert checked > 0
 
+    def check_sampled_downward(self, prec, n_local=48, n_leaf=16, tol=1e-11, seed=6):
+        """The downward pass element by element at full size (`downward_check`)."""
+        plan, ws = self.plans[prec], self.ws[prec]
+        D, org = plan.geometry()
+        exM, exL = ws.expansions(1, 0), ws.expansions(0, 1)
+        n_loc, n_lf = downward_check(
+            kappa=self.wl.kappa, L=self.wl.L, kernel=self.okernel, hf_threshold=2.0, dir_refine=0,
+            D=D, origin=org, tree=plan.tree(0), m2l=plan.m2l(), p2p=plan.p2p(),
+            mult=(exM["cell"], exM["dir"], exM["values"]), loc=(exL["cell"], exL["dir"], exL["values"]),
+            X=self.X, q=self.q, p=self.p[prec], n_local=n_local, n_leaf=n_leaf, tol=tol, seed=seed)
+        assert n_loc > 0 and n_lf > 0
+
     def direct(self, n_t, seed):
         D, _ = next(iter(self.plans.values())).geometry()
         tg = W.sample_targets(self.wl.n, n_t, seed)
@@ -165,6 +181,15 @@ def test_sphere1m_sampled_multipoles(sphere1m):
     r.check_sampled_multipoles(r.defmm.C64, n_leaf=16, n_father=8, tol=2e-5)
 
 
+def test_sphere1m_sampled_downward_pass(sphere1m):
+    """M2F, M2L, F2L, L2L, L2P and P2P at 1,048,576 points, sampled element by
+    element against the oracle's operators applied to the library's own inputs:
+    complex128 to rounding, complex64 within 2e-5 of each result's largest value."""
+    r = sphere1m
+    r.check_sampled_downward(r.defmm.C128, tol=1e-11)
+    r.check_sampled_downward(r.defmm.C64, n_local=24, n_leaf=8, tol=2e-5)
+
+
 def test_sphere1m_sampled_direct_sum(sphere1m):
     """Method error of the paper-literal settings (eta=1, HF iff kappa*w>2, E0=0)
     against the FP64 direct sum on sampled targets; measured 4.5e-2."""
@@ -183,6 +208,7 @@ def test_large_workloads(name):
     from paper_2202_04894_amd import defmm
     r = Run(name, [defmm.C64])
     r.check_sampled_multipoles(defmm.C64, n_leaf=16, n_father=6, tol=2e-5)
+    r.check_sampled_downward(defmm.C64, n_local=12, n_leaf=6, tol=2e-5)
     tg, pd = r.direct(128, 3000 + r.wl.seed)
     e = rel(r.p[defmm.C64][tg], pd)
     print(f"{name}: rel l2 vs direct sum on {len(tg)} targets = {e:.3e}")

@@ -25,6 +25,15 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def assert_close(p, ref, tol, what=""):
+    """Parity to `tol` in two norms: relative l2 over all elements, and every
+    element within tol of the largest reference magnitude (so an error confined
+    to a few targets or nodes cannot hide in the l2 sum)."""
+    e2 = rel(p, ref)
+    emax = float(np.abs(p - ref).max() / np.abs(ref).max())
+    assert e2 < tol and emax <= tol, (what, e2, emax)
+
+
 def _oracle_params(kw):
     return oracle.Params(L=kw["order_L"], ncrit=kw["ncrit"], eta=kw.get("eta", 1.0),
                          hf_threshold=kw.get("hf_threshold", 2.0), kernel=oracle.YUKAWA)
@@ -51,7 +60,7 @@ def test_screened_root_leaf_equals_direct_sum():
             p, _ = _matvec(plan, q)
             D, _ = plan.geometry()
             ref = oracle.direct_sum(X, X, q, mu, 1e-12 * D, kernel=oracle.YUKAWA)
-            assert rel(p, ref) < tol, (prec, mu, rel(p, ref))
+            assert_close(p, ref, tol, (prec, mu, rel(p, ref)))
 
 
 CASES = [
@@ -77,7 +86,7 @@ def test_screened_matches_oracle(geom, n, mu, kw):
     st = plan.stats()
     assert st["hf_levels"] == 0 and st["m2l_pairs"] > 0
     p, ws = _matvec(plan, q)
-    assert rel(p, ref) < 1e-11, rel(p, ref)
+    assert_close(p, ref, 1e-11, rel(p, ref))
     ex_o = F.expansions(0)
     for kind, key in ((0, "M"), (1, "L")):
         ex = ws.expansions(0, kind)
@@ -88,12 +97,12 @@ def test_screened_matches_oracle(geom, n, mu, kw):
         plan = defmm.Plan(X, None, mu, defmm.Params(precision=defmm.C64, flags=flags, **kw))
         for variant in (0, 1, 2):
             p, _ = _matvec(plan, q, overlap=0, p2p_waves_per_cu=2, m2l_variant=variant, dense_levels=0)
-            assert rel(p, ref) < 2e-5, (flags, variant, rel(p, ref))
+            assert_close(p, ref, 2e-5, (flags, variant, rel(p, ref)))
     for prec, tol in ((defmm.C128, 1e-11), (defmm.C64, 2e-5)):
         plan = defmm.Plan(X, None, mu, defmm.Params(precision=prec, flags=defmm.YUKAWA,
                                                     m2l_mode=defmm.M2L_DENSE, **kw))
         p, _ = _matvec(plan, q)
-        assert rel(p, ref) < tol, ("dense", prec, rel(p, ref))
+        assert_close(p, ref, tol, ("dense", prec, rel(p, ref)))
 
 
 def test_screened_distinct_sets_and_direct_sum():
@@ -109,7 +118,7 @@ def test_screened_distinct_sets_and_direct_sum():
     plan = defmm.Plan(X, Y, mu, defmm.Params(precision=defmm.C64, flags=defmm.YUKAWA, **kw))
     ws = defmm.Workspace(plan)
     p = ws.matvec(torch.as_tensor(qY, device="cuda").to(torch.complex64)).cpu().numpy().astype(np.complex128)
-    assert rel(p, ref) < 2e-5
+    assert_close(p, ref, 2e-5)
     D, _ = plan.geometry()
     direct = oracle.direct_sum(X, Y, qY, mu, 1e-12 * D, kernel=oracle.YUKAWA)
     assert rel(p, direct) < 1e-4, rel(p, direct)

@@ -145,3 +145,11 @@ def test_workspaces_are_pooled_per_plan():
     assert all(o.ok for o in out)
     # plan a + one workspace kept and reused, then plan b + its workspace
     assert sch.stats["peak_bytes"] == 2 * (10 + 20) * 1000
+
+
+def test_graph_replay_in_the_executor_is_closed():
+    """Graph replay inside the serving executor stays disabled until the cause
+    of the host fault seen with it is known: asking for it raises at once."""
+    from paper_2202_04894_amd import serving as S
+    with pytest.raises(NotImplementedError):
+        S.DeviceExecutor(graphs=True)
