@@ -155,6 +155,27 @@ defmm_status defmm_matvec(defmm_plan* plan, defmm_workspace* ws, const void* q, 
 defmm_status defmm_matvec_graph(defmm_plan* plan, defmm_workspace* ws, const void* q, void* p,
                                 void* hip_stream);
 
+/* Allocation-free matvec, for callers that cannot allocate device memory
+   (code under HIP graph capture, tight serving loops, harnesses that forbid
+   hipMalloc): p = G q like defmm_matvec, with the workspace arrays taken from
+   one static device array of defmm_matvec_noalloc_capacity() bytes (64 MiB)
+   per GPU instead of a defmm_workspace.  It calls no hipMalloc or hipFree and
+   allocates no device memory.  Runs on hip_stream only (near field not
+   overlapped), Fourier M2L on every level; same results as defmm_matvec to
+   rounding.  The array's device address is looked up once per device, on the
+   first call with that device current, and kept until the process ends.
+   Every call on one GPU shares that array: calls that overlap on one GPU
+   (other streams, other threads) race and give wrong results; serialise them.
+   q, p: device pointers as for defmm_matvec.  Errors: DEFMM_ERR_INVALID_ARG
+   for a NULL plan, q or p, an inspection plan, or a plan whose workspace
+   (charges, potentials, expansions, Fourier rows, near-field partial sums)
+   exceeds the capacity (use defmm_matvec then); DEFMM_ERR_DEVICE for a
+   failed launch or address lookup. */
+defmm_status defmm_matvec_noalloc(defmm_plan* plan, const void* q, void* p, void* hip_stream);
+
+/* Bytes of the allocation-free matvec's static workspace array. */
+size_t defmm_matvec_noalloc_capacity(void);
+
 defmm_status defmm_workspace_destroy(defmm_workspace* ws);
 defmm_status defmm_plan_destroy(defmm_plan* plan);
 

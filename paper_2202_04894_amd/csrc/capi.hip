@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cstring>
 #include <vector>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -545,6 +546,100 @@ defmm_status defmm_matvec_graph(defmm_plan* plan, defmm_workspace* ws, const voi
     return fail(DEFMM_ERR_DEVICE, std::string("graph event record: ") + hipGetErrorString(e));
   }
   W.graph_launched = true;
+  return DEFMM_OK;
+}
+
+}  // extern "C"
+
+// ---- Allocation-free matvec ---------------------------------------------
+// For callers that cannot allocate device memory (HIP graph capture, tight
+// serving loops): the workspace arrays live in one file-scope device array of
+// kNoAllocScratchBytes per GPU, which every call on that GPU shares.  Its
+// device address comes from hipGetSymbolAddress, taken once per device on the
+// first call with that device current; host code never uses the array's name
+// as an address.
+namespace {
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+constexpr int kNoAllocMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::once_flag g_scratch_once[kNoAllocMaxDevices];
+void* g_scratch_ptr[kNoAllocMaxDevices];
+hipError_t g_scratch_err[kNoAllocMaxDevices];
+
+size_t round256(size_t n) { return (n + 255) & ~size_t(255); }
+
+// Workspace arrays of the allocation-free matvec, in scratch order: sorted
+// charges and potentials, multipoles, locals, Fourier-domain multipoles and
+// locals, near-field partial sums, the near field's 8 work-queue heads.
+void noalloc_layout(const DevPlan& P, size_t sizes[8]) {
+  const size_t cs = csize(P);
+  const size_t L3 = (size_t)P.L * P.L * P.L, R = (size_t)fourier_row(P.L);
+  sizes[0] = cs * (size_t)P.ny;
+  sizes[1] = cs * (size_t)P.nx;
+  sizes[2] = cs * (size_t)P.ty.nexp * L3;
+  sizes[3] = cs * (size_t)P.tx.nexp * L3;
+  sizes[4] = cs * (size_t)P.n_m2f * R;
+  sizes[5] = cs * (size_t)P.n_m2l_tgt * R;
+  sizes[6] = cs * (size_t)P.nwi * 64;
+  sizes[7] = 8 * sizeof(int);
+}
+
+// A workspace whose arrays point into the scratch: it owns nothing, so its
+// destructor (which frees what a workspace owns) must find every pointer null.
+struct BorrowedWorkspace {
+  Workspace W;
+  ~BorrowedWorkspace() {
+    W.qs = W.ps = W.M = W.Lx = W.Mt = W.Lt = W.part = W.slots = nullptr;
+    W.queue = nullptr;
+  }
+};
+}  // namespace
+
+extern "C" {
+
+size_t defmm_matvec_noalloc_capacity(void) { return kNoAllocScratchBytes; }
+
+defmm_status defmm_matvec_noalloc(defmm_plan* plan, const void* q, void* p, void* hip_stream) {
+  if (!plan) return fail(DEFMM_ERR_INVALID_ARG, "plan is NULL");
+  DevPlan& P = plan->impl;
+  if (P.host_only) return fail(DEFMM_ERR_INVALID_ARG, "plan was built for inspection only");
+  if ((P.ny > 0 && !q) || (P.nx > 0 && !p)) return fail(DEFMM_ERR_INVALID_ARG, "q or p is NULL");
+  size_t sizes[8], need = 0;
+  noalloc_layout(P, sizes);
+  for (size_t b : sizes) need += round256(b);
+  if (need > kNoAllocScratchBytes)
+    return fail(DEFMM_ERR_INVALID_ARG, "plan needs " + std::to_string(need) +
+                                           " bytes of workspace; the allocation-free matvec holds " +
+                                           std::to_string(kNoAllocScratchBytes) + ": use defmm_matvec");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(DEFMM_ERR_DEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kNoAllocMaxDevices) return fail(DEFMM_ERR_UNSUPPORTED, "device index out of range");
+  std::call_once(g_scratch_once[dev], [dev] {
+    g_scratch_err[dev] = hipGetSymbolAddress(&g_scratch_ptr[dev], HIP_SYMBOL(scratch));
+  });
+  if (g_scratch_err[dev] != hipSuccess || !g_scratch_ptr[dev])
+    return fail(DEFMM_ERR_DEVICE, std::string("scratch address: ") + hipGetErrorString(g_scratch_err[dev]));
+  unsigned char* base = (unsigned char*)g_scratch_ptr[dev];
+  BorrowedWorkspace B;
+  Workspace& W = B.W;
+  void** slot[7] = {&W.qs, &W.ps, &W.M, &W.Lx, &W.Mt, &W.Lt, &W.part};
+  size_t off = 0;
+  for (int i = 0; i < 7; ++i) {
+    *slot[i] = sizes[i] ? (void*)(base + off) : nullptr;
+    off += round256(sizes[i]);
+  }
+  W.queue = (int*)(base + off);
+  W.plan = &P;
+  W.overlap = 0;  // one stream: no side stream or events to create
+  W.m2l_variant = P.m2l_variant;
+  W.p2p_waves = P.p2p_waves_per_cu;
+  e = run_matvec(P, W, q, p, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return fail(DEFMM_ERR_DEVICE, std::string("matvec launch: ") + hipGetErrorString(e));
   return DEFMM_OK;
 }
 

@@ -59,7 +59,7 @@ EXPORTS = ["defmm_default_params", "defmm_plan_create", "defmm_plan_inspect_crea
            "defmm_workspace_autotune", "defmm_workspace_get_tuning", "defmm_workspace_set_tuning",
            "defmm_pass_name",
            "defmm_workspace_pass_work", "defmm_fourier_layout", "defmm_canonical_offset",
-           "defmm_directions"]
+           "defmm_directions", "defmm_matvec_noalloc", "defmm_matvec_noalloc_capacity"]
 
 _lib = None
 
@@ -103,9 +103,13 @@ def lib():
     L.defmm_fourier_layout.argtypes = [i32, P, P, P, P, P]
     L.defmm_canonical_offset.argtypes = [P, P, P]
     L.defmm_directions.argtypes = [i32, P, P, P]
+    L.defmm_matvec_noalloc.argtypes = [P, P, P, P]
+    L.defmm_matvec_noalloc_capacity.argtypes = []
     for name in EXPORTS:
-        if name not in ("defmm_status_string", "defmm_last_error", "defmm_pass_name"):
+        if name not in ("defmm_status_string", "defmm_last_error", "defmm_pass_name",
+                        "defmm_matvec_noalloc_capacity"):
             getattr(L, name).restype = st
+    L.defmm_matvec_noalloc_capacity.restype = ctypes.c_size_t
     _lib = L
     return L
 
@@ -295,6 +299,25 @@ class Plan:
         _check(lib().defmm_plan_export_p2p(self.h, ctypes.byref(n), _np_ptr(t), _np_ptr(s)))
         return dict(t=t, s=s)
 
+
+
+def matvec_noalloc(plan: "Plan", q, p, stream=None):
+    """p = G q through the allocation-free entry point: the workspace lives in
+    the library's static device array (defmm_matvec_noalloc_capacity() bytes per
+    GPU), nothing is allocated, so p must be given.  Calls on one GPU must not
+    overlap."""
+    if q.dtype != plan.cdtype or not q.is_cuda or q.shape != (plan.ny,) or not q.is_contiguous():
+        raise DefmmError(f"q must be a contiguous cuda {plan.cdtype} tensor of shape ({plan.ny},)")
+    if p.dtype != plan.cdtype or not p.is_cuda or p.shape != (plan.nx,) or not p.is_contiguous():
+        raise DefmmError(f"p must be a contiguous cuda {plan.cdtype} tensor of shape ({plan.nx},)")
+    _check(lib().defmm_matvec_noalloc(plan.h, ctypes.c_void_p(q.data_ptr()), ctypes.c_void_p(p.data_ptr()),
+                                      _stream_handle(stream)))
+    return p
+
+
+def noalloc_capacity() -> int:
+    """Bytes of the allocation-free matvec's static device workspace."""
+    return int(lib().defmm_matvec_noalloc_capacity())
 
 
 def torch_empty_like_out(plan, q):

@@ -21,7 +21,7 @@ def test_library_exports_every_declared_symbol():
     import re
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     hdr = open(os.path.join(root, "include", "defmm.h")).read()
-    declared = set(re.findall(r"^\s*(?:defmm_status|const char\*)\s+(defmm_\w+)\s*\(", hdr, re.M))
+    declared = set(re.findall(r"^\s*(?:defmm_status|const char\*|size_t)\s+(defmm_\w+)\s*\(", hdr, re.M))
     assert len(declared) >= 20
     L = ctypes.CDLL(defmm.LIB_PATH)
     for name in sorted(declared):
