@@ -53,6 +53,10 @@ def parse():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after timing, run one plain device copy of this size (HBM counter calibration)")
     ap.add_argument("--c64-only", action="store_true", help="skip the complex128 path and the checks")
+    ap.add_argument("--check", action="store_true",
+                    help="with --c64-only: also the error against the FP64 direct sum on sampled targets")
+    ap.add_argument("--compress", action="store_true",
+                    help="one spectrum per symmetry class of offsets (DEFMM_COMPRESS_SPECTRA)")
     ap.add_argument("--serving", action="store_true",
                     help="serving configuration: Poisson-arriving requests with continuous batching")
     ap.add_argument("--requests", type=int, default=256)
@@ -330,6 +334,8 @@ def main():
     knobs = (eta, hf, e0)
     X = wl.points()
     kflag = defmm.YUKAWA if wl.kernel == "yukawa" else 0
+    if args.compress:
+        kflag |= defmm.COMPRESS_SPECTRA
     nsteps = max(args.steps, 1)
     nq = min(nsteps + args.warmup, 64)
 
@@ -367,10 +373,18 @@ def main():
         torch.cuda.synchronize()
         del a, b
     if args.c64_only:
-        print(json.dumps({"value": round(wl.n / (ms64 / 1e3) / 1e6, 3), "ms_per_step": round(ms64, 4),
-                          "knobs": knobs, "sequential_ms_per_step": round(ms_seq, 4), "tuning": tuned,
-                          "passes_ms_per_step": {n: round(float(v), 4) for n, v in zip(names, per_step)}}),
-              flush=True)
+        line = {"value": round(wl.n / (ms64 / 1e3) / 1e6, 3), "ms_per_step": round(ms64, 4),
+                "p99_ms": round(float(np.percentile(lat64, 99)), 4),
+                "knobs": knobs, "compress": bool(args.compress), "sequential_ms_per_step": round(ms_seq, 4),
+                "tuning": tuned, "setup_s": round(setup64, 3),
+                "passes_ms_per_step": {n: round(float(v), 4) for n, v in zip(names, per_step)},
+                "stats": {k: v for k, v in plan64.stats().items() if k != "m2l_mode_per_level"}}
+        if args.check:
+            D, _ = plan64.geometry()
+            tg = W.sample_targets(wl.n, args.check_targets, 3000 + wl.seed)
+            pd = direct_sum_sampled(X, wl.charges(0), wl.kappa, 1e-12 * D, tg, screened=bool(wl.kernel == "yukawa"))
+            line["rel_l2_vs_direct_c64"] = float(np.linalg.norm(p64[tg] - pd) / np.linalg.norm(pd))
+        print(json.dumps(line), flush=True)
         return
 
     st = plan64.stats()

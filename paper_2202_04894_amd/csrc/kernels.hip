@@ -384,76 +384,125 @@ __global__ __launch_bounds__(round64(L* L* L)) void k_m2m(int64_t n, const int32
   }
 }
 
-// ------------------------------------------------------------------ M2F
-// Expansions per workgroup of M2F and F2L: the layout's frequency table is
-// staged in LDS once for all of them.
-constexpr int kFourierItems = 4;
+// ------------------------------------------------------------------ M2F / F2L
+// The DFT twiddles e^{2 pi i k / P} as compile-time constants: cosine and sine
+// of the angle reduced to [-pi, pi], by their Taylor series (40 terms, far below
+// FP64 rounding for |x| <= pi).
+struct Twiddles {
+  double c[16], s[16];
+  constexpr explicit Twiddles(int P) : c(), s() {
+    for (int k = 0; k < P; ++k) {
+      const int kk = 2 * k > P ? k - P : k;
+      const double x = 6.283185307179586476925286766559 * (double)kk / (double)P, x2 = x * x;
+      double term = x, sn = 0.0;
+      for (int n = 1; n < 40; n += 2) {
+        sn += term;
+        term *= -x2 / (double)((n + 1) * (n + 2));
+      }
+      double cs = 0.0;
+      term = 1.0;
+      for (int n = 0; n < 40; n += 2) {
+        cs += term;
+        term *= -x2 / (double)((n + 1) * (n + 2));
+      }
+      c[k] = cs;
+      s[k] = sn;
+    }
+  }
+};
 
-// M~ = DFT_P(pad(M)): three pruned 1D DFT passes (x, y, z) in LDS; only the
-// L nonzero inputs of each line enter the sums.  The row is written in the
-// order of the Fourier layout (freq), padding as zeros.
+// out[k] = sum_m in[m] e^{SIGN 2 pi i k m / P} for k < NO, m < NI: one pencil of
+// a separable DFT, twiddles folded in at compile time.
+template <typename R, int P, int NI, int NO, int SIGN>
+__device__ __forceinline__ void dft_pencil(const C2<R> (&in)[NI], C2<R> (&out)[NO]) {
+  constexpr Twiddles T(P);
+#pragma unroll
+  for (int k = 0; k < NO; ++k) {
+    C2<R> acc = in[0];
+#pragma unroll
+    for (int m = 1; m < NI; ++m) {
+      const int km = (k * m) % P;
+      const R c = (R)T.c[km], sn = (R)(SIGN * T.s[km]);
+      acc.x = fma(in[m].x, c, fma(-in[m].y, sn, acc.x));
+      acc.y = fma(in[m].x, sn, fma(in[m].y, c, acc.y));
+    }
+    out[k] = acc;
+  }
+}
+
+// Expansions per workgroup of M2F and F2L: as many as fit 64 KB of LDS, at
+// most 4 (each needs a P^3 grid and a P^2 L stage).
+template <typename R, int L>
+constexpr int fourier_items() {
+  constexpr int P = 2 * L - 1;
+  constexpr int per = (P * P * P + P * P * L) * (int)sizeof(C2<R>);
+  return per * 4 <= 65536 ? 4 : per * 2 <= 65536 ? 2 : 1;
+}
+
+// M~ = DFT_P(pad(M)) by pencils: pass x (L^2 pencils of L values -> P), pass y
+// (P L pencils), pass z (P^2 pencils), one thread per pencil and G expansions
+// per workgroup; the P^3 grid is then written in the order of the Fourier
+// layout (freq), padding as zeros.  Stage layouts keep consecutive threads on
+// consecutive LDS words.
 template <typename R, int L>
 __global__ __launch_bounds__(256) void k_m2f(int64_t n, const int32_t* __restrict__ src,
                                              const int32_t* __restrict__ freq, const C2<R>* __restrict__ M,
                                              C2<R>* __restrict__ Mt) {
-  constexpr int P = 2 * L - 1, P3 = P * P * P, L3 = L * L * L;
-  __shared__ C2<R> W[P];
-  __shared__ C2<R> a[L3];
-  __shared__ C2<R> b[P * L * L];
-  __shared__ C2<R> c[P * P * L];
-  __shared__ int32_t fq[fourier_row(L)];
-  const int64_t i0 = (int64_t)blockIdx.x * kFourierItems;
+  constexpr int P = 2 * L - 1, P3 = P * P * P, L2 = L * L, L3 = L2 * L, G = fourier_items<R, L>(), NT = 256;
+  constexpr int RW = fourier_row(L);
+  constexpr int SA = P3 > P * L2 ? P3 : P * L2;  // x-stage, then the full grid
+  constexpr int SB = P * P * L;                   // y-stage
+  __shared__ C2<R> A[G][SA];
+  __shared__ C2<R> B[G][SB];
+  __shared__ int32_t fq[RW];
+  const int64_t i0 = (int64_t)blockIdx.x * G;
   if (i0 >= n) return;
-  const int64_t i1 = min(n, i0 + kFourierItems);
-  int tid = threadIdx.x;
-  if (tid < P) W[tid] = expi<R>(-2.0 * M_PI * (double)tid / (double)P);
-  for (int p = tid; p < fourier_row(L); p += 256) fq[p] = freq[p];
-  // the next expansion's values are loaded while the current one is transformed
-  constexpr int NV = (L3 + 255) / 256;
-  C2<R> nxt[NV];
+  const int ng = (int)min((int64_t)G, n - i0);
+  const int tid = threadIdx.x;
+  for (int p = tid; p < RW; p += NT) fq[p] = freq[p];
+  // pass x: pencil (ry, rz) reads its L contiguous values; A[g][xi * L^2 + ry + L rz]
+  for (int w = tid; w < ng * L2; w += NT) {
+    const int g = w / L2, yz = w % L2;
+    const C2<R>* m = M + (int64_t)src[i0 + g] * L3 + yz * L;
+    C2<R> in[L], out[P];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    const int i = tid + 256 * v;
-    nxt[v] = i < L3 ? M[(int64_t)src[i0] * L3 + i] : C2<R>{(R)0, (R)0};
+    for (int r = 0; r < L; ++r) in[r] = m[r];
+    dft_pencil<R, P, L, P, -1>(in, out);
+#pragma unroll
+    for (int k = 0; k < P; ++k) A[g][k * L2 + yz] = out[k];
   }
-  for (int64_t item = i0; item < i1; ++item) {
+  __syncthreads();
+  // pass y: pencil (rz, xi); B[g][rz + L (xi + P yi)]
+  for (int w = tid; w < ng * P * L; w += NT) {
+    const int g = w / (P * L), q = w % (P * L), rz = q % L, xi = q / L;
+    C2<R> in[L], out[P];
 #pragma unroll
-    for (int v = 0; v < NV; ++v)
-      if (tid + 256 * v < L3) a[tid + 256 * v] = nxt[v];
-    __syncthreads();
-    if (item + 1 < i1) {
-      const int64_t e = src[item + 1];
+    for (int r = 0; r < L; ++r) in[r] = A[g][xi * L2 + r + L * rz];
+    dft_pencil<R, P, L, P, -1>(in, out);
 #pragma unroll
-      for (int v = 0; v < NV; ++v)
-        if (tid + 256 * v < L3) nxt[v] = M[e * L3 + tid + 256 * v];
+    for (int k = 0; k < P; ++k) B[g][rz + L * (xi + P * k)] = out[k];
+  }
+  __syncthreads();
+  // pass z: pencil (xi, yi) = xy; A[g][xy + P^2 zi]
+  for (int w = tid; w < ng * P * P; w += NT) {
+    const int g = w / (P * P), xy = w % (P * P);
+    C2<R> in[L], out[P];
+#pragma unroll
+    for (int r = 0; r < L; ++r) in[r] = B[g][r + L * xy];
+    dft_pencil<R, P, L, P, -1>(in, out);
+#pragma unroll
+    for (int k = 0; k < P; ++k) A[g][xy + P * P * k] = out[k];
+  }
+  __syncthreads();
+  // the G rows are contiguous
+  constexpr int NV = (G * RW + NT - 1) / NT;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const int w = tid + k * NT;
+    if (w < ng * RW) {
+      const int f = fq[w % RW];
+      Mt[i0 * RW + w] = f >= 0 ? A[w / RW][f] : C2<R>{(R)0, (R)0};
     }
-    for (int i = tid; i < P * L * L; i += 256) {
-      int xi = i % P, rest = i / P;
-      C2<R> s = {(R)0, (R)0};
-#pragma unroll
-      for (int r = 0; r < L; ++r) cfma(s, a[r + L * rest], W[(xi * r) % P]);
-      b[i] = s;
-    }
-    __syncthreads();
-    for (int i = tid; i < P * P * L; i += 256) {
-      int xi = i % P, yi = (i / P) % P, rz = i / (P * P);
-      C2<R> s = {(R)0, (R)0};
-#pragma unroll
-      for (int r = 0; r < L; ++r) cfma(s, b[xi + P * (r + L * rz)], W[(yi * r) % P]);
-      c[i] = s;
-    }
-    __syncthreads();
-    for (int p = tid; p < fourier_row(L); p += 256) {
-      const int i = fq[p];
-      C2<R> s = {(R)0, (R)0};
-      if (i >= 0) {
-        int xy = i % (P * P), zi = i / (P * P);
-#pragma unroll
-        for (int r = 0; r < L; ++r) cfma(s, c[xy + P * P * r], W[(zi * r) % P]);
-      }
-      Mt[item * fourier_row(L) + p] = s;
-    }
-    __syncthreads();
   }
 }
 
@@ -701,75 +750,79 @@ __global__ __launch_bounds__(64) void k_m2l_runs(int64_t ngrp, const int32_t* __
     if (t < tc && ok) *reinterpret_cast<C2x2<R>*>(Lt + (tf + t) * P3R + fl) = acc[t];
 }
 
-// F2L: pruned inverse DFT of each target's accumulated Fourier-domain local
-// expansion, restricted to [0,L)^3 (the 1/P^3 is folded into the spectra).
+// F2L: inverse DFT of each target's accumulated Fourier-domain local
+// expansion restricted to [0,L)^3 (the 1/P^3 is folded into the spectra), by
+// pencils as in M2F: pass z (P^2 pencils of P values -> L), pass y (P L
+// pencils), pass x (L^2 pencils, each writing its L contiguous node values).
+// Targets in XCD-aware order, G per workgroup.
 template <typename R, int L>
 __global__ __launch_bounds__(256) void k_f2l(int64_t ntgt, const int32_t* __restrict__ tgt,
                                              const int32_t* __restrict__ freq, const C2<R>* __restrict__ Lt,
                                              C2<R>* __restrict__ Lx) {
-  constexpr int P = 2 * L - 1, P3 = P * P * P, L3 = L * L * L, NT = 256;
-  __shared__ C2<R> A[P3];
-  __shared__ C2<R> B1[P * P * L];
-  __shared__ C2<R> B2[P * L * L];
-  __shared__ C2<R> W[P];
-  __shared__ int32_t fq[fourier_row(L)];
-  const int64_t nch = (ntgt + kFourierItems - 1) / kFourierItems;
+  constexpr int P = 2 * L - 1, P3 = P * P * P, L2 = L * L, L3 = L2 * L, G = fourier_items<R, L>(), NT = 256;
+  constexpr int RW = fourier_row(L);
+  constexpr int SA = P3 > P * L2 ? P3 : P * L2;  // the full grid, then the y-stage output
+  constexpr int SB = P * P * L;                   // z-stage output
+  __shared__ C2<R> A[G][SA];
+  __shared__ C2<R> B[G][SB];
+  __shared__ int32_t fq[RW];
+  const int64_t nch = (ntgt + G - 1) / G;
   const int64_t ch = xcd_item(nch);
   if (ch >= nch) return;
-  const int64_t i1 = min(ntgt, (ch + 1) * kFourierItems);
-  int tid = threadIdx.x;
-  for (int p = tid; p < fourier_row(L); p += NT) fq[p] = freq[p];
-  if (tid < P) W[tid] = expi<R>(2.0 * M_PI * (double)tid / (double)P);
-  // the next row is loaded while the current one is transformed
-  constexpr int NV = (fourier_row(L) + NT - 1) / NT;
-  C2<R> nxt[NV];
+  const int64_t i0 = ch * G;
+  const int ng = (int)min((int64_t)G, ntgt - i0);
+  const int tid = threadIdx.x;
+  // the G rows are contiguous: every load is issued before the first LDS write
+  constexpr int NV = (G * RW + NT - 1) / NT;
+  C2<R> v[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    const int p = tid + NT * v;
-    nxt[v] = p < fourier_row(L) ? Lt[ch * kFourierItems * fourier_row(L) + p] : C2<R>{(R)0, (R)0};
+  for (int k = 0; k < NV; ++k) {
+    const int w = tid + k * NT;
+    v[k] = w < ng * RW ? Lt[i0 * RW + w] : C2<R>{(R)0, (R)0};
+  }
+  for (int p = tid; p < RW; p += NT) fq[p] = freq[p];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const int w = tid + k * NT;
+    if (w < ng * RW) {
+      const int f = fq[w % RW];
+      if (f >= 0) A[w / RW][f] = v[k];
+    }
   }
   __syncthreads();
-  for (int64_t i = ch * kFourierItems; i < i1; ++i) {
+  // pass z: pencil xy = (xi, yi) over zi; B[g][kz + L xy]
+  for (int w = tid; w < ng * P * P; w += NT) {
+    const int g = w / (P * P), xy = w % (P * P);
+    C2<R> in[P], out[L];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const int p = tid + NT * v;
-      if (p < fourier_row(L)) {
-        const int f = fq[p];
-        if (f >= 0) A[f] = nxt[v];
-      }
-    }
-    __syncthreads();
-    if (i + 1 < i1) {
+    for (int m = 0; m < P; ++m) in[m] = A[g][xy + P * P * m];
+    dft_pencil<R, P, P, L, 1>(in, out);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const int p = tid + NT * v;
-        if (p < fourier_row(L)) nxt[v] = Lt[(i + 1) * fourier_row(L) + p];
-      }
-    }
-    for (int j = tid; j < P * P * L; j += NT) {
-      int xy = j % (P * P), kz = j / (P * P);
-      C2<R> s = {(R)0, (R)0};
+    for (int k = 0; k < L; ++k) B[g][k + L * xy] = out[k];
+  }
+  __syncthreads();
+  // pass y: pencil (kz, xi) over yi; A[g][xi * L^2 + ky + L kz]
+  for (int w = tid; w < ng * P * L; w += NT) {
+    const int g = w / (P * L), q = w % (P * L), kz = q % L, xi = q / L;
+    C2<R> in[P], out[L];
 #pragma unroll
-      for (int m = 0; m < P; ++m) cfma(s, A[xy + P * P * m], W[(m * kz) % P]);
-      B1[j] = s;
-    }
-    __syncthreads();
-    for (int j = tid; j < P * L * L; j += NT) {
-      int xi = j % P, ky = (j / P) % L, kz = j / (P * L);
-      C2<R> s = {(R)0, (R)0};
+    for (int m = 0; m < P; ++m) in[m] = B[g][kz + L * (xi + P * m)];
+    dft_pencil<R, P, P, L, 1>(in, out);
 #pragma unroll
-      for (int m = 0; m < P; ++m) cfma(s, B1[xi + P * m + P * P * kz], W[(m * ky) % P]);
-      B2[j] = s;
-    }
-    __syncthreads();
-    for (int j = tid; j < L3; j += NT) {
-      int kx = j % L, kyz = j / L;
-      C2<R> s = {(R)0, (R)0};
+    for (int k = 0; k < L; ++k) A[g][xi * L2 + k + L * kz] = out[k];
+  }
+  __syncthreads();
+  // pass x: pencil (ky, kz) over xi, L contiguous node values
+  for (int w = tid; w < ng * L2; w += NT) {
+    const int g = w / L2, yz = w % L2;
+    C2<R> in[P], out[L];
 #pragma unroll
-      for (int m = 0; m < P; ++m) cfma(s, B2[m + P * kyz], W[(m * kx) % P]);
-      Lx[(int64_t)tgt[i] * L3 + j] = s;
-    }
-    __syncthreads();
+    for (int m = 0; m < P; ++m) in[m] = A[g][m * L2 + yz];
+    dft_pencil<R, P, P, L, 1>(in, out);
+    C2<R>* o = Lx + (int64_t)tgt[i0 + g] * L3 + yz * L;
+#pragma unroll
+    for (int k = 0; k < L; ++k) o[k] = out[k];
   }
 }
 
@@ -1497,7 +1550,7 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
   for (int k = 0; k < nfr; ++k) {
     const int64_t rb = P.lvl_m2f[fr_lo[k]], nr = P.lvl_m2f[fr_hi[k]] - rb;
     if (nr == 0) continue;
-    DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2f<R, LL>), dim3((unsigned)((nr + kFourierItems - 1) / kFourierItems)),
+    DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2f<R, LL>), dim3((unsigned)((nr + fourier_items<R, LL>() - 1) / fourier_items<R, LL>())),
                                          dim3(256), 0, s, nr, P.m2f_exp + rb,
                                          P.freq, (const C2<R>*)M, Mt + rb * P3R));
   }
@@ -1564,7 +1617,7 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
     for (int k = 0; k < nfr; ++k) {
       const int64_t tb = P.m2l_level_tgt[fr_lo[k]], nt = P.m2l_level_tgt[fr_hi[k]] - tb;
       if (nt == 0) continue;
-      DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_f2l<R, LL>), dim3(xcd_grid((nt + kFourierItems - 1) / kFourierItems)),
+      DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_f2l<R, LL>), dim3(xcd_grid((nt + fourier_items<R, LL>() - 1) / fourier_items<R, LL>())),
                                            dim3(256), 0, s, nt, P.m2l_tgt + tb,
                                            P.freq, (const C2<R>*)(Lt + tb * P3R), Lx));
     }
