@@ -63,6 +63,12 @@ def parse():
     ap.add_argument("--geometries", type=int, default=32)
     ap.add_argument("--load", type=float, default=0.7, help="arrival rate as a fraction of one-stream capacity")
     ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--solves", type=int, default=32,
+                    help="serving: GMRES solve requests run after the matvec requests (0: none)")
+    ap.add_argument("--literal", action="store_true",
+                    help="serving: paper-literal knobs instead of the per-order setting within 1e-4")
+    ap.add_argument("--error-sample", type=int, default=8,
+                    help="serving: requests whose first matvec is checked against the FP64 direct sum")
     return ap.parse_args()
 
 
@@ -73,7 +79,7 @@ PAPER_LITERAL = (1.0, 2.0, 0)
 # timed there.  None: no setting that fits one GPU reaches it, and the
 # paper-literal setting is timed instead (the error is reported either way).
 ACCURATE = {"sphere1m": (0.3, 0.75, 1), "ellipsoid2m": (0.3, 0.75, 1), "sphere1m_yukawa": (1.0, 2.0, 0),
-            "sphere8k": None, "cube8m": None}
+            "sphere8k": (0.15, 0.75, 1), "cube8m": None}
 
 
 def direct_sum_sampled(X, q, kappa, tau, targets, screened=False):
@@ -223,11 +229,13 @@ def run_serving(args):
     Then a sample of requests is run in a mix and alone: same bits."""
     import torch
     from paper_2202_04894_amd import serving as S
+    from paper_2202_04894_amd import workloads as W
     free, _ = torch.cuda.mem_get_info()
     budget = int(0.8 * free)
 
     def requests(rate=None):
-        return S.config_requests(n_requests=args.requests, n_geometries=args.geometries, seed=7, rate=rate)
+        return S.config_requests(n_requests=args.requests, n_geometries=args.geometries, seed=7, rate=rate,
+                                 accurate=not args.literal)
 
     ex = S.DeviceExecutor()
     S.Scheduler(ex, budget, max_slots=2).run(requests()[:4])  # warm-up: kernels, allocator
@@ -242,10 +250,16 @@ def run_serving(args):
         return dict(S.summarize(out, wall), Mpoints_per_s=round(pts / wall / 1e6, 3),
                     requests_per_s=round(sum(o.ok for o in out) / wall, 3), scheduler=sch.stats)
 
+    def note(what, r):
+        print(f"[serving] {what}: {r['requests_per_s']} requests/s over {r['wall_s']} s", file=sys.stderr, flush=True)
+
     full = run(requests(), args.slots)
+    note("full load", full)
     one = run(requests(), 1)
+    note("one at a time", one)
     rate = args.load * one["requests_per_s"]
     open_loop = run(requests(rate), args.slots)
+    note("open loop", open_loop)
     # the same requests alone give the same bits (sampled)
     rng = np.random.default_rng(3)
     sample = sorted(rng.choice(args.requests, size=min(4, args.requests), replace=False).tolist())
@@ -258,6 +272,52 @@ def run_serving(args):
     for r, m in zip(sub, mix):
         alone = S.Scheduler(exk, budget, max_slots=1, keep_results=True).run([r])[0]
         same = same and m.ok and alone.ok and all(np.array_equal(a, b) for a, b in zip(alone.results, m.results))
+    # method error per request: the first matvec of a sample of requests against
+    # the FP64 direct sum on 256 sampled targets (charges regenerated from the
+    # request's seed, as the executor drew them)
+    errors = []
+    if args.error_sample:
+        esample = sorted(rng.choice(args.requests, size=min(args.error_sample, args.requests),
+                                    replace=False).tolist())
+        esub = [requests()[i] for i in esample]
+        for r in esub:
+            r.n_matvecs = 1
+        out_e = S.Scheduler(exk, budget, max_slots=args.slots, keep_results=True).run(esub)
+        for r, o in zip(esub, out_e):
+            if not o.ok:
+                continue
+            g = torch.Generator(device="cuda")
+            g.manual_seed(1_000_003 * (r.rid + 1))
+            q0 = torch.randn(r.n_points, dtype=torch.complex64, device="cuda", generator=g)
+            X = np.ascontiguousarray(r.make_points(), dtype=np.float64)
+            D = float((X.max(0) - X.min(0)).max())
+            tg = W.sample_targets(r.n_points, 256, 3000 + r.rid)
+            pd = direct_sum_sampled(X, q0.cpu().numpy().astype(np.complex128), r.kappa, 1e-12 * D, tg)
+            p0 = o.results[0].astype(np.complex128)
+            errors.append({"rid": r.rid, "n": r.n_points, "kappa_d": round(2 * r.kappa, 2), "L": r.order_L,
+                           "rel_l2_vs_direct": float(np.linalg.norm(p0[tg] - pd) / np.linalg.norm(pd))})
+    solves = None
+    if args.solves:
+        sreqs = S.solve_requests(n_requests=args.solves, n_geometries=args.geometries, seed=7,
+                                 accurate=not args.literal)
+        sch = S.Scheduler(ex, budget, max_slots=args.slots)
+        t0 = time.perf_counter()
+        out_s = sch.run(sreqs)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        print(f"[serving] {len(out_s)} solves in {wall:.1f} s", file=sys.stderr, flush=True)
+        ok = [o for o in out_s if o.ok]
+        lat = np.array([o.latency for o in ok]) if ok else np.zeros(1)
+        solves = {"solves": len(out_s), "completed": len(ok), "converged": sum(o.info.get("converged", False) for o in ok),
+                  "solves_per_s": round(len(ok) / wall, 3), "wall_s": round(wall, 3),
+                  "solve_p50_s": round(float(np.percentile(lat, 50)), 4),
+                  "solve_p99_s": round(float(np.percentile(lat, 99)), 4),
+                  "iterations_mean": round(float(np.mean([o.info["iterations"] for o in ok])), 2) if ok else None,
+                  "matvecs_total": int(sum(o.info["matvecs"] for o in ok)),
+                  "max_residual": max((o.info["residual"] for o in ok), default=None),
+                  "system": "GMRES(30) on 0.5 x + G (w x) = b, equal-area weights w, complex N(0,1) b, tol 1e-4, "
+                            "complex64, on the serving geometries",
+                  "scheduler": sch.stats}
     line = {"metric": "serving: requests/s under continuous batching (full load); p50/p99 latency at "
                       f"{args.load:.0%} load",
             "value": full["requests_per_s"], "unit": "requests/s", "n_gpus": 1, "higher_is_better": True,
@@ -265,11 +325,14 @@ def run_serving(args):
             "config": {"workload": f"{args.requests} requests, N log-uniform in [1e4, 5e5] on spheres / "
                                    f"cap-weighted ellipsoids from a pool of {args.geometries} geometries, "
                                    "kappa*D in [16, 256], L in {4, 5}, leaf<=64, 20 complex64 matvecs each",
+                       "knobs_by_L": {str(k): v for k, v in S.ACCURATE_KNOBS.items()} if not args.literal
+                       else {"4": S.LITERAL_KNOBS, "5": S.LITERAL_KNOBS},
                        "slots": args.slots, "budget_GiB": round(budget / 2 ** 30, 1)},
             "full_load": full, "one_at_a_time": one,
             "batching_speedup": round(full["requests_per_s"] / one["requests_per_s"], 3),
             "open_loop": dict(open_loop, arrival_rate_per_s=round(rate, 3), load=args.load),
-            "alone_equals_mix_bitwise": bool(same), "alone_vs_mix_sample": sample}
+            "alone_equals_mix_bitwise": bool(same), "alone_vs_mix_sample": sample,
+            "direct_sum_errors": errors, "solves": solves}
     print(json.dumps(line), flush=True)
 
 

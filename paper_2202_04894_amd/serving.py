@@ -41,6 +41,12 @@ class Request:
     n_matvecs: int = 20
     charges: Optional[Callable[[int], np.ndarray]] = None  # k -> (n,) complex charges of matvec k
     arrival: float = 0.0                  # seconds after the start of the run
+    # a solve instead of a fixed number of matvecs: GMRES on alpha x + G (w x) = b
+    # with keys alpha, weight (w, the same for every point), tol, restart,
+    # maxiter, seed (of the complex N(0,1) right-hand side); the number of
+    # matvecs is whatever the solve needs
+    solve: Optional[dict] = None
+    knobs: tuple = (1.0, 2.0, 0)          # (eta, hf_threshold, dir_refine) of the plan
 
 
 @dataclasses.dataclass
@@ -53,7 +59,8 @@ class Outcome:
     done: float = float("nan")
     plan_cached: bool = False
     matvec_ms: list = dataclasses.field(default_factory=list)
-    results: Optional[list] = None        # potentials per matvec (host), when kept
+    results: Optional[list] = None        # potentials per matvec (host), when kept; a solve: [x]
+    info: dict = dataclasses.field(default_factory=dict)  # a solve: iterations, matvecs, residual, converged
 
     @property
     def latency(self) -> float:
@@ -71,7 +78,7 @@ class Scheduler:
       start(req, plan) -> handle           enqueue the request's matvecs (reusing a
                                            workspace the plan's last request left)
       done(handle) -> bool
-      finish(handle) -> (done_time, matvec_ms, results); the workspace is kept
+      finish(handle) -> (done_time, matvec_ms, results[, info]); the workspace is kept
       release_plan(plan)                   frees the plan and its kept workspaces
     """
 
@@ -113,10 +120,13 @@ class Scheduler:
             for rid in list(running):
                 req, h, wsb, oc = running[rid]
                 if self.ex.done(h):
-                    done, ms, res = self.ex.finish(h)
+                    fin = self.ex.finish(h)
+                    done, ms, res = fin[:3]
                     oc.done = done - t0
                     oc.matvec_ms = ms
                     oc.results = res if self.keep_results else None
+                    if len(fin) > 3:
+                        oc.info = fin[3]
                     ent = self.plans[req.geometry]
                     ent[3] -= 1
                     ent[4] += 1
@@ -240,6 +250,7 @@ class DeviceExecutor:
                                       "a host segmentation fault whose cause has not been found")
         self.graphs = False
         self.pool = {}  # id(plan) -> idle (workspace, charge buffer, potential buffer) of that plan
+        self.active_solves = 0
         self.build_stream = torch.cuda.Stream()
         torch.cuda.synchronize()
         self.ref = torch.cuda.Event(enable_timing=True)
@@ -251,7 +262,8 @@ class DeviceExecutor:
         return time.perf_counter()
 
     def idle(self, dt):
-        time.sleep(dt)
+        # a running solve needs the host between its steps: poll more often
+        time.sleep(min(dt, 5e-5) if self.active_solves else dt)
 
     def estimate(self, req):
         return int(self.plan_bpp * req.n_points), int(self.ws_bpp * req.n_points)
@@ -259,7 +271,9 @@ class DeviceExecutor:
     def build(self, req):
         torch, defmm = self.torch, self.defmm
         X = torch.as_tensor(np.ascontiguousarray(req.make_points(), dtype=np.float64), device="cuda")
-        prm = defmm.Params(order_L=req.order_L, ncrit=req.ncrit, precision=defmm.C64)
+        eta, hf, e0 = req.knobs
+        prm = defmm.Params(order_L=req.order_L, ncrit=req.ncrit, eta=eta, hf_threshold=hf, dir_refine=e0,
+                           precision=defmm.C64)
         plan = defmm.Plan(X, None, req.kappa, prm, stream=self.build_stream)
         self.build_stream.synchronize()
         pb, wb = plan.footprint()
@@ -282,6 +296,8 @@ class DeviceExecutor:
                 if self.graphs:
                     qbuf = torch.empty(plan.ny, dtype=torch.complex64, device="cuda")
                     pbuf = torch.empty(plan.nx, dtype=torch.complex64, device="cuda")
+            if req.solve is not None:
+                return self._start_solve(req, plan, s, ws, qbuf, pbuf)
             qs = []
             if req.charges is not None:
                 for k in range(req.n_matvecs):
@@ -311,10 +327,47 @@ class DeviceExecutor:
                 evs.append((e0, e1))
         return dict(s=s, ws=ws, bufs=(qbuf, pbuf), qs=qs, ps=ps, evs=evs)
 
+    def _start_solve(self, req, plan, s, ws, qbuf, pbuf):
+        """A GMRES solve of alpha x + G (w x) = b on the request's stream: the
+        stepper enqueues work and is advanced from done() whenever its last
+        step has finished, so solves interleave with the other requests."""
+        torch = self.torch
+        from . import solve as SV
+        sp = req.solve
+        g = torch.Generator(device="cuda")
+        g.manual_seed(int(sp.get("seed", 1_000_003 * (req.rid + 1))))
+        b = torch.randn(req.n_points, dtype=torch.complex64, device="cuda", generator=g)
+        op = SV.SecondKindOperator(ws, complex(sp.get("alpha", 0.5)),
+                                   weights=np.full(req.n_points, float(sp.get("weight", 1.0))), stream=s)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        st = SV.GmresStepper(op, b, tol=float(sp.get("tol", 1e-4)), restart=int(sp.get("restart", 30)),
+                             maxiter=int(sp.get("maxiter", 100)), stream=s, timed=True)
+        self.active_solves += 1
+        return dict(s=s, ws=ws, bufs=(qbuf, pbuf), solve=st, op=op, b=b, e0=e0, evs=[])
+
     def done(self, h):
+        st = h.get("solve")
+        if st is not None:
+            while not st.finished and st.ready():
+                st.advance()
+            return st.finished
         return h["evs"][-1][1].query() if h["evs"] else True
 
     def finish(self, h):
+        st = h.get("solve")
+        if st is not None:
+            st.event.synchronize()
+            done = self.t_ref + self.ref.elapsed_time(st.event) / 1e3
+            r = st.result()
+            info = dict(iterations=r.iterations, matvecs=h["op"].matvecs, converged=r.converged,
+                        residual=float(r.residuals[-1]) if r.residuals else None,
+                        solve_ms=h["e0"].elapsed_time(st.event))
+            res = [r.x.cpu().numpy(), h["b"].cpu().numpy()] if self.keep_results else None
+            self.pool.setdefault(id(h["ws"].plan), []).append((h["ws"], *h["bufs"]))
+            h.clear()
+            self.active_solves -= 1
+            return done, [], res, info
         h["evs"][-1][1].synchronize() if h["evs"] else h["s"].synchronize()
         ms = [a.elapsed_time(b) for a, b in h["evs"]]
         done = self.t_ref + (self.ref.elapsed_time(h["evs"][-1][1]) / 1e3 if h["evs"] else 0.0)
@@ -332,8 +385,16 @@ class DeviceExecutor:
         plan.close()
 
 
+# Knob settings (eta, hf_threshold, dir_refine) per interpolation order whose
+# potentials came within 1e-4 of the FP64 direct sum in device and oracle
+# sweeps (L = 4 on 8,192 sphere points at kappa*D = 32; L = 5 on 1,048,576
+# sphere points at kappa*D = 256); the paper-literal setting is (1, 2, 0).
+ACCURATE_KNOBS = {4: (0.15, 0.75, 1), 5: (0.3, 0.75, 1)}
+LITERAL_KNOBS = (1.0, 2.0, 0)
+
+
 def config_requests(n_requests=256, n_geometries=32, seed=7, n_min=10_000, n_max=500_000, kd=(16.0, 256.0),
-                    orders=(4, 5), n_matvecs=20, rate=None, host_charges=False):
+                    orders=(4, 5), n_matvecs=20, rate=None, host_charges=False, accurate=True):
     """Requests with the shapes of the serving configuration: N log-uniform in
     [n_min, n_max] on the unit sphere or the cap-weighted ellipsoid (50/50),
     kappa*D uniform in kd, L drawn from orders, leaves <= 64, fresh complex
@@ -364,15 +425,36 @@ def config_requests(n_requests=256, n_geometries=32, seed=7, n_min=10_000, n_max
         def ch(k, n=n, cseed=cseed):
             return W.charges(n, cseed + k, np.complex64)
 
-        reqs.append(Request(rid=i, geometry=f"{kind}-{n}-{kD:.3f}-{L}", make_points=mk, n_points=n,
+        knobs = ACCURATE_KNOBS[L] if accurate else LITERAL_KNOBS
+        reqs.append(Request(rid=i, geometry=f"{kind}-{n}-{kD:.3f}-{L}-{knobs}", make_points=mk, n_points=n,
                             kappa=kD / 2.0, order_L=L, ncrit=64, n_matvecs=n_matvecs,
-                            charges=ch if host_charges else None, arrival=t))
+                            charges=ch if host_charges else None, arrival=t, knobs=knobs))
+    return reqs
+
+
+# Surface areas of the two serving geometries (unit sphere; the (1, 0.5, 0.25)
+# ellipsoid, by Thomsen's approximation), for equal-area quadrature weights.
+SURFACE_AREA = {"sphere": 4.0 * np.pi, "ellipsoid": 3.975}
+
+
+def solve_requests(n_requests=32, n_geometries=32, seed=7, rate=None, alpha=0.5, tol=1e-4, restart=30,
+                   maxiter=100, **kw):
+    """Solve requests on the geometries of config_requests (same pool, same
+    seed): GMRES on alpha x + G (w x) = b with equal-area weights w and a
+    seeded complex N(0,1) right-hand side, to a relative residual of tol; each
+    needs a data-dependent number of matvecs."""
+    reqs = config_requests(n_requests=n_requests, n_geometries=n_geometries, seed=seed, rate=rate, **kw)
+    for r in reqs:
+        kind = r.geometry.split("-")[0]
+        r.solve = dict(alpha=alpha, weight=SURFACE_AREA[kind] / r.n_points, tol=tol, restart=restart,
+                       maxiter=maxiter, seed=7_000_003 * (r.rid + 1))
+        r.n_matvecs = 0
     return reqs
 
 
 def summarize(outcomes, wall_s):
     ok = [o for o in outcomes if o.ok]
-    mv = np.array([m for o in ok for m in o.matvec_ms]) if ok else np.zeros(1)
+    mv = np.array([m for o in ok for m in o.matvec_ms]) if any(o.matvec_ms for o in ok) else np.zeros(1)
     lat = np.array([o.latency for o in ok]) if ok else np.zeros(1)
     return dict(requests=len(outcomes), completed=len(ok), failed=len(outcomes) - len(ok),
                 wall_s=round(wall_s, 3),

@@ -218,6 +218,26 @@ def test_sphere8k_against_oracle_and_direct_sum():
     assert e < 5e-2  # paper-literal knobs at L = 4 (method error, not a parity bound)
 
 
+def test_sphere8k_accurate_setting_within_1e4_of_direct_sum():
+    """The same workload at the knob setting an oracle sweep found to reach 1e-4
+    at L = 4 (eta = 0.15, high-frequency threshold 0.75, one extra direction
+    refinement; oracle 4.8e-5): complex128 and complex64 against the oracle and
+    the direct sum on every target."""
+    defmm = _defmm()
+    wl = W.WORKLOADS["sphere8k"]
+    X = wl.points()
+    q = wl.charges(0)
+    kw = dict(order_L=wl.L, ncrit=wl.ncrit, eta=0.15, hf_threshold=0.75, dir_refine=1)
+    ref = oracle.FMM(X, None, wl.kappa, oracle_params(defmm.Params(**kw))).apply(q)
+    p128, plan, _ = run_gpu(X, q, wl.kappa, defmm.Params(precision=defmm.C128, **kw))
+    p64, _, _ = run_gpu(X, q, wl.kappa, defmm.Params(precision=defmm.C64, **kw))
+    assert_close(p128, ref, 1e-11)
+    assert_close(p64, ref, 2e-5)
+    D, _ = plan.geometry()
+    direct = oracle.direct_sum(X, X, q, wl.kappa, 1e-12 * D)
+    assert rel(p128, direct) < 1e-4 and rel(p64, direct) < 1e-4, (rel(p128, direct), rel(p64, direct))
+
+
 def test_repeatable_bitwise():
     defmm = _defmm()
     X = W.ellipsoid(6000, 9)

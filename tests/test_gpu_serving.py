@@ -82,3 +82,42 @@ def test_budget_forces_queueing_on_device():
     assert all(o.ok for o in out), [o.error for o in out]
     assert st["peak_bytes"] <= budget and st["evictions"] > 0 and st["max_running"] < len(reqs)
     print("footprints (MB):", [round(f / 2 ** 20, 1) for f in fps], "stats:", st)
+
+
+def test_solve_requests_in_the_mix():
+    """GMRES solves as serving requests (alpha x + G (w x) = b, a data-dependent
+    number of matvecs each), admitted and run concurrently with matvec requests:
+    every solve converges in the FMM's own residual, and its solution meets the
+    system built from the oracle's FP64 direct sum up to the method error of the
+    paper-literal knobs."""
+    import oracle
+    from paper_2202_04894_amd.serving import Request, SURFACE_AREA
+    reqs = _requests(n_matvecs=2)[:3]
+    specs = [("sphere", 4000, 20.0, 5), ("ellipsoid", 6000, 30.0, 4), ("sphere", 3000, 12.0, 5)]
+    for i, (kind, n, kD, L) in enumerate(specs):
+        gseed = 900 + n
+
+        def mk(kind=kind, n=n, gseed=gseed):
+            return W.GENERATORS[kind](n, gseed)
+
+        reqs.append(Request(rid=10 + i, geometry=f"{kind}-{n}-{kD}-{L}", make_points=mk, n_points=n,
+                            kappa=kD / 2, order_L=L, ncrit=64, n_matvecs=0, arrival=0.0,
+                            solve=dict(alpha=0.5, weight=SURFACE_AREA[kind] / n, tol=1e-5, restart=30,
+                                       maxiter=150, seed=77 + i)))
+    out, st = _run(reqs, slots=6)
+    assert all(o.ok for o in out), [o.error for o in out]
+    assert st["max_running"] >= 4
+    for r, o in zip(reqs, out):
+        if r.solve is None:
+            assert len(o.results) == 2
+            continue
+        assert o.info["converged"] and o.info["matvecs"] > o.info["iterations"] > 1, o.info
+        x, b = (v.astype(np.complex128) for v in o.results)
+        X = r.make_points()
+        D = float((X.max(0) - X.min(0)).max())
+        w = np.full(r.n_points, r.solve["weight"])
+        Gx = oracle.direct_sum(X, X, w * x, r.kappa, 1e-12 * D)
+        true_res = np.linalg.norm(0.5 * x + Gx - b) / np.linalg.norm(b)
+        print(f"solve {r.rid}: {o.info['iterations']} iterations, {o.info['matvecs']} matvecs, "
+              f"direct-sum residual {true_res:.2e}")
+        assert true_res < 5e-2, true_res
