@@ -236,19 +236,24 @@ defmm_status defmm_workspace_set_timing(defmm_workspace* ws, int32_t enable);
                     merged by source (default);
    dense_levels     bit l set: level l runs the dense MFMA M2L (only levels whose
                     dense matrices the plan built: DEFMM_M2L_AUTO or _DENSE);
+   updown_variant   M2M and L2L kernels: 1 = one wave per pair of expansions of
+                    a cell, pencils in registers (default); 0 = one workgroup
+                    per expansion, one node per thread;
    ms               median matvec time measured by defmm_workspace_autotune. */
 typedef struct {
   int32_t overlap;
   int32_t p2p_waves_per_cu;
   int32_t m2l_variant;
   uint32_t dense_levels;
+  int32_t updown_variant;
   double ms;
 } defmm_tuning;
 
 /* Times the candidate execution choices on this workspace (each: one warm-up
    and `reps` matvecs of q into p on hip_stream; host-synchronous) and keeps
-   the fastest: the Fourier-path M2L variant in sequence first, then, level by
-   level, the dense MFMA M2L where the plan holds its matrices, then the
+   the fastest: the Fourier-path M2L variant in sequence first, then the M2M/L2L
+   kernels, then, level by level, the dense MFMA M2L where the plan holds its
+   matrices, then the
    overlapped near field forked early or after M2F, with 2, 3, 4 and 6 waves
    per CU.  q and p as in defmm_matvec; p holds a valid result afterwards.
    chosen (optional) receives the choice. */

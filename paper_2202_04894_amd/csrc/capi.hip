@@ -83,6 +83,33 @@ void upload_tree(DevPlan& P, DevTree& d, const Tree& t) {
 
 size_t csize(const DevPlan& P) { return P.precision == 0 ? 16 : 8; }
 
+// Expansions per wave of the pencil M2M/L2L kernels (the device side's
+// pencil_epw): two when a half wave holds the L^2 pencils of one expansion.
+int pencil_epw_host(int L) { return L * L <= 32 ? 2 : 1; }
+
+// Work list of the pencil kernels from the cell of each item (items of a cell
+// consecutive): pairs of items of the same cell, (i, -1) for a lone one; with
+// one expansion per wave, every item alone.
+std::vector<int32_t> pencil_pairs(const std::vector<int32_t>& cell, int L) {
+  std::vector<int32_t> out;
+  const int64_t n = (int64_t)cell.size();
+  if (pencil_epw_host(L) == 1) {
+    for (int64_t i = 0; i < n; ++i) out.push_back((int32_t)i);
+    return out;
+  }
+  for (int64_t i = 0; i < n;) {
+    out.push_back((int32_t)i);
+    if (i + 1 < n && cell[i + 1] == cell[i]) {
+      out.push_back((int32_t)(i + 1));
+      i += 2;
+    } else {
+      out.push_back(-1);
+      i += 1;
+    }
+  }
+  return out;
+}
+
 
 }  // namespace
 
@@ -261,6 +288,11 @@ defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int
       P.m2m[l].a = upload(P, H.m2m_par[l]);
       P.m2m[l].b = upload(P, H.m2m_child[l]);
       P.m2m[l].oct = upload(P, H.m2m_oct[l]);
+      std::vector<int32_t> cell(H.m2m_par[l].size());
+      for (size_t i = 0; i < cell.size(); ++i) cell[i] = H.ty->exp_cell[H.m2m_par[l][i]];
+      std::vector<int32_t> pr = pencil_pairs(cell, P.L);
+      P.m2m[l].npair = (int64_t)pr.size() / pencil_epw_host(P.L);
+      P.m2m[l].pair = upload(P, pr);
     }
     P.m2f_exp = upload(P, H.m2f_exp);
     P.n_m2f = (int64_t)H.m2f_exp.size();
@@ -280,6 +312,18 @@ defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int
     P.grp_tcount = upload(P, H.grp_tcount);
     P.grp_run_begin = upload(P, H.grp_run_begin);
     P.runs = upload(P, H.runs);
+    if (!P.sym && !H.runs.empty()) {
+      const int64_t half = fourier_row(P.L) / 2;
+      const int64_t n_rows = (int64_t)H.m2f_exp.size();
+      if ((n_rows + 1) * half < ((int64_t)1 << 31) && ((int64_t)H.offsets.size() + 1) * half < ((int64_t)1 << 31)) {
+        std::vector<int32_t> ro(H.runs.size());
+        for (size_t i = 0; i < H.runs.size(); ++i) {
+          const int32_t v = H.runs[i];
+          ro[i] = v < 0 ? v : (int32_t)((i % 9 == 0 ? (int64_t)v : (int64_t)(v >> 6)) * half);
+        }
+        P.runs_off = upload(P, ro);
+      }
+    }
     P.n_grp = (int64_t)H.grp_tfirst.size();
     P.lvl_grp.assign(H.lvl_grp.begin(), H.lvl_grp.end());
     P.lvl_m2f.assign(H.lvl_m2f.begin(), H.lvl_m2f.end());
@@ -336,6 +380,11 @@ defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int
       P.l2l[l].b = upload(P, H.l2l_begin[l]);
       P.l2l[l].c = upload(P, H.l2l_par[l]);
       P.l2l[l].oct = upload(P, H.l2l_oct[l]);
+      std::vector<int32_t> cell(H.l2l_ch[l].size());
+      for (size_t i = 0; i < cell.size(); ++i) cell[i] = H.tx.exp_cell[H.l2l_ch[l][i]];
+      std::vector<int32_t> pr = pencil_pairs(cell, P.L);
+      P.l2l[l].npair = (int64_t)pr.size() / pencil_epw_host(P.L);
+      P.l2l[l].pair = upload(P, pr);
     }
     P.l2p_cell = upload(P, H.l2p_cell);
     P.l2p_first = upload(P, H.l2p_first);
@@ -755,6 +804,7 @@ defmm_status defmm_workspace_get_tuning(const defmm_workspace* ws, defmm_tuning*
   out->overlap = ws->impl.overlap;
   out->p2p_waves_per_cu = ws->impl.p2p_waves;
   out->m2l_variant = ws->impl.m2l_variant;
+  out->updown_variant = ws->impl.pencil_updown;
   out->dense_levels = 0;
   for (size_t l = 0; l < ws->impl.dense_level.size() && l < 32; ++l)
     if (ws->impl.dense_level[l]) out->dense_levels |= 1u << l;
@@ -765,12 +815,13 @@ defmm_status defmm_workspace_get_tuning(const defmm_workspace* ws, defmm_tuning*
 defmm_status defmm_workspace_set_tuning(defmm_workspace* ws, const defmm_tuning* t) {
   if (!ws || !t) return fail(DEFMM_ERR_INVALID_ARG, "NULL argument");
   if (t->p2p_waves_per_cu < 1 || t->p2p_waves_per_cu > 32 || t->m2l_variant < 0 || t->m2l_variant > 2 ||
-      t->overlap < 0 || t->overlap > 2)
+      t->overlap < 0 || t->overlap > 2 || t->updown_variant < 0 || t->updown_variant > 1)
     return fail(DEFMM_ERR_INVALID_ARG, "tuning out of range");
   ws->impl.graph_stale = true;
   ws->impl.overlap = t->overlap;
   ws->impl.p2p_waves = t->p2p_waves_per_cu;
   ws->impl.m2l_variant = t->m2l_variant;
+  ws->impl.pencil_updown = t->updown_variant;
   const DevPlan& P = *ws->impl.plan;
   for (size_t l = 0; l < ws->impl.dense_level.size(); ++l)
     ws->impl.dense_level[l] = (l < 32 && (t->dense_levels >> l) & 1u && P.dense_ok[l]) ? 1 : 0;
@@ -796,6 +847,7 @@ defmm_status defmm_workspace_autotune(defmm_plan* plan, defmm_workspace* ws, con
     W.overlap = t.overlap;
     W.p2p_waves = t.p2p_waves_per_cu;
     W.m2l_variant = t.m2l_variant;
+    W.pencil_updown = t.updown_variant;
     for (size_t l = 0; l < W.dense_level.size(); ++l)
       W.dense_level[l] = (l < 32 && (t.dense_levels >> l) & 1u && P.dense_ok[l]) ? 1 : 0;
   };
@@ -818,19 +870,25 @@ defmm_status defmm_workspace_autotune(defmm_plan* plan, defmm_workspace* ws, con
     }
     return e;
   };
-  defmm_tuning best{0, 8, 2, 0u, 1e30};
+  defmm_tuning best{0, 8, 2, 0u, 1, 1e30};
   hipError_t err = hipSuccess;
   // M2L variant, timed with every pass in sequence
   for (int var : {2, 1}) {
-    defmm_tuning t{0, 8, var, 0u, 0.0};
+    defmm_tuning t{0, 8, var, 0u, 1, 0.0};
     err = measure(t, &t.ms);
     if (err != hipSuccess) break;
     if (t.ms < best.ms) best = t;
   }
+  // M2M/L2L kernels
+  if (err == hipSuccess) {
+    defmm_tuning t{0, 8, best.m2l_variant, 0u, 0, 0.0};
+    err = measure(t, &t.ms);
+    if (err == hipSuccess && t.ms < best.ms) best = t;
+  }
   // per level: dense MFMA M2L instead of the Fourier path where it is faster
   for (size_t l = 0; l < P.dense_ok.size() && l < 32 && err == hipSuccess; ++l) {
     if (!P.dense_ok[l]) continue;
-    defmm_tuning t{0, 8, best.m2l_variant, best.dense_levels | (1u << l), 0.0};
+    defmm_tuning t{0, 8, best.m2l_variant, best.dense_levels | (1u << l), best.updown_variant, 0.0};
     err = measure(t, &t.ms);
     if (err != hipSuccess) break;
     if (t.ms < best.ms) best = t;
@@ -840,7 +898,7 @@ defmm_status defmm_workspace_autotune(defmm_plan* plan, defmm_workspace* ws, con
   for (int ov : {1, 2})
     for (int w : {2, 3, 4, 6}) {
       if (err != hipSuccess) break;
-      defmm_tuning t{ov, w, best.m2l_variant, best.dense_levels, 0.0};
+      defmm_tuning t{ov, w, best.m2l_variant, best.dense_levels, best.updown_variant, 0.0};
       err = measure(t, &t.ms);
       if (err != hipSuccess) break;
       if (t.ms < best.ms) best = t;

@@ -50,6 +50,10 @@ struct LevelTable {  // per-level operator table on the device
   int32_t* b = nullptr;
   int32_t* c = nullptr;
   int8_t* oct = nullptr;
+  // the pencil kernels' work: items of one cell taken two at a time when a half
+  // wave holds an expansion (L^2 <= 32), else one at a time (-1 = no second)
+  int32_t* pair = nullptr;
+  int64_t npair = 0;
 };
 
 struct DevPlan {
@@ -75,6 +79,10 @@ struct DevPlan {
   int64_t n_m2l_tgt = 0, n_m2l = 0;
   std::vector<int64_t> m2l_level_tgt;  // target range per level (host copy)
   int32_t *grp_tfirst = nullptr, *grp_tcount = nullptr, *grp_run_begin = nullptr, *runs = nullptr;
+  // runs with element offsets instead of indices (per-offset spectra only): the
+  // source's row and each target's spectrum as offsets in 16-byte pairs, so
+  // the kernel adds instead of multiplying; null when an offset would not fit
+  int32_t* runs_off = nullptr;
   int64_t n_grp = 0;
   std::vector<int64_t> lvl_grp, lvl_m2f;  // per level: group range, Fourier-row range
   // dense M2L (per level; K tables only where they fit, see dense_ok)
@@ -119,6 +127,7 @@ struct Workspace {
   int overlap = 2;  // 0: in sequence; 1: near field forked after the gather; 2: forked after M2F
   int p2p_waves = 2;     // persistent near-field workgroups (one wave) per CU when overlapped
   int m2l_variant = 2;   // 0: fused per target, 1: sliced per target, 2: sliced per group of 8 (source runs)
+  int pencil_updown = 1;  // M2M and L2L: 1 = pencil kernels (a wave per expansion pair), 0 = a workgroup per expansion
   std::vector<char> dense_level;  // per level: use the dense MFMA M2L
   void* slots = nullptr;          // dense M2L per-pair results, dense_slots_max x L^3
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;

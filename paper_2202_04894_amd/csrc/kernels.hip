@@ -98,16 +98,34 @@ __device__ __forceinline__ C2<float> expi<float>(double a) {
   return {__builtin_amdgcn_cosf(f), __builtin_amdgcn_sinf(f)};
 }
 
-// Lagrange basis on the L equispaced nodes j/(L-1) of [0,1] (Sec. 2.3).
+// 1 / prod_{j != m} (m - j) for the L equispaced nodes: the constant factor
+// of the Lagrange basis polynomial of node m (computed in FP64 at compile time).
+template <int L>
+struct LagrangeScale {
+  double c[L];
+  constexpr LagrangeScale() : c() {
+    for (int m = 0; m < L; ++m) {
+      double d = 1.0;
+      for (int j = 0; j < L; ++j)
+        if (j != m) d *= (double)(m - j);
+      c[m] = 1.0 / d;
+    }
+  }
+};
+
+// Lagrange basis on the L equispaced nodes j/(L-1) of [0,1] (Sec. 2.3):
+// l_m(t) = c_m prod_{j != m} (s - j), s = (L-1) t, with c_m a compile-time
+// constant (no division at run time).
 template <typename R, int L>
 __device__ __forceinline__ void lagrange(R t, R* w) {
+  constexpr LagrangeScale<L> C{};
   R s = t * (R)(L - 1);
 #pragma unroll
   for (int m = 0; m < L; ++m) {
-    R v = (R)1;
+    R v = (R)C.c[m];
 #pragma unroll
     for (int j = 0; j < L; ++j)
-      if (j != m) v *= (s - (R)j) / (R)(m - j);
+      if (j != m) v *= (s - (R)j);
     w[m] = v;
   }
 }
@@ -311,6 +329,254 @@ __device__ __forceinline__ void son_matrices(R (*A)[L][L]) {
     lagrange<R, L>(((R)b + (R)r / (R)(L - 1)) * (R)0.5, w);
 #pragma unroll
     for (int l = 0; l < L; ++l) A[b][l][r] = w[l];
+  }
+}
+
+// ------------------------------------------------------------------ pencil M2M / L2L
+// Son matrices as compile-time constants: a[b][l][r] = l_l((b + r/(L-1))/2),
+// the Lagrange basis of the father's nodes at the son's nodes (b = the son's
+// half along the axis), in FP64.
+template <int L>
+struct SonMatrices {
+  double a[2][L][L];
+  constexpr SonMatrices() : a() {
+    for (int b = 0; b < 2; ++b)
+      for (int r = 0; r < L; ++r) {
+        const double s = ((double)b + (double)r / (double)(L - 1)) * 0.5 * (double)(L - 1);
+        for (int l = 0; l < L; ++l) {
+          double v = 1.0;
+          for (int j = 0; j < L; ++j)
+            if (j != l) v *= (s - (double)j) / (double)(l - j);
+          a[b][l][r] = v;
+        }
+      }
+  }
+};
+
+// out[l] = sum_r w(l, r) in[r] along one axis with the son matrix of half B:
+// w = a[B][l][r] (son to father, M2M) or a[B][r][l] (father to son, L2L).
+// Zero weights (a node shared by father and son) are skipped at compile time.
+template <typename R, int L, int B, bool TR>
+__device__ __forceinline__ void son_mode(const C2<R> (&in)[L], C2<R> (&out)[L]) {
+  constexpr SonMatrices<L> S{};
+#pragma unroll
+  for (int l = 0; l < L; ++l) {
+    C2<R> acc = {(R)0, (R)0};
+#pragma unroll
+    for (int r = 0; r < L; ++r) {
+      const R w = (R)(TR ? S.a[B][r][l] : S.a[B][l][r]);
+      if (w != (R)0) cfma_r(acc, in[r], w);
+    }
+    out[l] = acc;
+  }
+}
+
+template <typename R, int L, bool TR>
+__device__ __forceinline__ void son_mode_b(int b, const C2<R> (&in)[L], C2<R> (&out)[L]) {
+  if (b) son_mode<R, L, 1, TR>(in, out);
+  else son_mode<R, L, 0, TR>(in, out);
+}
+
+// exp(i 2 pi t) from FP64 turns t, reduced in FP64 (the phases of M2M/L2L).
+template <typename R>
+__device__ __forceinline__ C2<R> expi_turns(double t);
+template <>
+__device__ __forceinline__ C2<float> expi_turns<float>(double t) {
+  const float f = (float)(t - rint(t));
+  return {__builtin_amdgcn_cosf(f), __builtin_amdgcn_sinf(f)};
+}
+template <>
+__device__ __forceinline__ C2<double> expi_turns<double>(double t) {
+  double s, c;
+  sincos_turns(t, s, c);
+  return {c, s};
+}
+
+// Expansions (of one cell) per wave in the pencil kernels: two when a half
+// wave holds the L^2 pencils of one expansion.
+template <int L>
+constexpr int pencil_epw() { return L * L <= 32 ? 2 : 1; }
+
+// M2M by pencils (Sec. 5.2, eq. dlefturight, one father cell's expansions
+// sharing a wave).  A wave serves up to two expansions v of one father cell;
+// lane p < L^2 of a half holds pencil p.  For each son: the son's expansion
+// Father(v) as x-pencils (r_y, r_z), the son-node phases exp(-i kappa <y'_r -
+// a_s, v>) with FP64 arguments, three mode products with the son matrices
+// (x-, y- and z-pencils, exchanged through LDS), summed over sons in
+// z-pencils (l_x, l_y); then the father-node phases exp(i kappa <y_l - a_s, v>).
+// Both expansions of a wave share the father cell, so its sons and their
+// octants (which choose the matrices) are the same for every lane.
+template <typename R, int L>
+__global__ __launch_bounds__(64) void k_m2m_p(int64_t npair, const int32_t* __restrict__ pairs,
+                                              const int32_t* __restrict__ par, const int32_t* __restrict__ child,
+                                              const int8_t* __restrict__ oct, TreeView T, Geo g,
+                                              C2<R>* __restrict__ M) {
+  constexpr int L2 = L * L, L3 = L2 * L, EPW = pencil_epw<L>(), HW = 64 / EPW;
+  __shared__ C2<R> st[EPW][L3];
+  const int64_t w = blockIdx.x;
+  if (w >= npair) return;
+  const int lane = threadIdx.x, hf = lane / HW, p = lane % HW;
+  const int item0 = pairs[EPW * w];
+  const int item = EPW == 2 ? pairs[EPW * w + hf] : item0;
+  const bool on = item >= 0 && p < L2;
+  const int it = item >= 0 ? item : item0;
+  const int pe = par[it];
+  const int c = T.exp_cell[pe];
+  const double h = ldexp(g.D, -T.level[c]), hc = 0.5 * h;
+  const double v0 = T.exp_u[3 * pe], v1 = T.exp_u[3 * pe + 1], v2 = T.exp_u[3 * pe + 2];
+  // turns per unit of son-node index along each axis, kappa hc v_d / ((L-1) 2 pi)
+  constexpr double inv2pi = 0.15915494309189533577;
+  const double ks = g.kappa * hc * inv2pi;
+  const int a0 = p % L, a1 = (p / L) % L;  // (first, second) pencil coordinates
+  C2<R> acc[L];
+#pragma unroll
+  for (int l = 0; l < L; ++l) acc[l] = {(R)0, (R)0};
+  C2<R>* stg = st[hf];
+  for (int k = 0; k < 8; ++k) {
+    const int ce0 = child[(int64_t)item0 * 8 + k];
+    if (ce0 < 0) break;  // the same for both expansions of the wave
+    const int o = oct[(int64_t)item0 * 8 + k];
+    const int bx = o & 1, by = (o >> 1) & 1, bz = (o >> 2) & 1;
+    const int ce = child[(int64_t)it * 8 + k];
+    C2<R> in[L], out[L];
+#pragma unroll
+    for (int r = 0; r < L; ++r) in[r] = {(R)0, (R)0};
+    if (on) {
+      // x-pencil (r_y, r_z) = (a0, a1) of the son, times exp(-i kappa <y'_r - a_s, v>)
+      const C2<R>* src = M + (int64_t)ce * L3 + p * L;
+      const double t0 = -ks * (v0 * bx + v1 * (by + (double)a0 / (L - 1)) + v2 * (bz + (double)a1 / (L - 1)));
+      const double dt = -ks * v0 / (L - 1);
+#pragma unroll
+      for (int r = 0; r < L; ++r) in[r] = cmul(src[r], expi_turns<R>(t0 + dt * r));
+    }
+    son_mode_b<R, L, false>(bx, in, out);
+    __syncthreads();
+    if (on) {  // x-pencil (r_y, r_z) -> stage [l_x][r_z][r_y]
+#pragma unroll
+      for (int l = 0; l < L; ++l) stg[(l + L * a1) * L + a0] = out[l];
+    }
+    __syncthreads();
+    if (on) {  // y-pencil (l_x, r_z) = (a0, a1)
+#pragma unroll
+      for (int r = 0; r < L; ++r) in[r] = stg[p * L + r];
+    }
+    son_mode_b<R, L, false>(by, in, out);
+    __syncthreads();
+    if (on) {  // -> stage [l_x][l_y][r_z]
+#pragma unroll
+      for (int l = 0; l < L; ++l) stg[(a0 + L * l) * L + a1] = out[l];
+    }
+    __syncthreads();
+    if (on) {  // z-pencil (l_x, l_y) = (a0, a1)
+#pragma unroll
+      for (int r = 0; r < L; ++r) in[r] = stg[p * L + r];
+    }
+    son_mode_b<R, L, false>(bz, in, out);
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      acc[l].x += out[l].x;
+      acc[l].y += out[l].y;
+    }
+  }
+  if (on) {
+    // father-node phases exp(i kappa h <l, v> / (L-1)), z-pencil (l_x, l_y)
+    const double kf = g.kappa * h / (L - 1) * inv2pi;
+    const double t0 = kf * (v0 * a0 + v1 * a1), dt = kf * v2;
+    C2<R>* dst = M + (int64_t)pe * L3 + p;
+#pragma unroll
+    for (int l = 0; l < L; ++l) dst[L2 * l] = cmul(acc[l], expi_turns<R>(t0 + dt * l));
+  }
+}
+
+// L2L by pencils, the transpose of k_m2m_p: a wave serves up to two local
+// expansions u of one son cell; for each father expansion v feeding u
+// (Father(v) = u, or every one for a low-frequency son): the father's values
+// as x-pencils, the father-node phases exp(-i kappa <x_k - a_t, v>), three
+// mode products with the transposed son matrices, the son-node phases
+// exp(i kappa <x'_h - a_t, v>), summed over fathers; then added to the son's
+// values.  The two expansions may have different numbers of fathers.
+template <typename R, int L>
+__global__ __launch_bounds__(64) void k_l2l_p(int64_t npair, const int32_t* __restrict__ pairs,
+                                              const int32_t* __restrict__ ch, const int32_t* __restrict__ begin,
+                                              const int32_t* __restrict__ par, const int8_t* __restrict__ oct,
+                                              TreeView T, Geo g, C2<R>* __restrict__ Lx) {
+  constexpr int L2 = L * L, L3 = L2 * L, EPW = pencil_epw<L>(), HW = 64 / EPW;
+  __shared__ C2<R> st[EPW][L3];
+  const int64_t w = blockIdx.x;
+  if (w >= npair) return;
+  const int lane = threadIdx.x, hf = lane / HW, p = lane % HW;
+  const int item0 = pairs[EPW * w];
+  const int item1 = EPW == 2 ? pairs[EPW * w + 1] : -1;
+  const int item = hf == 0 ? item0 : item1;
+  const bool on = item >= 0 && p < L2;
+  const int it = item >= 0 ? item : item0;
+  const int ce = ch[it];
+  const int c = T.exp_cell[ce];
+  const double hcs = ldexp(g.D, -T.level[c]), hp = 2.0 * hcs;
+  constexpr double inv2pi = 0.15915494309189533577;
+  const int a0 = p % L, a1 = (p / L) % L;
+  const int k0 = begin[it], k1 = begin[it + 1];
+  const int n0 = begin[item0 + 1] - begin[item0];
+  const int n1 = item1 >= 0 ? begin[item1 + 1] - begin[item1] : 0;
+  const int nmax = n0 > n1 ? n0 : n1;
+  const int o = oct[begin[item0]];  // the son's octant: the same for every father of the wave
+  const int bx = o & 1, by = (o >> 1) & 1, bz = (o >> 2) & 1;
+  C2<R> acc[L];
+#pragma unroll
+  for (int l = 0; l < L; ++l) acc[l] = {(R)0, (R)0};
+  C2<R>* stg = st[hf];
+  for (int k = 0; k < nmax; ++k) {
+    const bool act = on && k0 + k < k1;
+    const int pe = par[act ? k0 + k : k0];
+    const double v0 = T.exp_u[3 * pe], v1 = T.exp_u[3 * pe + 1], v2 = T.exp_u[3 * pe + 2];
+    C2<R> in[L], out[L];
+#pragma unroll
+    for (int r = 0; r < L; ++r) in[r] = {(R)0, (R)0};
+    if (act) {
+      // x-pencil (k_y, k_z) of the father, times exp(-i kappa hp <k, v> / (L-1))
+      const C2<R>* src = Lx + (int64_t)pe * L3 + p * L;
+      const double kf = g.kappa * hp / (L - 1) * inv2pi;
+      const double t0 = -kf * (v1 * a0 + v2 * a1), dt = -kf * v0;
+#pragma unroll
+      for (int r = 0; r < L; ++r) in[r] = cmul(src[r], expi_turns<R>(t0 + dt * r));
+    }
+    son_mode_b<R, L, true>(bx, in, out);
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int l = 0; l < L; ++l) stg[(l + L * a1) * L + a0] = out[l];
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < L; ++r) in[r] = stg[p * L + r];
+    }
+    son_mode_b<R, L, true>(by, in, out);
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int l = 0; l < L; ++l) stg[(a0 + L * l) * L + a1] = out[l];
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int r = 0; r < L; ++r) in[r] = stg[p * L + r];
+      son_mode_b<R, L, true>(bz, in, out);
+      // son-node phases exp(i kappa hc <b + h / (L-1), v>), z-pencil (h_x, h_y)
+      const double ks = g.kappa * hcs * inv2pi;
+      const double t0 = ks * (v0 * (bx + (double)a0 / (L - 1)) + v1 * (by + (double)a1 / (L - 1)) + v2 * bz);
+      const double dt = ks * v2 / (L - 1);
+#pragma unroll
+      for (int l = 0; l < L; ++l) cfma(acc[l], out[l], expi_turns<R>(t0 + dt * l));
+    }
+  }
+  if (on) {
+    C2<R>* dst = Lx + (int64_t)ce * L3 + p;
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+      const C2<R> cur = dst[L2 * l];
+      dst[L2 * l] = {cur.x + acc[l].x, cur.y + acc[l].y};
+    }
   }
 }
 
@@ -678,7 +944,7 @@ __global__ __launch_bounds__(64) void k_m2l_slice(int64_t ntgt, const int32_t* _
 // interacts with it, so one source load feeds several targets.  All branches
 // depend only on the run records (uniform), accumulators sit at fixed
 // register indices.  Every load of a batch is issued before the first wait.
-template <typename R, int L, int NSL, bool SYM>
+template <typename R, int L, int NSL, bool SYM, bool OFF = false>
 __global__ __launch_bounds__(64) void k_m2l_runs(int64_t ngrp, const int32_t* __restrict__ grp_tfirst,
                                                  const int32_t* __restrict__ grp_tcount,
                                                  const int32_t* __restrict__ run_begin, const int32_t* __restrict__ runs,
@@ -726,11 +992,21 @@ __global__ __launch_bounds__(64) void k_m2l_runs(int64_t ngrp, const int32_t* __
     C2x2<R> mv[U], dv[U][G];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      mv[u] = *reinterpret_cast<const C2x2<R>*>(Mt + (int64_t)rec[u][0] * P3R + fl);
+      if constexpr (OFF) {
+        // run records hold offsets in 16-byte pairs: one add per address
+        mv[u] = reinterpret_cast<const C2x2<R>*>(Mt)[rec[u][0] + (fl >> 1)];
 #pragma unroll
-      for (int t = 0; t < G; ++t) {
-        if (rec[u][1 + t] < 0) continue;
-        dv[u][t] = spectrum_pair<SYM>(S, rec[u][1 + t], P3R, s0, pt, lane, fl);
+        for (int t = 0; t < G; ++t) {
+          if (rec[u][1 + t] < 0) continue;
+          dv[u][t] = reinterpret_cast<const C2x2<R>*>(S)[rec[u][1 + t] + (fl >> 1)];
+        }
+      } else {
+        mv[u] = *reinterpret_cast<const C2x2<R>*>(Mt + (int64_t)rec[u][0] * P3R + fl);
+#pragma unroll
+        for (int t = 0; t < G; ++t) {
+          if (rec[u][1 + t] < 0) continue;
+          dv[u][t] = spectrum_pair<SYM>(S, rec[u][1 + t], P3R, s0, pt, lane, fl);
+        }
       }
     }
 #pragma unroll
@@ -1521,8 +1797,13 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
   for (int l = (int)P.m2m.size() - 1; l >= 0; --l) {
     const LevelTable& t = P.m2m[l];
     if (t.n == 0) continue;
-    DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2m<R, LL>), dim3((unsigned)t.n), dim3(round64(LL * LL * LL)), 0, s,
-                                          t.n, t.a, t.b, t.oct, TY, g, M));
+    if (W.pencil_updown) {
+      DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2m_p<R, LL>), dim3((unsigned)t.npair), dim3(64), 0, s, t.npair,
+                                            t.pair, t.a, t.b, t.oct, TY, g, M));
+    } else {
+      DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2m<R, LL>), dim3((unsigned)t.n), dim3(round64(LL * LL * LL)), 0,
+                                            s, t.n, t.a, t.b, t.oct, TY, g, M));
+    }
   }
   tm.end();
 
@@ -1591,6 +1872,11 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
                                              dim3(xcd_grid(m2l_slices(LL) * ng)), dim3(64), 0, s, ng,
                                              P.grp_tfirst + gb, P.grp_tcount + gb, P.grp_run_begin + gb, P.runs,
                                              P.perm, (const C2<R>*)Mt, S, Lt));
+      } else if (P.runs_off) {
+        DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_runs<R, LL, m2l_slices(LL), false, true>),
+                                             dim3(xcd_grid(m2l_slices(LL) * ng)), dim3(64), 0, s, ng,
+                                             P.grp_tfirst + gb, P.grp_tcount + gb, P.grp_run_begin + gb,
+                                             P.runs_off, P.perm, (const C2<R>*)Mt, S, Lt));
       } else {
         DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_runs<R, LL, m2l_slices(LL), false>),
                                              dim3(xcd_grid(m2l_slices(LL) * ng)), dim3(64), 0, s, ng,
@@ -1627,8 +1913,13 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
   for (size_t l = 0; l < P.l2l.size(); ++l) {
     const LevelTable& t = P.l2l[l];
     if (t.n == 0) continue;
-    DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_l2l<R, LL>), dim3((unsigned)t.n), dim3(round64(LL * LL * LL)), 0, s,
-                                          t.n, t.a, t.b, t.c, t.oct, TX, g, Lx));
+    if (W.pencil_updown) {
+      DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_l2l_p<R, LL>), dim3((unsigned)t.npair), dim3(64), 0, s, t.npair,
+                                            t.pair, t.a, t.b, t.c, t.oct, TX, g, Lx));
+    } else {
+      DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_l2l<R, LL>), dim3((unsigned)t.n), dim3(round64(LL * LL * LL)), 0,
+                                            s, t.n, t.a, t.b, t.c, t.oct, TX, g, Lx));
+    }
   }
   tm.end();
 

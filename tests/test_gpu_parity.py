@@ -92,14 +92,20 @@ def test_c128_matches_oracle(geom, n, kappa, kw):
     ref = F.apply(q)
     assert plan.stats()["m2l_pairs"] > 0
     assert_close(p, ref, 1e-11, rel(p, ref))
-    # per-pass: multipole and local node values of every expansion
+    # per-pass: multipole and local node values of every expansion, with the
+    # pencil M2M/L2L kernels (default) and the node-per-thread ones
     ex_o = F.expansions(0)
-    for kind, key in ((0, "M"), (1, "L")):
-        ex = ws.expansions(0, kind)
-        np.testing.assert_array_equal(ex["cell"], ex_o["cell"])
-        np.testing.assert_array_equal(ex["dir"], ex_o["dir"])
-        scale = np.abs(ex_o[key]).max()
-        assert np.abs(ex["values"] - ex_o[key]).max() <= 1e-11 * scale, key
+    qt = torch.as_tensor(q, device="cuda").to(plan.cdtype)
+    for updown in (1, 0):
+        ws.set_tuning(overlap=2, p2p_waves_per_cu=2, m2l_variant=2, dense_levels=0, updown_variant=updown)
+        p2 = ws.matvec(qt).cpu().numpy()
+        assert_close(p2, ref, 1e-11, ("updown", updown))
+        for kind, key in ((0, "M"), (1, "L")):
+            ex = ws.expansions(0, kind)
+            np.testing.assert_array_equal(ex["cell"], ex_o["cell"])
+            np.testing.assert_array_equal(ex["dir"], ex_o["dir"])
+            scale = np.abs(ex_o[key]).max()
+            assert np.abs(ex["values"] - ex_o[key]).max() <= 1e-11 * scale, (key, updown)
 
 
 @pytest.mark.parametrize("geom,n,kappa,kw", FMM_CASES[:3])
