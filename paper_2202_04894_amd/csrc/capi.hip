@@ -312,18 +312,6 @@ defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int
     P.grp_tcount = upload(P, H.grp_tcount);
     P.grp_run_begin = upload(P, H.grp_run_begin);
     P.runs = upload(P, H.runs);
-    if (!P.sym && !H.runs.empty()) {
-      const int64_t half = fourier_row(P.L) / 2;
-      const int64_t n_rows = (int64_t)H.m2f_exp.size();
-      if ((n_rows + 1) * half < ((int64_t)1 << 31) && ((int64_t)H.offsets.size() + 1) * half < ((int64_t)1 << 31)) {
-        std::vector<int32_t> ro(H.runs.size());
-        for (size_t i = 0; i < H.runs.size(); ++i) {
-          const int32_t v = H.runs[i];
-          ro[i] = v < 0 ? v : (int32_t)((i % 9 == 0 ? (int64_t)v : (int64_t)(v >> 6)) * half);
-        }
-        P.runs_off = upload(P, ro);
-      }
-    }
     P.n_grp = (int64_t)H.grp_tfirst.size();
     P.lvl_grp.assign(H.lvl_grp.begin(), H.lvl_grp.end());
     P.lvl_m2f.assign(H.lvl_m2f.begin(), H.lvl_m2f.end());

@@ -79,10 +79,6 @@ struct DevPlan {
   int64_t n_m2l_tgt = 0, n_m2l = 0;
   std::vector<int64_t> m2l_level_tgt;  // target range per level (host copy)
   int32_t *grp_tfirst = nullptr, *grp_tcount = nullptr, *grp_run_begin = nullptr, *runs = nullptr;
-  // runs with element offsets instead of indices (per-offset spectra only): the
-  // source's row and each target's spectrum as offsets in 16-byte pairs, so
-  // the kernel adds instead of multiplying; null when an offset would not fit
-  int32_t* runs_off = nullptr;
   int64_t n_grp = 0;
   std::vector<int64_t> lvl_grp, lvl_m2f;  // per level: group range, Fourier-row range
   // dense M2L (per level; K tables only where they fit, see dense_ok)

@@ -944,7 +944,7 @@ __global__ __launch_bounds__(64) void k_m2l_slice(int64_t ntgt, const int32_t* _
 // interacts with it, so one source load feeds several targets.  All branches
 // depend only on the run records (uniform), accumulators sit at fixed
 // register indices.  Every load of a batch is issued before the first wait.
-template <typename R, int L, int NSL, bool SYM, bool OFF = false>
+template <typename R, int L, int NSL, bool SYM>
 __global__ __launch_bounds__(64) void k_m2l_runs(int64_t ngrp, const int32_t* __restrict__ grp_tfirst,
                                                  const int32_t* __restrict__ grp_tcount,
                                                  const int32_t* __restrict__ run_begin, const int32_t* __restrict__ runs,
@@ -992,21 +992,11 @@ __global__ __launch_bounds__(64) void k_m2l_runs(int64_t ngrp, const int32_t* __
     C2x2<R> mv[U], dv[U][G];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if constexpr (OFF) {
-        // run records hold offsets in 16-byte pairs: one add per address
-        mv[u] = reinterpret_cast<const C2x2<R>*>(Mt)[rec[u][0] + (fl >> 1)];
+      mv[u] = *reinterpret_cast<const C2x2<R>*>(Mt + (int64_t)rec[u][0] * P3R + fl);
 #pragma unroll
-        for (int t = 0; t < G; ++t) {
-          if (rec[u][1 + t] < 0) continue;
-          dv[u][t] = reinterpret_cast<const C2x2<R>*>(S)[rec[u][1 + t] + (fl >> 1)];
-        }
-      } else {
-        mv[u] = *reinterpret_cast<const C2x2<R>*>(Mt + (int64_t)rec[u][0] * P3R + fl);
-#pragma unroll
-        for (int t = 0; t < G; ++t) {
-          if (rec[u][1 + t] < 0) continue;
-          dv[u][t] = spectrum_pair<SYM>(S, rec[u][1 + t], P3R, s0, pt, lane, fl);
-        }
+      for (int t = 0; t < G; ++t) {
+        if (rec[u][1 + t] < 0) continue;
+        dv[u][t] = spectrum_pair<SYM>(S, rec[u][1 + t], P3R, s0, pt, lane, fl);
       }
     }
 #pragma unroll
@@ -1872,11 +1862,6 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
                                              dim3(xcd_grid(m2l_slices(LL) * ng)), dim3(64), 0, s, ng,
                                              P.grp_tfirst + gb, P.grp_tcount + gb, P.grp_run_begin + gb, P.runs,
                                              P.perm, (const C2<R>*)Mt, S, Lt));
-      } else if (P.runs_off) {
-        DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_runs<R, LL, m2l_slices(LL), false, true>),
-                                             dim3(xcd_grid(m2l_slices(LL) * ng)), dim3(64), 0, s, ng,
-                                             P.grp_tfirst + gb, P.grp_tcount + gb, P.grp_run_begin + gb,
-                                             P.runs_off, P.perm, (const C2<R>*)Mt, S, Lt));
       } else {
         DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_runs<R, LL, m2l_slices(LL), false>),
                                              dim3(xcd_grid(m2l_slices(LL) * ng)), dim3(64), 0, s, ng,
