@@ -236,9 +236,11 @@ defmm_status defmm_workspace_set_timing(defmm_workspace* ws, int32_t enable);
                     merged by source (default);
    dense_levels     bit l set: level l runs the dense MFMA M2L (only levels whose
                     dense matrices the plan built: DEFMM_M2L_AUTO or _DENSE);
-   updown_variant   M2M and L2L kernels: 1 = one wave per pair of expansions of
-                    a cell, pencils in registers (default); 0 = one workgroup
-                    per expansion, one node per thread;
+   updown_variant   P2M, M2M and L2L kernels: 1 = P2M one workgroup per leaf
+                    (weights once for all its expansions), M2M/L2L one wave per
+                    pair of expansions of a cell with pencils in registers
+                    (default); 0 = one workgroup per expansion, one node per
+                    thread;
    ms               median matvec time measured by defmm_workspace_autotune. */
 typedef struct {
   int32_t overlap;

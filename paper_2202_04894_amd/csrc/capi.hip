@@ -282,6 +282,15 @@ defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int
     else upload_tree(P, P.ty, H.ty_own);
     P.p2m_exp = upload(P, H.p2m_exp);
     P.n_p2m = (int64_t)H.p2m_exp.size();
+    {
+      std::vector<int32_t> lv;
+      for (int32_t e : H.p2m_exp) {
+        const int32_t c = H.ty->exp_cell[e];
+        if (lv.empty() || lv.back() != c) lv.push_back(c);
+      }
+      P.p2m_leaf = upload(P, lv);
+      P.n_p2m_leaf = (int64_t)lv.size();
+    }
     P.m2m.resize(H.m2m_par.size());
     for (size_t l = 0; l < H.m2m_par.size(); ++l) {
       P.m2m[l].n = (int64_t)H.m2m_par[l].size();
@@ -307,6 +316,21 @@ defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int
       P.m2l_pair = upload(P, pr);
     }
     P.n_m2l_tgt = (int64_t)H.m2l_tgt.size();
+    {
+      std::vector<uint8_t> fl((size_t)std::max<int64_t>(H.tx.nexp(), 1), 0);
+      for (int32_t e : H.m2l_tgt) fl[e] = 1;
+      P.has_m2l = upload(P, fl);
+      // local expansions no M2L and no L2L writes (cells marked only as M2L
+      // sources, with no father expansion feeding them): cleared every matvec
+      std::vector<uint8_t> fed(fl.begin(), fl.end());
+      for (const auto& v : H.l2l_ch)
+        for (int32_t e : v) fed[e] = 1;
+      std::vector<int32_t> z;
+      for (int64_t e = 0; e < H.tx.nexp(); ++e)
+        if (!fed[e]) z.push_back((int32_t)e);
+      P.zero_exp = upload(P, z);
+      P.n_zero_exp = (int64_t)z.size();
+    }
     P.m2l_level_tgt.assign(H.m2l_level_tgt.begin(), H.m2l_level_tgt.end());
     P.grp_tfirst = upload(P, H.grp_tfirst);
     P.grp_tcount = upload(P, H.grp_tcount);
@@ -976,7 +1000,8 @@ defmm_status defmm_workspace_pass_work(const defmm_workspace* ws, double* bytes,
   double cs = (double)csize(P);
   double L = P.L, Pp = 2 * P.L - 1, L3 = L * L * L, P3 = Pp * Pp * Pp;
   double b[kNumPasses] = {0}, f[kNumPasses] = {0};
-  b[kPassSetup] = (double)P.ny * (2 * cs + 4) + cs * ((double)H.tx.nexp() * L3 + (double)P.nx);
+  b[kPassSetup] = (double)P.ny * (2 * cs + 4) +
+                  cs * ((W.pencil_updown ? (double)P.n_zero_exp : (double)H.tx.nexp()) * L3 + (double)P.nx);
   double npts = 0;
   for (int32_t e : H.p2m_exp) npts += H.ty->count[H.ty->exp_cell[e]];
   b[kPassP2M] = npts * (24 + cs) + (double)P.n_p2m * cs * L3;

@@ -71,6 +71,11 @@ struct DevPlan {
   // tables
   int32_t* p2m_exp = nullptr;
   int64_t n_p2m = 0;
+  int32_t* p2m_leaf = nullptr;  // source leaves holding expansions (P2M per leaf)
+  uint8_t* has_m2l = nullptr;   // per local expansion: 1 if it is an M2L target
+  int32_t* zero_exp = nullptr;  // local expansions written by neither M2L nor L2L
+  int64_t n_zero_exp = 0;
+  int64_t n_p2m_leaf = 0;
   std::vector<LevelTable> m2m;  // a = parent exps, b = 8 child exps per parent, oct = 8 per parent
   int32_t* m2f_exp = nullptr;
   int64_t n_m2f = 0;
@@ -123,7 +128,7 @@ struct Workspace {
   int overlap = 2;  // 0: in sequence; 1: near field forked after the gather; 2: forked after M2F
   int p2p_waves = 2;     // persistent near-field workgroups (one wave) per CU when overlapped
   int m2l_variant = 2;   // 0: fused per target, 1: sliced per target, 2: sliced per group of 8 (source runs)
-  int pencil_updown = 1;  // M2M and L2L: 1 = pencil kernels (a wave per expansion pair), 0 = a workgroup per expansion
+  int pencil_updown = 1;  // P2M, M2M and L2L: 1 = per leaf / pencil kernels (default), 0 = a workgroup per expansion
   std::vector<char> dense_level;  // per level: use the dense MFMA M2L
   void* slots = nullptr;          // dense M2L per-pair results, dense_slots_max x L^3
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;

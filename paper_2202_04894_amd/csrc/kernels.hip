@@ -98,6 +98,22 @@ __device__ __forceinline__ C2<float> expi<float>(double a) {
   return {__builtin_amdgcn_cosf(f), __builtin_amdgcn_sinf(f)};
 }
 
+// exp(i 2 pi t) from FP64 turns t, reduced in FP64 (the phases of P2M, M2M
+// and L2L, whose arguments are formed in turns).
+template <typename R>
+__device__ __forceinline__ C2<R> expi_turns(double t);
+template <>
+__device__ __forceinline__ C2<float> expi_turns<float>(double t) {
+  const float f = (float)(t - rint(t));
+  return {__builtin_amdgcn_cosf(f), __builtin_amdgcn_sinf(f)};
+}
+template <>
+__device__ __forceinline__ C2<double> expi_turns<double>(double t) {
+  double s, c;
+  sincos_turns(t, s, c);
+  return {c, s};
+}
+
 // 1 / prod_{j != m} (m - j) for the L equispaced nodes: the constant factor
 // of the Lagrange basis polynomial of node m (computed in FP64 at compile time).
 template <int L>
@@ -198,6 +214,13 @@ template <typename R>
 __global__ void k_zero(int64_t n, C2<R>* __restrict__ a) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) a[i] = {(R)0, (R)0};
+}
+
+// Clears rows of `len` values: row rows[i] of a, for i < n.
+template <typename R>
+__global__ void k_zero_rows(int64_t n, int len, const int32_t* __restrict__ rows, C2<R>* __restrict__ a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n * len) a[(int64_t)rows[i / len] * len + i % len] = {(R)0, (R)0};
 }
 
 // ------------------------------------------------------------------ spectra
@@ -318,6 +341,75 @@ __global__ __launch_bounds__(round64(L* L* L)) void k_p2m(int64_t n, const int32
   }
 }
 
+// P2M per leaf: the workgroup of a source leaf computes, for a chunk of up to
+// PT points, the weights S_r(y) once (one per node and point, held in
+// registers) and then serves every expansion u of the leaf:
+// M^u(y_r) = exp(ik<y_r - a, u>) sum_y S_r(y) [exp(-ik<y - a, u>) q(y)].
+template <typename R, int L>
+__global__ __launch_bounds__(round64(L* L* L)) void k_p2m_leaf(int64_t n, const int32_t* __restrict__ leaf,
+                                                              TreeView T, Geo g, const C2<R>* __restrict__ qs,
+                                                              C2<R>* __restrict__ M) {
+  constexpr int L3 = L * L * L, PT = sizeof(R) == 4 ? 64 : 32;
+  constexpr double inv2pi = 0.15915494309189533577;
+  __shared__ R w[PT][3][L];
+  __shared__ double dd[PT][3];
+  __shared__ C2<R> qv[PT];
+  __shared__ C2<R> qq[PT];
+  const int64_t item = blockIdx.x;
+  if (item >= n) return;
+  const int c = leaf[item];
+  const double h = ldexp(g.D, -T.level[c]);
+  const double ax = g.ox + h * T.ijk[3 * c], ay = g.oy + h * T.ijk[3 * c + 1], az = g.oz + h * T.ijk[3 * c + 2];
+  const int first = T.first[c], cnt = T.count[c];
+  const int e0 = T.exp_begin[c], e1 = T.exp_begin[c + 1];
+  const int tid = threadIdx.x;
+  const int tn = tid < L3 ? tid : L3 - 1;  // padding threads read a valid node
+  const int rx = tn % L, ry = (tn / L) % L, rz = tn / (L * L);
+  const int nch = (cnt + PT - 1) / PT;
+  R W[PT];
+  int m = 0;
+  auto load_chunk = [&](int ch) {
+    __syncthreads();
+    const int j = ch * PT + tid;
+    if (tid < PT && j < cnt) {
+      const int64_t pi = first + j;
+      const double d0 = T.soa[pi] - ax, d1 = T.soa[T.n + pi] - ay, d2 = T.soa[2 * T.n + pi] - az;
+      lagrange<R, L>((R)(d0 / h), w[tid][0]);
+      lagrange<R, L>((R)(d1 / h), w[tid][1]);
+      lagrange<R, L>((R)(d2 / h), w[tid][2]);
+      dd[tid][0] = d0;
+      dd[tid][1] = d1;
+      dd[tid][2] = d2;
+      qv[tid] = qs[pi];
+    }
+    __syncthreads();
+    m = min(PT, cnt - ch * PT);
+#pragma unroll
+    for (int k = 0; k < PT; ++k) W[k] = k < m ? w[k][0][rx] * w[k][1][ry] * w[k][2][rz] : (R)0;
+  };
+  if (nch == 1) load_chunk(0);
+  for (int e = e0; e < e1; ++e) {
+    const double ux = T.exp_u[3 * e], uy = T.exp_u[3 * e + 1], uz = T.exp_u[3 * e + 2];
+    const double ku = g.kappa * inv2pi;
+    C2<R> acc = {(R)0, (R)0};
+    for (int ch = 0; ch < nch; ++ch) {
+      if (nch > 1) load_chunk(ch);
+      // entries past the chunk's points are zero: the sum below runs over all PT
+      if (tid < PT)
+        qq[tid] = tid < m ? cmul(qv[tid], expi_turns<R>(-ku * (ux * dd[tid][0] + uy * dd[tid][1] + uz * dd[tid][2])))
+                          : C2<R>{(R)0, (R)0};
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < PT; ++k) cfma_r(acc, qq[k], W[k]);
+      __syncthreads();
+    }
+    if (tid < L3) {
+      const double t = g.kappa * h / (double)(L - 1) * inv2pi * (ux * rx + uy * ry + uz * rz);
+      M[(int64_t)e * L3 + tid] = cmul(acc, expi_turns<R>(t));
+    }
+  }
+}
+
 // Interpolation matrices between a cell and its sons (Sec. 5.2, tensorised
 // M2M/L2L): A[b][l][r] = l_l((b + r/(L-1))/2), b = son half along an axis.
 template <typename R, int L>
@@ -375,21 +467,6 @@ template <typename R, int L, bool TR>
 __device__ __forceinline__ void son_mode_b(int b, const C2<R> (&in)[L], C2<R> (&out)[L]) {
   if (b) son_mode<R, L, 1, TR>(in, out);
   else son_mode<R, L, 0, TR>(in, out);
-}
-
-// exp(i 2 pi t) from FP64 turns t, reduced in FP64 (the phases of M2M/L2L).
-template <typename R>
-__device__ __forceinline__ C2<R> expi_turns(double t);
-template <>
-__device__ __forceinline__ C2<float> expi_turns<float>(double t) {
-  const float f = (float)(t - rint(t));
-  return {__builtin_amdgcn_cosf(f), __builtin_amdgcn_sinf(f)};
-}
-template <>
-__device__ __forceinline__ C2<double> expi_turns<double>(double t) {
-  double s, c;
-  sincos_turns(t, s, c);
-  return {c, s};
 }
 
 // Expansions (of one cell) per wave in the pencil kernels: two when a half
@@ -499,7 +576,8 @@ template <typename R, int L>
 __global__ __launch_bounds__(64) void k_l2l_p(int64_t npair, const int32_t* __restrict__ pairs,
                                               const int32_t* __restrict__ ch, const int32_t* __restrict__ begin,
                                               const int32_t* __restrict__ par, const int8_t* __restrict__ oct,
-                                              TreeView T, Geo g, C2<R>* __restrict__ Lx) {
+                                              const uint8_t* __restrict__ has_m2l, TreeView T, Geo g,
+                                              C2<R>* __restrict__ Lx) {
   constexpr int L2 = L * L, L3 = L2 * L, EPW = pencil_epw<L>(), HW = 64 / EPW;
   __shared__ C2<R> st[EPW][L3];
   const int64_t w = blockIdx.x;
@@ -571,10 +649,13 @@ __global__ __launch_bounds__(64) void k_l2l_p(int64_t npair, const int32_t* __re
     }
   }
   if (on) {
+    // added to what M2L wrote (an M2L target), else the son's only contribution:
+    // the local expansions are not cleared before the matvec
     C2<R>* dst = Lx + (int64_t)ce * L3 + p;
+    const bool add = has_m2l[ce] != 0;
 #pragma unroll
     for (int l = 0; l < L; ++l) {
-      const C2<R> cur = dst[L2 * l];
+      const C2<R> cur = add ? dst[L2 * l] : C2<R>{(R)0, (R)0};
       dst[L2 * l] = {cur.x + acc[l].x, cur.y + acc[l].y};
     }
   }
@@ -1732,8 +1813,14 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
   if (P.ny > 0)
     hipLaunchKernelGGL((k_gather<R>), dim3(blocks_for(P.ny, 256)), dim3(256), 0, s, P.ny, P.ty.perm,
                        (const C2<R>*)q, qs);
-  if (P.tx.nexp > 0)
+  // a local expansion is written by its M2L (an M2L target), by L2L, or by
+  // neither (cleared here); the node-per-thread L2L adds to what is there, so
+  // it needs every one cleared first
+  if (P.tx.nexp > 0 && !W.pencil_updown)
     hipLaunchKernelGGL((k_zero<R>), dim3(blocks_for(P.tx.nexp * L3, 256)), dim3(256), 0, s, P.tx.nexp * L3, Lx);
+  else if (P.n_zero_exp > 0)
+    hipLaunchKernelGGL((k_zero_rows<R>), dim3(blocks_for(P.n_zero_exp * L3, 256)), dim3(256), 0, s, P.n_zero_exp,
+                       L3, P.zero_exp, Lx);
   tm.end();
 
   // Near field on the workspace's side stream, concurrently with the far
@@ -1778,9 +1865,14 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
   }
 
   tm.begin(kPassP2M);
-  if (P.n_p2m > 0)
+  if (P.n_p2m_leaf > 0 && W.pencil_updown) {
+    DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_p2m_leaf<R, LL>), dim3((unsigned)P.n_p2m_leaf),
+                                          dim3(round64(LL * LL * LL)), 0, s, P.n_p2m_leaf, P.p2m_leaf, TY, g,
+                                          (const C2<R>*)qs, M));
+  } else if (P.n_p2m > 0) {
     DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_p2m<R, LL>), dim3((unsigned)P.n_p2m), dim3(round64(LL * LL * LL)), 0,
                                           s, P.n_p2m, P.p2m_exp, TY, g, (const C2<R>*)qs, M));
+  }
   tm.end();
 
   tm.begin(kPassM2M);
@@ -1900,7 +1992,7 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
     if (t.n == 0) continue;
     if (W.pencil_updown) {
       DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_l2l_p<R, LL>), dim3((unsigned)t.npair), dim3(64), 0, s, t.npair,
-                                            t.pair, t.a, t.b, t.c, t.oct, TX, g, Lx));
+                                            t.pair, t.a, t.b, t.c, t.oct, P.has_m2l, TX, g, Lx));
     } else {
       DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_l2l<R, LL>), dim3((unsigned)t.n), dim3(round64(LL * LL * LL)), 0,
                                             s, t.n, t.a, t.b, t.c, t.oct, TX, g, Lx));
