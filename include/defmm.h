@@ -241,6 +241,8 @@ defmm_status defmm_workspace_set_timing(defmm_workspace* ws, int32_t enable);
                     pair of expansions of a cell with pencils in registers
                     (default); 0 = one workgroup per expansion, one node per
                     thread;
+   fourier_items    expansions per workgroup of M2F and F2L: 1, 2 or 4 (capped
+                    to what fits the LDS), 0 = as many as fit 64 KB;
    ms               median matvec time measured by defmm_workspace_autotune. */
 typedef struct {
   int32_t overlap;
@@ -248,13 +250,14 @@ typedef struct {
   int32_t m2l_variant;
   uint32_t dense_levels;
   int32_t updown_variant;
+  int32_t fourier_items;
   double ms;
 } defmm_tuning;
 
 /* Times the candidate execution choices on this workspace (each: one warm-up
    and `reps` matvecs of q into p on hip_stream; host-synchronous) and keeps
    the fastest: the Fourier-path M2L variant in sequence first, then the M2M/L2L
-   kernels, then, level by level, the dense MFMA M2L where the plan holds its
+   kernels, then the M2F/F2L expansions per workgroup, then, level by level, the dense MFMA M2L where the plan holds its
    matrices, then the
    overlapped near field forked early or after M2F, with 2, 3, 4 and 6 waves
    per CU.  q and p as in defmm_matvec; p holds a valid result afterwards.

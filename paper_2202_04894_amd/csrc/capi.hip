@@ -817,6 +817,7 @@ defmm_status defmm_workspace_get_tuning(const defmm_workspace* ws, defmm_tuning*
   out->p2p_waves_per_cu = ws->impl.p2p_waves;
   out->m2l_variant = ws->impl.m2l_variant;
   out->updown_variant = ws->impl.pencil_updown;
+  out->fourier_items = ws->impl.fourier_items;
   out->dense_levels = 0;
   for (size_t l = 0; l < ws->impl.dense_level.size() && l < 32; ++l)
     if (ws->impl.dense_level[l]) out->dense_levels |= 1u << l;
@@ -827,13 +828,15 @@ defmm_status defmm_workspace_get_tuning(const defmm_workspace* ws, defmm_tuning*
 defmm_status defmm_workspace_set_tuning(defmm_workspace* ws, const defmm_tuning* t) {
   if (!ws || !t) return fail(DEFMM_ERR_INVALID_ARG, "NULL argument");
   if (t->p2p_waves_per_cu < 1 || t->p2p_waves_per_cu > 32 || t->m2l_variant < 0 || t->m2l_variant > 2 ||
-      t->overlap < 0 || t->overlap > 2 || t->updown_variant < 0 || t->updown_variant > 1)
+      t->overlap < 0 || t->overlap > 2 || t->updown_variant < 0 || t->updown_variant > 1 ||
+      !(t->fourier_items == 0 || t->fourier_items == 1 || t->fourier_items == 2 || t->fourier_items == 4))
     return fail(DEFMM_ERR_INVALID_ARG, "tuning out of range");
   ws->impl.graph_stale = true;
   ws->impl.overlap = t->overlap;
   ws->impl.p2p_waves = t->p2p_waves_per_cu;
   ws->impl.m2l_variant = t->m2l_variant;
   ws->impl.pencil_updown = t->updown_variant;
+  ws->impl.fourier_items = t->fourier_items;
   const DevPlan& P = *ws->impl.plan;
   for (size_t l = 0; l < ws->impl.dense_level.size(); ++l)
     ws->impl.dense_level[l] = (l < 32 && (t->dense_levels >> l) & 1u && P.dense_ok[l]) ? 1 : 0;
@@ -860,6 +863,7 @@ defmm_status defmm_workspace_autotune(defmm_plan* plan, defmm_workspace* ws, con
     W.p2p_waves = t.p2p_waves_per_cu;
     W.m2l_variant = t.m2l_variant;
     W.pencil_updown = t.updown_variant;
+    W.fourier_items = t.fourier_items;
     for (size_t l = 0; l < W.dense_level.size(); ++l)
       W.dense_level[l] = (l < 32 && (t.dense_levels >> l) & 1u && P.dense_ok[l]) ? 1 : 0;
   };
@@ -882,25 +886,33 @@ defmm_status defmm_workspace_autotune(defmm_plan* plan, defmm_workspace* ws, con
     }
     return e;
   };
-  defmm_tuning best{0, 8, 2, 0u, 1, 1e30};
+  defmm_tuning best{0, 8, 2, 0u, 1, 0, 1e30};
   hipError_t err = hipSuccess;
   // M2L variant, timed with every pass in sequence
   for (int var : {2, 1}) {
-    defmm_tuning t{0, 8, var, 0u, 1, 0.0};
+    defmm_tuning t{0, 8, var, 0u, 1, 0, 0.0};
     err = measure(t, &t.ms);
     if (err != hipSuccess) break;
     if (t.ms < best.ms) best = t;
   }
   // M2M/L2L kernels
   if (err == hipSuccess) {
-    defmm_tuning t{0, 8, best.m2l_variant, 0u, 0, 0.0};
+    defmm_tuning t{0, 8, best.m2l_variant, 0u, 0, 0, 0.0};
+    err = measure(t, &t.ms);
+    if (err == hipSuccess && t.ms < best.ms) best = t;
+  }
+  // M2F/F2L expansions per workgroup
+  for (int gi : {1, 2, 4}) {
+    if (err != hipSuccess) break;
+    defmm_tuning t{0, 8, best.m2l_variant, 0u, best.updown_variant, gi, 0.0};
     err = measure(t, &t.ms);
     if (err == hipSuccess && t.ms < best.ms) best = t;
   }
   // per level: dense MFMA M2L instead of the Fourier path where it is faster
   for (size_t l = 0; l < P.dense_ok.size() && l < 32 && err == hipSuccess; ++l) {
     if (!P.dense_ok[l]) continue;
-    defmm_tuning t{0, 8, best.m2l_variant, best.dense_levels | (1u << l), best.updown_variant, 0.0};
+    defmm_tuning t{0, 8, best.m2l_variant, best.dense_levels | (1u << l), best.updown_variant, best.fourier_items,
+                   0.0};
     err = measure(t, &t.ms);
     if (err != hipSuccess) break;
     if (t.ms < best.ms) best = t;
@@ -910,7 +922,7 @@ defmm_status defmm_workspace_autotune(defmm_plan* plan, defmm_workspace* ws, con
   for (int ov : {1, 2})
     for (int w : {2, 3, 4, 6}) {
       if (err != hipSuccess) break;
-      defmm_tuning t{ov, w, best.m2l_variant, best.dense_levels, best.updown_variant, 0.0};
+      defmm_tuning t{ov, w, best.m2l_variant, best.dense_levels, best.updown_variant, best.fourier_items, 0.0};
       err = measure(t, &t.ms);
       if (err != hipSuccess) break;
       if (t.ms < best.ms) best = t;

@@ -128,6 +128,7 @@ struct Workspace {
   int overlap = 2;  // 0: in sequence; 1: near field forked after the gather; 2: forked after M2F
   int p2p_waves = 2;     // persistent near-field workgroups (one wave) per CU when overlapped
   int m2l_variant = 2;   // 0: fused per target, 1: sliced per target, 2: sliced per group of 8 (source runs)
+  int fourier_items = 0;  // M2F/F2L expansions per workgroup: 1, 2 or 4 (capped to what fits LDS), 0 = default
   int pencil_updown = 1;  // P2M, M2M and L2L: 1 = per leaf / pencil kernels (default), 0 = a workgroup per expansion
   std::vector<char> dense_level;  // per level: use the dense MFMA M2L
   void* slots = nullptr;          // dense M2L per-pair results, dense_slots_max x L^3

@@ -777,13 +777,27 @@ __device__ __forceinline__ void dft_pencil(const C2<R> (&in)[NI], C2<R> (&out)[N
   }
 }
 
-// Expansions per workgroup of M2F and F2L: as many as fit 64 KB of LDS, at
-// most 4 (each needs a P^3 grid and a P^2 L stage).
+// Expansions per workgroup of M2F and F2L (each needs a P^3 grid and a P^2 L
+// stage in LDS): the default is as many as fit 64 KB, at most 4; a workspace
+// may ask for 1, 2 or 4, capped at what fits 96 KB.
+template <typename R, int L>
+constexpr int fourier_item_bytes() {
+  constexpr int P = 2 * L - 1;
+  return (P * P * P + P * P * L) * (int)sizeof(C2<R>);
+}
 template <typename R, int L>
 constexpr int fourier_items() {
-  constexpr int P = 2 * L - 1;
-  constexpr int per = (P * P * P + P * P * L) * (int)sizeof(C2<R>);
+  constexpr int per = fourier_item_bytes<R, L>();
   return per * 4 <= 65536 ? 4 : per * 2 <= 65536 ? 2 : 1;
+}
+template <typename R, int L>
+constexpr int fourier_items_max() {
+  constexpr int per = fourier_item_bytes<R, L>();
+  return per * 4 <= 98304 ? 4 : per * 2 <= 98304 ? 2 : 1;
+}
+template <typename R, int L, int G>
+constexpr int fourier_items_capped() {
+  return G < fourier_items_max<R, L>() ? G : fourier_items_max<R, L>();
 }
 
 // M~ = DFT_P(pad(M)) by pencils: pass x (L^2 pencils of L values -> P), pass y
@@ -791,11 +805,11 @@ constexpr int fourier_items() {
 // per workgroup; the P^3 grid is then written in the order of the Fourier
 // layout (freq), padding as zeros.  Stage layouts keep consecutive threads on
 // consecutive LDS words.
-template <typename R, int L>
+template <typename R, int L, int G>
 __global__ __launch_bounds__(256) void k_m2f(int64_t n, const int32_t* __restrict__ src,
                                              const int32_t* __restrict__ freq, const C2<R>* __restrict__ M,
                                              C2<R>* __restrict__ Mt) {
-  constexpr int P = 2 * L - 1, P3 = P * P * P, L2 = L * L, L3 = L2 * L, G = fourier_items<R, L>(), NT = 256;
+  constexpr int P = 2 * L - 1, P3 = P * P * P, L2 = L * L, L3 = L2 * L, NT = 256;
   constexpr int RW = fourier_row(L);
   constexpr int SA = P3 > P * L2 ? P3 : P * L2;  // x-stage, then the full grid
   constexpr int SB = P * P * L;                   // y-stage
@@ -1102,11 +1116,11 @@ __global__ __launch_bounds__(64) void k_m2l_runs(int64_t ngrp, const int32_t* __
 // pencils as in M2F: pass z (P^2 pencils of P values -> L), pass y (P L
 // pencils), pass x (L^2 pencils, each writing its L contiguous node values).
 // Targets in XCD-aware order, G per workgroup.
-template <typename R, int L>
+template <typename R, int L, int G>
 __global__ __launch_bounds__(256) void k_f2l(int64_t ntgt, const int32_t* __restrict__ tgt,
                                              const int32_t* __restrict__ freq, const C2<R>* __restrict__ Lt,
                                              C2<R>* __restrict__ Lx) {
-  constexpr int P = 2 * L - 1, P3 = P * P * P, L2 = L * L, L3 = L2 * L, G = fourier_items<R, L>(), NT = 256;
+  constexpr int P = 2 * L - 1, P3 = P * P * P, L2 = L * L, L3 = L2 * L, NT = 256;
   constexpr int RW = fourier_row(L);
   constexpr int SA = P3 > P * L2 ? P3 : P * L2;  // the full grid, then the y-stage output
   constexpr int SB = P * P * L;                   // z-stage output
@@ -1794,6 +1808,34 @@ inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) /
 
 }  // namespace
 
+// Dispatch on the M2F/F2L expansions per workgroup (1, 2 or 4; 0 = the
+// default), GG a compile-time constant capped at what fits LDS.
+#define DEFMM_G_SWITCH(gv, RR, LLL, ...)                                            \
+  do {                                                                              \
+    switch (gv) {                                                                   \
+      case 1: {                                                                     \
+        constexpr int GG = 1;                                                       \
+        __VA_ARGS__;                                                                \
+        break;                                                                      \
+      }                                                                             \
+      case 2: {                                                                     \
+        constexpr int GG = fourier_items_capped<RR, LLL, 2>();                      \
+        __VA_ARGS__;                                                                \
+        break;                                                                      \
+      }                                                                             \
+      case 4: {                                                                     \
+        constexpr int GG = fourier_items_capped<RR, LLL, 4>();                      \
+        __VA_ARGS__;                                                                \
+        break;                                                                      \
+      }                                                                             \
+      default: {                                                                    \
+        constexpr int GG = fourier_items<RR, LLL>();                                \
+        __VA_ARGS__;                                                                \
+        break;                                                                      \
+      }                                                                             \
+    }                                                                               \
+  } while (0)
+
 template <typename R>
 static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, hipStream_t s) {
   const int L = P.L;
@@ -1913,9 +1955,9 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
   for (int k = 0; k < nfr; ++k) {
     const int64_t rb = P.lvl_m2f[fr_lo[k]], nr = P.lvl_m2f[fr_hi[k]] - rb;
     if (nr == 0) continue;
-    DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2f<R, LL>), dim3((unsigned)((nr + fourier_items<R, LL>() - 1) / fourier_items<R, LL>())),
-                                         dim3(256), 0, s, nr, P.m2f_exp + rb,
-                                         P.freq, (const C2<R>*)M, Mt + rb * P3R));
+    DEFMM_L_SWITCH(L, DEFMM_G_SWITCH(W.fourier_items, R, LL, hipLaunchKernelGGL((k_m2f<R, LL, GG>),
+                                     dim3((unsigned)((nr + GG - 1) / GG)), dim3(256), 0, s, nr, P.m2f_exp + rb,
+                                     P.freq, (const C2<R>*)M, Mt + rb * P3R)));
   }
   tm.end();
   if (fork_late) {
@@ -1980,9 +2022,9 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
     for (int k = 0; k < nfr; ++k) {
       const int64_t tb = P.m2l_level_tgt[fr_lo[k]], nt = P.m2l_level_tgt[fr_hi[k]] - tb;
       if (nt == 0) continue;
-      DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_f2l<R, LL>), dim3(xcd_grid((nt + fourier_items<R, LL>() - 1) / fourier_items<R, LL>())),
-                                           dim3(256), 0, s, nt, P.m2l_tgt + tb,
-                                           P.freq, (const C2<R>*)(Lt + tb * P3R), Lx));
+      DEFMM_L_SWITCH(L, DEFMM_G_SWITCH(W.fourier_items, R, LL, hipLaunchKernelGGL((k_f2l<R, LL, GG>),
+                                       dim3(xcd_grid((nt + GG - 1) / GG)), dim3(256), 0, s, nt, P.m2l_tgt + tb,
+                                       P.freq, (const C2<R>*)(Lt + tb * P3R), Lx)));
     }
   tm.end();
 

@@ -35,7 +35,8 @@ class _Params(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("overlap", ctypes.c_int32), ("p2p_waves_per_cu", ctypes.c_int32), ("m2l_variant", ctypes.c_int32),
-                ("dense_levels", ctypes.c_uint32), ("updown_variant", ctypes.c_int32), ("ms", ctypes.c_double)]
+                ("dense_levels", ctypes.c_uint32), ("updown_variant", ctypes.c_int32),
+                ("fourier_items", ctypes.c_int32), ("ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -380,8 +381,9 @@ class Workspace:
         _check(lib().defmm_workspace_get_tuning(self.h, ctypes.byref(t)))
         return t.as_dict()
 
-    def set_tuning(self, overlap=2, p2p_waves_per_cu=2, m2l_variant=2, dense_levels=0, updown_variant=1, **_):
-        t = Tuning(overlap, p2p_waves_per_cu, m2l_variant, dense_levels, updown_variant, 0.0)
+    def set_tuning(self, overlap=2, p2p_waves_per_cu=2, m2l_variant=2, dense_levels=0, updown_variant=1,
+                   fourier_items=0, **_):
+        t = Tuning(overlap, p2p_waves_per_cu, m2l_variant, dense_levels, updown_variant, fourier_items, 0.0)
         _check(lib().defmm_workspace_set_tuning(self.h, ctypes.byref(t)))
 
     def set_overlap(self, on: bool):

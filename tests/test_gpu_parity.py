@@ -96,6 +96,9 @@ def test_c128_matches_oracle(geom, n, kappa, kw):
     # pencil M2M/L2L kernels (default) and the node-per-thread ones
     ex_o = F.expansions(0)
     qt = torch.as_tensor(q, device="cuda").to(plan.cdtype)
+    for fi in (1, 2, 4):  # M2F/F2L expansions per workgroup
+        ws.set_tuning(overlap=2, p2p_waves_per_cu=2, m2l_variant=2, dense_levels=0, fourier_items=fi)
+        assert_close(ws.matvec(qt).cpu().numpy(), ref, 1e-11, ("fourier_items", fi))
     for updown in (1, 0):
         ws.set_tuning(overlap=2, p2p_waves_per_cu=2, m2l_variant=2, dense_levels=0, updown_variant=updown)
         p2 = ws.matvec(qt).cpu().numpy()
