@@ -540,7 +540,7 @@ def main():
         torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, X, wl.kappa, knobs, perm, args.cpu_sample or min(wl.n, 65536),
+        out["cpu_baseline"] = cpu_baseline(wl, X, wl.kappa, knobs, perm, args.cpu_sample or min(wl.n, 32768),
                                            args.cpu_single or 0)
     else:
         out["cpu_baseline"] = None
