@@ -334,8 +334,33 @@ defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int
     P.m2l_level_tgt.assign(H.m2l_level_tgt.begin(), H.m2l_level_tgt.end());
     P.grp_tfirst = upload(P, H.grp_tfirst);
     P.grp_tcount = upload(P, H.grp_tcount);
-    P.grp_run_begin = upload(P, H.grp_run_begin);
-    P.runs = upload(P, H.runs);
+    {
+      // device layout of the runs: kRunWords words per record, each group padded
+      // to a multiple of the kernel's batch with target-less records (the
+      // group's first source again), one batch of them more at the end
+      const int U = P.precision == 0 ? m2l_run_batch<double>() : m2l_run_batch<float>();
+      const int64_t ng = (int64_t)H.grp_tfirst.size();
+      std::vector<int32_t> rb(ng + 1, 0), rr;
+      rr.reserve((H.runs.size() / 9 + ng + U) * kRunWords);
+      auto push = [&](const int32_t* rec) {
+        for (int q = 0; q < kRunWords; ++q) rr.push_back(q < 9 ? rec[q] : 0);
+      };
+      int32_t dummy[9];
+      for (int64_t gi = 0; gi < ng; ++gi) {
+        rb[gi] = (int32_t)(rr.size() / kRunWords);
+        const int64_t a = H.grp_run_begin[gi], e = H.grp_run_begin[gi + 1];
+        for (int64_t k = a; k < e; ++k) push(&H.runs[9 * k]);
+        dummy[0] = e > a ? H.runs[9 * a] : 0;
+        for (int q = 1; q < 9; ++q) dummy[q] = -1;
+        for (int64_t k = e - a; k % U != 0; ++k) push(dummy);
+      }
+      rb[ng] = (int32_t)(rr.size() / kRunWords);
+      dummy[0] = 0;
+      for (int k = 0; k < U; ++k) push(dummy);
+      if ((int64_t)rr.size() / kRunWords > INT32_MAX) throw std::runtime_error("M2L run table too large");
+      P.grp_run_begin = upload(P, rb);
+      P.runs = upload(P, rr);
+    }
     P.n_grp = (int64_t)H.grp_tfirst.size();
     P.lvl_grp.assign(H.lvl_grp.begin(), H.lvl_grp.end());
     P.lvl_m2f.assign(H.lvl_m2f.begin(), H.lvl_m2f.end());

@@ -44,6 +44,14 @@ struct DevTree {
   double* exp_u = nullptr;       // 3 per expansion
 };
 
+// Words per M2L source-run record in the device table (one 64-byte scalar load).
+constexpr int kRunWords = 16;
+
+// Runs per batch of the source-run M2L kernel: two when a run's loads are
+// 16 bytes per lane (complex64 pairs), one for complex128.
+template <typename R>
+constexpr int m2l_run_batch() { return sizeof(R) == 4 ? 2 : 1; }
+
 struct LevelTable {  // per-level operator table on the device
   int64_t n = 0;     // number of work items
   int32_t* a = nullptr;
@@ -83,6 +91,10 @@ struct DevPlan {
   int32_t* m2l_pair = nullptr;  // per entry: (Fourier-domain multipole row, spectrum id)
   int64_t n_m2l_tgt = 0, n_m2l = 0;
   std::vector<int64_t> m2l_level_tgt;  // target range per level (host copy)
+  // M2L source runs as the kernel reads them: kRunWords words per record
+  // (source row, 8 spectrum codes or -1, padding), each group's runs padded to a
+  // multiple of m2l_run_batch with target-less records, one batch more at the
+  // end; grp_run_begin counts records of this padded table
   int32_t *grp_tfirst = nullptr, *grp_tcount = nullptr, *grp_run_begin = nullptr, *runs = nullptr;
   int64_t n_grp = 0;
   std::vector<int64_t> lvl_grp, lvl_m2f;  // per level: group range, Fourier-row range

@@ -469,6 +469,19 @@ __device__ __forceinline__ void son_mode_b(int b, const C2<R> (&in)[L], C2<R> (&
   else son_mode<R, L, 0, TR>(in, out);
 }
 
+// exp(i 2 pi (t0 + l dt)) for l < N: both turns reduced in FP64, the run by
+// repeated rotation (N - 1 complex products in R), as along one pencil of a
+// cell's nodes.
+template <typename R, int N>
+__device__ __forceinline__ void phase_run(double t0, double dt, C2<R> (&ph)[N]) {
+  ph[0] = expi_turns<R>(t0);
+  if constexpr (N > 1) {
+    const C2<R> st = expi_turns<R>(dt);
+#pragma unroll
+    for (int l = 1; l < N; ++l) ph[l] = cmul(ph[l - 1], st);
+  }
+}
+
 // Expansions (of one cell) per wave in the pencil kernels: two when a half
 // wave holds the L^2 pencils of one expansion.
 template <int L>
@@ -481,6 +494,8 @@ constexpr int pencil_epw() { return L * L <= 32 ? 2 : 1; }
 // a_s, v>) with FP64 arguments, three mode products with the son matrices
 // (x-, y- and z-pencils, exchanged through LDS), summed over sons in
 // z-pencils (l_x, l_y); then the father-node phases exp(i kappa <y_l - a_s, v>).
+// Along a pencil the phases are one FP64-reduced turn and its step rotated
+// L - 1 times (phase_run).
 // Both expansions of a wave share the father cell, so its sons and their
 // octants (which choose the matrices) are the same for every lane.
 template <typename R, int L>
@@ -522,9 +537,10 @@ __global__ __launch_bounds__(64) void k_m2m_p(int64_t npair, const int32_t* __re
       // x-pencil (r_y, r_z) = (a0, a1) of the son, times exp(-i kappa <y'_r - a_s, v>)
       const C2<R>* src = M + (int64_t)ce * L3 + p * L;
       const double t0 = -ks * (v0 * bx + v1 * (by + (double)a0 / (L - 1)) + v2 * (bz + (double)a1 / (L - 1)));
-      const double dt = -ks * v0 / (L - 1);
+      C2<R> ph[L];
+      phase_run<R, L>(t0, -ks * v0 / (L - 1), ph);
 #pragma unroll
-      for (int r = 0; r < L; ++r) in[r] = cmul(src[r], expi_turns<R>(t0 + dt * r));
+      for (int r = 0; r < L; ++r) in[r] = cmul(src[r], ph[r]);
     }
     son_mode_b<R, L, false>(bx, in, out);
     __syncthreads();
@@ -558,10 +574,11 @@ __global__ __launch_bounds__(64) void k_m2m_p(int64_t npair, const int32_t* __re
   if (on) {
     // father-node phases exp(i kappa h <l, v> / (L-1)), z-pencil (l_x, l_y)
     const double kf = g.kappa * h / (L - 1) * inv2pi;
-    const double t0 = kf * (v0 * a0 + v1 * a1), dt = kf * v2;
+    C2<R> ph[L];
+    phase_run<R, L>(kf * (v0 * a0 + v1 * a1), kf * v2, ph);
     C2<R>* dst = M + (int64_t)pe * L3 + p;
 #pragma unroll
-    for (int l = 0; l < L; ++l) dst[L2 * l] = cmul(acc[l], expi_turns<R>(t0 + dt * l));
+    for (int l = 0; l < L; ++l) dst[L2 * l] = cmul(acc[l], ph[l]);
   }
 }
 
@@ -614,9 +631,10 @@ __global__ __launch_bounds__(64) void k_l2l_p(int64_t npair, const int32_t* __re
       // x-pencil (k_y, k_z) of the father, times exp(-i kappa hp <k, v> / (L-1))
       const C2<R>* src = Lx + (int64_t)pe * L3 + p * L;
       const double kf = g.kappa * hp / (L - 1) * inv2pi;
-      const double t0 = -kf * (v1 * a0 + v2 * a1), dt = -kf * v0;
+      C2<R> ph[L];
+      phase_run<R, L>(-kf * (v1 * a0 + v2 * a1), -kf * v0, ph);
 #pragma unroll
-      for (int r = 0; r < L; ++r) in[r] = cmul(src[r], expi_turns<R>(t0 + dt * r));
+      for (int r = 0; r < L; ++r) in[r] = cmul(src[r], ph[r]);
     }
     son_mode_b<R, L, true>(bx, in, out);
     __syncthreads();
@@ -642,10 +660,11 @@ __global__ __launch_bounds__(64) void k_l2l_p(int64_t npair, const int32_t* __re
       son_mode_b<R, L, true>(bz, in, out);
       // son-node phases exp(i kappa hc <b + h / (L-1), v>), z-pencil (h_x, h_y)
       const double ks = g.kappa * hcs * inv2pi;
-      const double t0 = ks * (v0 * (bx + (double)a0 / (L - 1)) + v1 * (by + (double)a1 / (L - 1)) + v2 * bz);
-      const double dt = ks * v2 / (L - 1);
+      C2<R> ph[L];
+      phase_run<R, L>(ks * (v0 * (bx + (double)a0 / (L - 1)) + v1 * (by + (double)a1 / (L - 1)) + v2 * bz),
+                      ks * v2 / (L - 1), ph);
 #pragma unroll
-      for (int l = 0; l < L; ++l) cfma(acc[l], out[l], expi_turns<R>(t0 + dt * l));
+      for (int l = 0; l < L; ++l) cfma(acc[l], out[l], ph[l]);
     }
   }
   if (on) {
@@ -1036,18 +1055,22 @@ __global__ __launch_bounds__(64) void k_m2l_slice(int64_t ntgt, const int32_t* _
 // group of <= 8 targets sharing level and direction, and one frequency slice
 // (slice-major per XCD as in k_m2l_slice).  Each run loads the source's
 // Fourier-domain multipole once and the spectrum of every group target that
-// interacts with it, so one source load feeds several targets.  All branches
-// depend only on the run records (uniform), accumulators sit at fixed
-// register indices.  Every load of a batch is issued before the first wait.
+// interacts with it, so one source load feeds several targets.  Run records
+// are 16 words (source row, the 8 targets' spectrum codes or -1, padding), one
+// scalar load each; a group's runs are padded to a multiple of the batch, and
+// the table carries one batch more at its end, so no record load is
+// conditional.  All branches depend only on the run records (uniform),
+// accumulators sit at fixed register indices, and every load of a batch is
+// issued before the first wait.
 template <typename R, int L, int NSL, bool SYM>
 __global__ __launch_bounds__(64) void k_m2l_runs(int64_t ngrp, const int32_t* __restrict__ grp_tfirst,
                                                  const int32_t* __restrict__ grp_tcount,
                                                  const int32_t* __restrict__ run_begin, const int32_t* __restrict__ runs,
                                                  const uint8_t* __restrict__ perm, const C2<R>* __restrict__ Mt,
                                                  const C2<R>* __restrict__ S, C2<R>* __restrict__ Lt) {
-  constexpr int P3R = fourier_row(L), SL = P3R / NSL, NP = SL / 2, G = 8;
+  constexpr int P3R = fourier_row(L), SL = P3R / NSL, NP = SL / 2, G = 8, RS = kRunWords;
   static_assert(SL % 2 == 0 && NP <= 64, "a slice holds at most 64 frequency pairs");
-  constexpr int U = sizeof(R) == 4 ? 2 : 1;  // runs per batch
+  constexpr int U = m2l_run_batch<R>();  // runs per batch
   __shared__ uint32_t ptab[48 * 16];
   int slice;
   int64_t g;
@@ -1062,13 +1085,13 @@ __global__ __launch_bounds__(64) void k_m2l_runs(int64_t ngrp, const int32_t* __
   for (int t = 0; t < G; ++t) acc[t] = C2x2<R>{{(R)0, (R)0}, {(R)0, (R)0}};
   int r = run_begin[g];
   const int re = run_begin[g + 1];
-  // the next batch's run records are fetched (scalar loads) while this
-  // batch's vector loads are in flight
+  // the next batch's records are fetched (scalar loads) while this batch's
+  // vector loads are in flight
   int nx[U][9];
 #pragma unroll
   for (int u = 0; u < U; ++u)
 #pragma unroll
-    for (int q = 0; q < 9; ++q) nx[u][q] = (r + u < re) ? runs[(int64_t)(r + u) * 9 + q] : (q == 0 ? -2 : -1);
+    for (int q = 0; q < 9; ++q) nx[u][q] = runs[(int64_t)(r + u) * RS + q];
   for (; r < re; r += U) {
     int rec[U][9];
 #pragma unroll
@@ -1078,12 +1101,7 @@ __global__ __launch_bounds__(64) void k_m2l_runs(int64_t ngrp, const int32_t* __
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int q = 0; q < 9; ++q) nx[u][q] = (r + U + u < re) ? runs[(int64_t)(r + U + u) * 9 + q] : (q == 0 ? -2 : -1);
-    // past the group's last run: re-read run 0's source row, no targets, so
-    // every batch issues its source loads unconditionally
-#pragma unroll
-    for (int u = 1; u < U; ++u)
-      if (rec[u][0] < 0) rec[u][0] = rec[0][0];
+      for (int q = 0; q < 9; ++q) nx[u][q] = runs[(int64_t)(r + U + u) * RS + q];
     C2x2<R> mv[U], dv[U][G];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
