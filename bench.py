@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--c64-only", action="store_true", help="skip the complex128 path and the checks")
     ap.add_argument("--check", action="store_true",
                     help="with --c64-only: also the error against the FP64 direct sum on sampled targets")
+    ap.add_argument("--force", default="",
+                    help="with --c64-only: tuning fields set after the autotuner, e.g. m2l_variant=3,fourier_items=4")
     ap.add_argument("--compress", action="store_true",
                     help="one spectrum per symmetry class of offsets (DEFMM_COMPRESS_SPECTRA)")
     ap.add_argument("--serving", action="store_true",
@@ -415,6 +417,9 @@ def main():
     charges64 = [torch.as_tensor(wl.charges(k, np.complex64), device="cuda") for k in range(nq)]
     # execution choices (M2L variant, dense levels, near-field overlap) tuned on this workspace
     tuned = ws64.autotune(charges64[0], reps=3)
+    if args.force:
+        tuned.update({k: int(v) for k, v in (kv.split("=") for kv in args.force.split(","))})
+        ws64.set_tuning(**tuned)
     # production mode: tuned choices, no per-pass events
     ms64, lat64, _ = time_matvecs(ws64, charges64, nsteps, args.warmup, timing=False)
     # the same matvecs in sequence with per-pass HIP events: each kernel's own duration
