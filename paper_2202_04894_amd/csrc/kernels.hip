@@ -27,6 +27,12 @@ struct C2 {
   R x, y;
 };
 
+// two adjacent complex entries, moved as one 16- or 32-byte access
+template <typename R>
+struct alignas(2 * sizeof(C2<R>)) C2x2 {
+  C2<R> a, b;
+};
+
 template <typename R>
 __device__ __forceinline__ C2<R> cmul(C2<R> a, C2<R> b) {
   return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
@@ -874,14 +880,18 @@ __global__ __launch_bounds__(256) void k_m2f(int64_t n, const int32_t* __restric
     for (int k = 0; k < P; ++k) A[g][xy + P * P * k] = out[k];
   }
   __syncthreads();
-  // the G rows are contiguous
-  constexpr int NV = (G * RW + NT - 1) / NT;
+  // the G rows are contiguous; stored two entries (16 or 32 bytes) per thread
+  constexpr int RW2 = RW / 2, NV = (G * RW2 + NT - 1) / NT;
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     const int w = tid + k * NT;
-    if (w < ng * RW) {
-      const int f = fq[w % RW];
-      Mt[i0 * RW + w] = f >= 0 ? A[w / RW][f] : C2<R>{(R)0, (R)0};
+    if (w < ng * RW2) {
+      const int g = w / RW2, p = 2 * (w % RW2);
+      const int f0 = fq[p], f1 = fq[p + 1];
+      C2x2<R> v;
+      v.a = f0 >= 0 ? A[g][f0] : C2<R>{(R)0, (R)0};
+      v.b = f1 >= 0 ? A[g][f1] : C2<R>{(R)0, (R)0};
+      reinterpret_cast<C2x2<R>*>(Mt + i0 * RW)[w] = v;
     }
   }
 }
@@ -972,11 +982,6 @@ __global__ __launch_bounds__(256) void k_m2l(int64_t ntgt, const int32_t* __rest
 // are dealt to the XCDs in contiguous slice-major shares (slice_item), so
 // each XCD's L2 holds one slice of the spectra and Fourier-domain multipoles
 // its targets read.  One wave per workgroup.
-template <typename R>
-struct alignas(2 * sizeof(C2<R>)) C2x2 {
-  C2<R> a, b;
-};
-
 // Loads one slice's pair permutations (48 symmetries x 64 lanes, bytes) into
 // LDS; the workgroup is one wave.
 __device__ __forceinline__ const uint8_t* load_slice_perm(const uint8_t* __restrict__ perm, int slice,
@@ -1151,22 +1156,25 @@ __global__ __launch_bounds__(256) void k_f2l(int64_t ntgt, const int32_t* __rest
   const int64_t i0 = ch * G;
   const int ng = (int)min((int64_t)G, ntgt - i0);
   const int tid = threadIdx.x;
-  // the G rows are contiguous: every load is issued before the first LDS write
-  constexpr int NV = (G * RW + NT - 1) / NT;
-  C2<R> v[NV];
+  // the G rows are contiguous: every load (two entries per thread) is issued
+  // before the first LDS write
+  constexpr int RW2 = RW / 2, NV = (G * RW2 + NT - 1) / NT;
+  C2x2<R> v[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     const int w = tid + k * NT;
-    v[k] = w < ng * RW ? Lt[i0 * RW + w] : C2<R>{(R)0, (R)0};
+    if (w < ng * RW2) v[k] = reinterpret_cast<const C2x2<R>*>(Lt + i0 * RW)[w];
   }
   for (int p = tid; p < RW; p += NT) fq[p] = freq[p];
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     const int w = tid + k * NT;
-    if (w < ng * RW) {
-      const int f = fq[w % RW];
-      if (f >= 0) A[w / RW][f] = v[k];
+    if (w < ng * RW2) {
+      const int g = w / RW2, p = 2 * (w % RW2);
+      const int f0 = fq[p], f1 = fq[p + 1];
+      if (f0 >= 0) A[g][f0] = v[k].a;
+      if (f1 >= 0) A[g][f1] = v[k].b;
     }
   }
   __syncthreads();
