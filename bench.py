@@ -31,6 +31,9 @@ HBM_PASSES = {"setup", "p2m", "m2m", "m2f", "m2l", "f2l", "l2l", "p2p_reduce", "
 MFMA_PASSES = {"m2l_dense"}
 KERNEL_OF_PASS = {"m2l": "k_m2l_runs", "f2l": "k_f2l", "p2p": "k_p2p", "m2f": "k_m2f", "m2m": "k_m2m",
                   "l2l": "k_l2l", "p2m": "k_p2m", "l2p": "k_l2p", "m2l_dense": "k_m2l_dense"}
+# the kernels of the pencil upward/downward passes (one thread per pencil of
+# interpolation values, P2M once per leaf)
+PENCIL_KERNEL_OF_PASS = {"m2m": "k_m2m_p", "l2l": "k_l2l_p", "p2m": "k_p2m_leaf"}
 
 
 def parse():
@@ -347,6 +350,8 @@ def roofline_of(names, per_step, bytes_, flops, tuned, wl_name, knobs):
     kern = KERNEL_OF_PASS.get(dname, dname)
     if dname == "m2l" and tuned["m2l_variant"] == 1:
         kern = "k_m2l_slice"
+    if tuned.get("updown_variant", 0) == 1 and dname in PENCIL_KERNEL_OF_PASS:
+        kern = PENCIL_KERNEL_OF_PASS[dname]
     if dname in MFMA_PASSES:
         ach = flops[dom] / t_launch / 1e12
         roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
