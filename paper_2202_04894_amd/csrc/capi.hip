@@ -337,11 +337,12 @@ defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int
     {
       // device layout of the runs: kRunWords words per record, each group padded
       // to a multiple of the kernel's batch with target-less records (the
-      // group's first source again), one batch of them more at the end
+      // group's first source again), two batches of them more at the end (the
+      // kernel reads records one batch and source words two batches ahead)
       const int U = P.precision == 0 ? m2l_run_batch<double>() : m2l_run_batch<float>();
       const int64_t ng = (int64_t)H.grp_tfirst.size();
       std::vector<int32_t> rb(ng + 1, 0), rr;
-      rr.reserve((H.runs.size() / 9 + ng + U) * kRunWords);
+      rr.reserve((H.runs.size() / 9 + ng + 2 * U) * kRunWords);
       auto push = [&](const int32_t* rec) {
         for (int q = 0; q < kRunWords; ++q) rr.push_back(q < 9 ? rec[q] : 0);
       };
@@ -356,7 +357,7 @@ defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int
       }
       rb[ng] = (int32_t)(rr.size() / kRunWords);
       dummy[0] = 0;
-      for (int k = 0; k < U; ++k) push(dummy);
+      for (int k = 0; k < 2 * U; ++k) push(dummy);
       if ((int64_t)rr.size() / kRunWords > INT32_MAX) throw std::runtime_error("M2L run table too large");
       P.grp_run_begin = upload(P, rb);
       P.runs = upload(P, rr);

@@ -93,8 +93,8 @@ struct DevPlan {
   std::vector<int64_t> m2l_level_tgt;  // target range per level (host copy)
   // M2L source runs as the kernel reads them: kRunWords words per record
   // (source row, 8 spectrum codes or -1, padding), each group's runs padded to a
-  // multiple of m2l_run_batch with target-less records, one batch more at the
-  // end; grp_run_begin counts records of this padded table
+  // multiple of m2l_run_batch with target-less records, two batches more at
+  // the end; grp_run_begin counts records of this padded table
   int32_t *grp_tfirst = nullptr, *grp_tcount = nullptr, *grp_run_begin = nullptr, *runs = nullptr;
   int64_t n_grp = 0;
   std::vector<int64_t> lvl_grp, lvl_m2f;  // per level: group range, Fourier-row range

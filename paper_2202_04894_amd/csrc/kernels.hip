@@ -1056,6 +1056,56 @@ __global__ __launch_bounds__(64) void k_m2l_slice(int64_t ntgt, const int32_t* _
   if (ok) *reinterpret_cast<C2x2<R>*>(Lt + i * P3R + fl) = C2x2<R>{acc0, acc1};
 }
 
+// Word 3 of a gfx9 buffer descriptor for raw dword access (32-bit data
+// format, no swizzle).
+constexpr int kBufferWord3 = 0x00020000;
+
+// Two adjacent entries of a row through a buffer descriptor built from the
+// row's (uniform) base: the per-lane byte offset is the only vector operand,
+// so a batch of loads needs no per-lane 64-bit addresses.  `bytes` bounds the
+// offsets (the hardware returns zeros beyond it).
+template <typename R>
+__device__ __forceinline__ C2x2<R> buffer_pair(const void* base, uint32_t bytes, uint32_t lane_bytes) {
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kBufferWord3);
+  if constexpr (sizeof(R) == 4) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)lane_bytes, 0, 0);
+    C2x2<R> out;
+    __builtin_memcpy(&out, &v, sizeof(out));
+    return out;
+  } else {
+    const auto v0 = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)lane_bytes, 0, 0);
+    const auto v1 = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)lane_bytes + 16, 0, 0);
+    C2x2<R> out;
+    __builtin_memcpy(&out.a, &v0, sizeof(out.a));
+    __builtin_memcpy(&out.b, &v1, sizeof(out.b));
+    return out;
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ C2x2<R> row_pair(const C2<R>* __restrict__ A, uint32_t row, uint32_t row_bytes,
+                                            uint32_t lane_bytes) {
+  return buffer_pair<R>(reinterpret_cast<const char*>(A) + (uint64_t)row * row_bytes, row_bytes, lane_bytes);
+}
+
+// spectrum_pair with the same addressing: per-offset spectra read the lane's
+// pair of row e >> 6; compressed spectra the pair the slice's permutation
+// table names, in the canonical spectrum's plain or pair-exchanged row.
+template <bool SYM, typename R>
+__device__ __forceinline__ C2x2<R> spectrum_pair_b(const C2<R>* __restrict__ S, int e, uint32_t row_bytes,
+                                                   uint32_t slice_bytes, const uint8_t* pt, int lane,
+                                                   uint32_t lane_bytes) {
+  if constexpr (SYM) {
+    const int pe = pt[(e & 63) * 64 + lane];
+    const char* base = reinterpret_cast<const char*>(S) + (uint64_t)(uint32_t)(2 * (e >> 6)) * row_bytes;
+    const uint32_t off = (uint32_t)(pe >> 7) * row_bytes + slice_bytes + (uint32_t)(pe & 127) * 2 * sizeof(C2<R>);
+    return buffer_pair<R>(base, 2 * row_bytes, off);
+  } else {
+    return row_pair(S, (uint32_t)(e >> 6), row_bytes, lane_bytes);
+  }
+}
+
 // Hadamard accumulate over source runs.  A workgroup (one wave) handles one
 // group of <= 8 targets sharing level and direction, and one frequency slice
 // (slice-major per XCD as in k_m2l_slice).  Each run loads the source's
@@ -1063,10 +1113,14 @@ __global__ __launch_bounds__(64) void k_m2l_slice(int64_t ntgt, const int32_t* _
 // interacts with it, so one source load feeds several targets.  Run records
 // are 16 words (source row, the 8 targets' spectrum codes or -1, padding), one
 // scalar load each; a group's runs are padded to a multiple of the batch, and
-// the table carries one batch more at its end, so no record load is
-// conditional.  All branches depend only on the run records (uniform),
-// accumulators sit at fixed register indices, and every load of a batch is
-// issued before the first wait.
+// the table carries two batches more at its end, so no record load is
+// conditional.  The source rows are loaded one batch ahead (their source
+// words two batches ahead): a batch waits only for its spectra, which the
+// XCD's L2 mostly holds, while the next batch's source rows, which mostly
+// come from beyond it, are in flight.  The two source-row register sets
+// alternate (the loop is unrolled by two), so no copy waits for a load.
+// All branches depend only on the run records (uniform) and accumulators sit
+// at fixed register indices.
 template <typename R, int L, int NSL, bool SYM>
 __global__ __launch_bounds__(64) void k_m2l_runs(int64_t ngrp, const int32_t* __restrict__ grp_tfirst,
                                                  const int32_t* __restrict__ grp_tcount,
@@ -1076,6 +1130,7 @@ __global__ __launch_bounds__(64) void k_m2l_runs(int64_t ngrp, const int32_t* __
   constexpr int P3R = fourier_row(L), SL = P3R / NSL, NP = SL / 2, G = 8, RS = kRunWords;
   static_assert(SL % 2 == 0 && NP <= 64, "a slice holds at most 64 frequency pairs");
   constexpr int U = m2l_run_batch<R>();  // runs per batch
+  constexpr uint32_t RB = P3R * sizeof(C2<R>);  // row bytes
   __shared__ uint32_t ptab[48 * 16];
   int slice;
   int64_t g;
@@ -1085,47 +1140,65 @@ __global__ __launch_bounds__(64) void k_m2l_runs(int64_t ngrp, const int32_t* __
   const bool ok = lane < NP;
   const int s0 = slice * SL;
   const int fl = ok ? s0 + 2 * lane : s0;
+  const uint32_t lb = (uint32_t)fl * sizeof(C2<R>), sb = (uint32_t)s0 * sizeof(C2<R>);
   C2x2<R> acc[G];
 #pragma unroll
   for (int t = 0; t < G; ++t) acc[t] = C2x2<R>{{(R)0, (R)0}, {(R)0, (R)0}};
   int r = run_begin[g];
   const int re = run_begin[g + 1];
-  // the next batch's records are fetched (scalar loads) while this batch's
-  // vector loads are in flight
-  int nx[U][9];
+  int rec[U][9], src1[U];
+  C2x2<R> mA[U], mB[U];
 #pragma unroll
-  for (int u = 0; u < U; ++u)
+  for (int u = 0; u < U; ++u) {
 #pragma unroll
-    for (int q = 0; q < 9; ++q) nx[u][q] = runs[(int64_t)(r + u) * RS + q];
-  for (; r < re; r += U) {
-    int rec[U][9];
+    for (int q = 0; q < 9; ++q) rec[u][q] = runs[(int64_t)(r + u) * RS + q];
+    src1[u] = runs[(int64_t)(r + U + u) * RS];
+  }
 #pragma unroll
-    for (int u = 0; u < U; ++u)
+  for (int u = 0; u < U; ++u) mA[u] = row_pair(Mt, (uint32_t)rec[u][0], RB, lb);
+  // one batch: records of the next batch and source words of the one after
+  // are fetched, the spectra of this batch and the source rows of the next
+  // are loaded, then this batch is accumulated from mc
+  auto step = [&](const C2x2<R>(&mc)[U], C2x2<R>(&mn)[U]) {
+    int nx[U][9], src2[U];
 #pragma unroll
-      for (int q = 0; q < 9; ++q) rec[u][q] = nx[u][q];
-#pragma unroll
-    for (int u = 0; u < U; ++u)
+    for (int u = 0; u < U; ++u) {
 #pragma unroll
       for (int q = 0; q < 9; ++q) nx[u][q] = runs[(int64_t)(r + U + u) * RS + q];
-    C2x2<R> mv[U], dv[U][G];
+      src2[u] = runs[(int64_t)(r + 2 * U + u) * RS];
+    }
+    C2x2<R> dv[U][G];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      mv[u] = *reinterpret_cast<const C2x2<R>*>(Mt + (int64_t)rec[u][0] * P3R + fl);
+    for (int u = 0; u < U; ++u)
 #pragma unroll
       for (int t = 0; t < G; ++t) {
         if (rec[u][1 + t] < 0) continue;
-        dv[u][t] = spectrum_pair<SYM>(S, rec[u][1 + t], P3R, s0, pt, lane, fl);
+        dv[u][t] = spectrum_pair_b<SYM>(S, rec[u][1 + t], RB, sb, pt, lane, lb);
+      }
+#pragma unroll
+    for (int u = 0; u < U; ++u) mn[u] = row_pair(Mt, (uint32_t)src1[u], RB, lb);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int t = 0; t < G; ++t) {
+        if (rec[u][1 + t] < 0) continue;
+        cfma(acc[t].a, dv[u][t].a, mc[u].a);
+        cfma(acc[t].b, dv[u][t].b, mc[u].b);
       }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
 #pragma unroll
-      for (int t = 0; t < G; ++t) {
-        if (rec[u][1 + t] < 0) continue;
-        cfma(acc[t].a, dv[u][t].a, mv[u].a);
-        cfma(acc[t].b, dv[u][t].b, mv[u].b);
-      }
+      for (int q = 0; q < 9; ++q) rec[u][q] = nx[u][q];
+      src1[u] = src2[u];
     }
+    r += U;
+  };
+  for (;;) {
+    step(mA, mB);
+    if (r >= re) break;
+    step(mB, mA);
+    if (r >= re) break;
   }
   const int64_t tf = grp_tfirst[g];
   const int tc = grp_tcount[g];
