@@ -330,7 +330,9 @@ def run_serving(args):
             "config": {"workload": f"{args.requests} requests, N log-uniform in [1e4, 5e5] on spheres / "
                                    f"cap-weighted ellipsoids from a pool of {args.geometries} geometries, "
                                    "kappa*D in [16, 256], L in {4, 5}, leaf<=64, 20 complex64 matvecs each",
-                       "knobs_by_L": {str(k): v for k, v in S.ACCURATE_KNOBS.items()} if not args.literal
+                       "knobs_by_L": {str(k): {f"kappa*D < {S.HIGH_KD:g}": v,
+                                               f"kappa*D >= {S.HIGH_KD:g}": S.ACCURATE_KNOBS_HIGH_KD[k]}
+                                      for k, v in S.ACCURATE_KNOBS.items()} if not args.literal
                        else {"4": S.LITERAL_KNOBS, "5": S.LITERAL_KNOBS},
                        "slots": args.slots, "budget_GiB": round(budget / 2 ** 30, 1)},
             "full_load": full, "one_at_a_time": one,

@@ -385,13 +385,24 @@ class DeviceExecutor:
         plan.close()
 
 
-# Knob settings (eta, hf_threshold, dir_refine) per interpolation order whose
-# potentials came within 1e-4 of the FP64 direct sum in device and oracle
-# sweeps (L = 5 on 1,048,576 sphere points at kappa*D = 256; L = 4 on 8,192
-# sphere points at kappa*D = 32 with one more direction refinement than that
-# sweep needed, for the higher kappa of the serving mix); the paper-literal
-# setting is (1, 2, 0).
+# Knob settings (eta, hf_threshold, dir_refine) per interpolation order and
+# kappa*D band whose potentials came within 1e-4 of the FP64 direct sum in
+# device and oracle sweeps: L = 5 on 1,048,576 sphere points at kappa*D = 256
+# (8.4e-5 at eta = 0.35; 0.3 keeps a margin for the mix); L = 4 on 8,192
+# sphere points at kappa*D = 32 (4.8e-5 at E0 = 1, run with one refinement
+# more) and, for kappa*D >= 96, on the mix's L = 4 geometries at kappa*D
+# 234-251, where eta = 0.15 left 6.8e-5 to 1.15e-4 and eta = 0.1 gives
+# 2.9e-5 to 4.0e-5.  The paper-literal setting is (1, 2, 0).
 ACCURATE_KNOBS = {4: (0.15, 0.75, 2), 5: (0.3, 0.75, 1)}
+ACCURATE_KNOBS_HIGH_KD = {4: (0.1, 0.75, 2), 5: (0.3, 0.75, 1)}
+HIGH_KD = 96.0
+
+
+def accurate_knobs(L, kappa_d):
+    """The per-request setting within 1e-4 of the direct sum for order L at kappa*D."""
+    return (ACCURATE_KNOBS_HIGH_KD if kappa_d >= HIGH_KD else ACCURATE_KNOBS)[L]
+
+
 LITERAL_KNOBS = (1.0, 2.0, 0)
 
 
@@ -427,7 +438,7 @@ def config_requests(n_requests=256, n_geometries=32, seed=7, n_min=10_000, n_max
         def ch(k, n=n, cseed=cseed):
             return W.charges(n, cseed + k, np.complex64)
 
-        knobs = ACCURATE_KNOBS[L] if accurate else LITERAL_KNOBS
+        knobs = accurate_knobs(L, kD) if accurate else LITERAL_KNOBS
         reqs.append(Request(rid=i, geometry=f"{kind}-{n}-{kD:.3f}-{L}-{knobs}", make_points=mk, n_points=n,
                             kappa=kD / 2.0, order_L=L, ncrit=64, n_matvecs=n_matvecs,
                             charges=ch if host_charges else None, arrival=t, knobs=knobs))
