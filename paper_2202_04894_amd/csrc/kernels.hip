@@ -783,10 +783,81 @@ struct Twiddles {
   }
 };
 
+// y[k] = sum_{a < NIN} x[a] w^{a k} for k < NOUT, w = e^{SIGN 2 pi i / 3}: a
+// length-3 DFT on a prefix of its inputs, for a prefix of its outputs, with
+// w = -1/2 + SIGN i sqrt(3)/2 (two constants instead of a complex product).
+template <typename R, int SIGN, int NIN, int NOUT>
+__device__ __forceinline__ void dft3(const C2<R> (&x)[3], C2<R> (&y)[3]) {
+  static_assert(NIN >= 1 && NIN <= 3 && NOUT >= 1 && NOUT <= 3, "length-3 DFT");
+  constexpr R h = (R)0.5, r3 = (R)(SIGN * 0.86602540378443864676372317075294);
+  if constexpr (NIN == 1) {
+#pragma unroll
+    for (int k = 0; k < NOUT; ++k) y[k] = x[0];
+  } else if constexpr (NIN == 2) {
+    y[0] = {x[0].x + x[1].x, x[0].y + x[1].y};
+    const C2<R> t = {fma(-h, x[1].x, x[0].x), fma(-h, x[1].y, x[0].y)};
+    if constexpr (NOUT > 1) y[1] = {fma(-r3, x[1].y, t.x), fma(r3, x[1].x, t.y)};
+    if constexpr (NOUT > 2) y[2] = {fma(r3, x[1].y, t.x), fma(-r3, x[1].x, t.y)};
+  } else {
+    const C2<R> sm = {x[1].x + x[2].x, x[1].y + x[2].y};
+    y[0] = {x[0].x + sm.x, x[0].y + sm.y};
+    if constexpr (NOUT > 1) {
+      const C2<R> d = {x[1].x - x[2].x, x[1].y - x[2].y};
+      const C2<R> t = {fma(-h, sm.x, x[0].x), fma(-h, sm.y, x[0].y)};
+      y[1] = {fma(-r3, d.y, t.x), fma(r3, d.x, t.y)};
+      if constexpr (NOUT > 2) y[2] = {fma(r3, d.y, t.x), fma(-r3, d.x, t.y)};
+    }
+  }
+}
+
+// The pencil DFT of length 9 as 3 x 3 (Cooley-Tukey): with m = 3a + b and
+// k = k1 + 3 k2, out[k] = sum_b w9^{b k} sum_a in[3a + b] w3^{a k1}, where
+// w9^{b k} = w9^{b k1} w3^{b k2}: three length-3 DFTs over a (on the inputs
+// present), the twiddles w9^{b k1}, then three length-3 DFTs over b (for the
+// outputs asked for).  About 2.3x fewer operations than the direct sums.
+template <typename R, int NI, int NO, int SIGN>
+__device__ __forceinline__ void dft9(const C2<R> (&in)[NI], C2<R> (&out)[NO]) {
+  static_assert(NI >= 3 && NI <= 9 && NO >= 3 && NO <= 9, "length-9 pencil");
+  constexpr Twiddles T(9);
+  C2<R> z[3][3];  // z[b][k1]
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    C2<R> x[3], y[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) x[a] = 3 * a + b < NI ? in[3 * a + b < NI ? 3 * a + b : 0] : C2<R>{(R)0, (R)0};
+    if (b == 0) dft3<R, SIGN, (NI + 2) / 3, 3>(x, y);
+    else if (b == 1) dft3<R, SIGN, (NI + 1) / 3, 3>(x, y);
+    else dft3<R, SIGN, NI / 3, 3>(x, y);
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) {
+      if (b * k1 == 0) {
+        z[b][k1] = y[k1];
+      } else {
+        const R c = (R)T.c[b * k1], sn = (R)(SIGN * T.s[b * k1]);
+        z[b][k1] = {fma(y[k1].x, c, -y[k1].y * sn), fma(y[k1].x, sn, y[k1].y * c)};
+      }
+    }
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < 3; ++k1) {
+    C2<R> x[3] = {z[0][k1], z[1][k1], z[2][k1]}, y[3];
+    if (k1 == 0) dft3<R, SIGN, 3, (NO + 2) / 3>(x, y);
+    else if (k1 == 1) dft3<R, SIGN, 3, (NO + 1) / 3>(x, y);
+    else dft3<R, SIGN, 3, NO / 3>(x, y);
+#pragma unroll
+    for (int k2 = 0; k2 < 3; ++k2)
+      if (k1 + 3 * k2 < NO) out[k1 + 3 * k2 < NO ? k1 + 3 * k2 : 0] = y[k2];
+  }
+}
+
 // out[k] = sum_m in[m] e^{SIGN 2 pi i k m / P} for k < NO, m < NI: one pencil of
-// a separable DFT, twiddles folded in at compile time.
+// a separable DFT, twiddles folded in at compile time (P = 9 factored).
 template <typename R, int P, int NI, int NO, int SIGN>
 __device__ __forceinline__ void dft_pencil(const C2<R> (&in)[NI], C2<R> (&out)[NO]) {
+  if constexpr (P == 9 && NI >= 3 && NO >= 3) {
+    dft9<R, NI, NO, SIGN>(in, out);
+    return;
+  }
   constexpr Twiddles T(P);
 #pragma unroll
   for (int k = 0; k < NO; ++k) {
