@@ -400,13 +400,19 @@ __global__ __launch_bounds__(round64(L* L* L)) void k_p2m_leaf(int64_t n, const 
     C2<R> acc = {(R)0, (R)0};
     for (int ch = 0; ch < nch; ++ch) {
       if (nch > 1) load_chunk(ch);
-      // entries past the chunk's points are zero: the sum below runs over all PT
+      // entries past the chunk's points are zero
       if (tid < PT)
         qq[tid] = tid < m ? cmul(qv[tid], expi_turns<R>(-ku * (ux * dd[tid][0] + uy * dd[tid][1] + uz * dd[tid][2])))
                           : C2<R>{(R)0, (R)0};
       __syncthreads();
+      // the chunk's points in blocks of 8, skipping the empty blocks (m is
+      // uniform; leaves hold 18 points on average)
 #pragma unroll
-      for (int k = 0; k < PT; ++k) cfma_r(acc, qq[k], W[k]);
+      for (int kb = 0; kb < PT; kb += 8) {
+        if (kb >= m) break;
+#pragma unroll
+        for (int k = kb; k < kb + 8; ++k) cfma_r(acc, qq[k], W[k]);
+      }
       __syncthreads();
     }
     if (tid < L3) {
