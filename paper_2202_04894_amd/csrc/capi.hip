@@ -342,17 +342,20 @@ defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int
       const int U = P.precision == 0 ? m2l_run_batch<double>() : m2l_run_batch<float>();
       const int64_t ng = (int64_t)H.grp_tfirst.size();
       std::vector<int32_t> rb(ng + 1, 0), rr;
-      rr.reserve((H.runs.size() / 9 + ng + 2 * U) * kRunWords);
+      constexpr int RQ = 1 + kRunTargets;  // words of a host record
+      static_assert(RQ <= kRunWords, "run record too long");
+      static_assert(kRunTargets == 8, "k_m2l_runs reads 8 target codes per record");
+      rr.reserve((H.runs.size() / RQ + ng + 2 * U) * kRunWords);
       auto push = [&](const int32_t* rec) {
-        for (int q = 0; q < kRunWords; ++q) rr.push_back(q < 9 ? rec[q] : 0);
+        for (int q = 0; q < kRunWords; ++q) rr.push_back(q < RQ ? rec[q] : 0);
       };
-      int32_t dummy[9];
+      int32_t dummy[RQ];
       for (int64_t gi = 0; gi < ng; ++gi) {
         rb[gi] = (int32_t)(rr.size() / kRunWords);
         const int64_t a = H.grp_run_begin[gi], e = H.grp_run_begin[gi + 1];
-        for (int64_t k = a; k < e; ++k) push(&H.runs[9 * k]);
-        dummy[0] = e > a ? H.runs[9 * a] : 0;
-        for (int q = 1; q < 9; ++q) dummy[q] = -1;
+        for (int64_t k = a; k < e; ++k) push(&H.runs[RQ * k]);
+        dummy[0] = e > a ? H.runs[RQ * a] : 0;
+        for (int q = 1; q < RQ; ++q) dummy[q] = -1;
         for (int64_t k = e - a; k % U != 0; ++k) push(dummy);
       }
       rb[ng] = (int32_t)(rr.size() / kRunWords);

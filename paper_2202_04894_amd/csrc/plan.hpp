@@ -15,6 +15,7 @@ constexpr int kP2PBlock = 64;  // target points per P2P block
 constexpr int kP2PChunk = 2048;  // source points per P2P work item (balance)
 constexpr int kL2PChunk = 256;   // target points per L2P work item
 constexpr int kMaxSegPerItem = 64;  // source segments per P2P work item (one wave-wide scan)
+constexpr int kRunTargets = 8;     // targets per M2L group (a run record holds 1 + this many words)
 constexpr double kMaxSpectraBytes = 8.0 * (1ull << 30);  // per-offset spectra beyond this are compressed
 
 // Dense M2L: L^3 padded to a multiple of 16 (the MFMA tile edge).
@@ -129,10 +130,11 @@ struct HostPlan {
   // M2L: target expansions with interactions, CSR of (Fourier row, offset id)
   std::vector<int32_t> m2l_tgt, m2l_begin;  // begin: ntgt + 1
   std::vector<int32_t> m2l_level_tgt;       // per level l: first target of level l (nlevels + 1)
-  // M2L source runs: targets grouped by <= 8 (same level and direction,
-  // consecutive); per group the pairs are merged by source into runs of
-  // 9 int32: Fourier row of the source, then the spectrum code for each of the
-  // group's 8 targets (-1 where that target has no pair with this source).
+  // M2L source runs: targets grouped by <= kRunTargets (same level and
+  // direction, consecutive); per group the pairs are merged by source into runs
+  // of 1 + kRunTargets int32: Fourier row of the source, then the spectrum code
+  // for each of the group's targets (-1 where that target has no pair with
+  // this source).
   std::vector<int32_t> grp_tfirst, grp_tcount, grp_run_begin;  // run CSR: ngrp + 1
   std::vector<int32_t> runs;
   std::vector<int32_t> lvl_grp, lvl_m2f;  // per level: group range, Fourier-row range (nlevels + 1)

@@ -490,7 +490,7 @@ void build_tables(HostPlan& hp) {
     hp.m2l_off[k] = hp.m2l[i].off;
   }
   hp.m2l_begin.push_back((int32_t)nm);
-  // groups of <= 8 targets sharing level and direction, merged by source
+  // groups of <= kRunTargets targets sharing level and direction, merged by source
   {
     int64_t nt = (int64_t)hp.m2l_tgt.size();
     std::vector<int64_t> g0;  // first target of each group
@@ -498,7 +498,7 @@ void build_tables(HostPlan& hp) {
       int32_t c0 = X.exp_cell[hp.m2l_tgt[t0]];
       int lv = X.level[c0], dr = X.exp_dir[hp.m2l_tgt[t0]];
       int64_t t1 = t0 + 1;
-      while (t1 < nt && t1 - t0 < 8 && X.level[X.exp_cell[hp.m2l_tgt[t1]]] == lv &&
+      while (t1 < nt && t1 - t0 < kRunTargets && X.level[X.exp_cell[hp.m2l_tgt[t1]]] == lv &&
              X.exp_dir[hp.m2l_tgt[t1]] == dr)
         ++t1;
       g0.push_back(t0);
@@ -510,25 +510,25 @@ void build_tables(HostPlan& hp) {
     const int64_t nch = std::max<int64_t>(1, std::min<int64_t>(64, ng / 512));
     std::vector<std::vector<int32_t>> chunk_runs(nch), chunk_nrun(nch);
     parallel_chunks(nch, 1, [&](int64_t cb, int64_t ce, int) {
-      std::vector<std::pair<int32_t, int32_t>> ent;  // (source row, tloc * 2^28 + offset)
+      std::vector<std::pair<int32_t, int64_t>> ent;  // (source row, tloc * 2^32 + spectrum code)
       for (int64_t ch = cb; ch < ce; ++ch) {
         for (int64_t g = ng * ch / nch; g < ng * (ch + 1) / nch; ++g) {
           ent.clear();
           for (int64_t t = g0[g]; t < g0[g + 1]; ++t)
             for (int32_t k = hp.m2l_begin[t]; k < hp.m2l_begin[t + 1]; ++k)
-              ent.push_back({hp.m2l_src[k], (int32_t)(((t - g0[g]) << 28) | hp.off_spec[hp.m2l_off[k]])});
+              ent.push_back({hp.m2l_src[k], ((t - g0[g]) << 32) | (int64_t)(uint32_t)hp.off_spec[hp.m2l_off[k]]});
           std::sort(ent.begin(), ent.end());
           int32_t nr = 0;
           for (size_t a = 0; a < ent.size();) {
             size_t b = a;
-            int32_t rec[9];
+            int32_t rec[1 + kRunTargets];
             rec[0] = ent[a].first;
-            for (int q = 1; q < 9; ++q) rec[q] = -1;
+            for (int q = 1; q < 1 + kRunTargets; ++q) rec[q] = -1;
             while (b < ent.size() && ent[b].first == ent[a].first) {
-              rec[1 + (ent[b].second >> 28)] = ent[b].second & ((1 << 28) - 1);
+              rec[1 + (ent[b].second >> 32)] = (int32_t)(ent[b].second & 0xffffffffll);
               ++b;
             }
-            chunk_runs[ch].insert(chunk_runs[ch].end(), rec, rec + 9);
+            chunk_runs[ch].insert(chunk_runs[ch].end(), rec, rec + 1 + kRunTargets);
             ++nr;
             a = b;
           }
