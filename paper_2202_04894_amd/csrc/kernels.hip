@@ -169,6 +169,13 @@ __device__ __forceinline__ int64_t xcd_item(int64_t n) {
 
 static inline unsigned xcd_grid(int64_t n) { return (unsigned)(8 * ((n + 7) / 8)); }
 
+// Persistent M2F grid: 4 workgroups per CU (what the LDS holds at 4
+// expansions per workgroup, and the registers at fewer), a multiple of 8, no
+// more than the chunks need.
+static inline unsigned fourier_grid(int64_t nchunk, int num_cu) {
+  return xcd_grid(std::min<int64_t>(nchunk, (int64_t)num_cu * 4));
+}
+
 // Work item (slice, i) of nsl frequency slices x n items, in slice-major
 // order through xcd_item: each XCD walks a contiguous share of the list, so
 // its L2 holds one slice (two at a share boundary) of the rows its items
@@ -179,6 +186,17 @@ __device__ __forceinline__ bool slice_item(int nsl, int64_t n, int& slice, int64
   slice = (int)(w / n);
   i = w % n;
   return true;
+}
+
+// Persistent XCD-aware walk over n items: with a grid that is a multiple of
+// 8, block b runs on XCD b % 8 and takes items first, first + step, ... < end
+// of that XCD's contiguous share.
+struct XcdWalk {
+  int64_t first, end, step;
+};
+__device__ __forceinline__ XcdWalk xcd_walk(int64_t n) {
+  const int64_t nper = (n + 7) / 8, x = blockIdx.x % 8;
+  return {x * nper + blockIdx.x / 8, min(n, (x + 1) * nper), (int64_t)(gridDim.x / 8)};
 }
 
 struct TreeView {
@@ -904,9 +922,11 @@ constexpr int fourier_items_capped() {
 
 // M~ = DFT_P(pad(M)) by pencils: pass x (L^2 pencils of L values -> P), pass y
 // (P L pencils), pass z (P^2 pencils), one thread per pencil and G expansions
-// per workgroup; the P^3 grid is then written in the order of the Fourier
-// layout (freq), padding as zeros.  Stage layouts keep consecutive threads on
-// consecutive LDS words.
+// per chunk; the P^3 grid is then written in the order of the Fourier layout
+// (freq), padding as zeros.  Stage layouts keep consecutive threads on
+// consecutive LDS words.  Persistent workgroups walk the chunks (xcd_walk);
+// the node values of a thread's next pass-x pencil are loaded while the
+// current chunk goes through passes y and z and the store.
 template <typename R, int L, int G>
 __global__ __launch_bounds__(256) void k_m2f(int64_t n, const int32_t* __restrict__ src,
                                              const int32_t* __restrict__ freq, const C2<R>* __restrict__ M,
@@ -915,61 +935,85 @@ __global__ __launch_bounds__(256) void k_m2f(int64_t n, const int32_t* __restric
   constexpr int RW = fourier_row(L);
   constexpr int SA = P3 > P * L2 ? P3 : P * L2;  // x-stage, then the full grid
   constexpr int SB = P * P * L;                   // y-stage
+  constexpr int NX = (G * L2 + NT - 1) / NT;      // pass-x pencils per thread
   __shared__ C2<R> A[G][SA];
   __shared__ C2<R> B[G][SB];
   __shared__ int32_t fq[RW];
-  const int64_t i0 = (int64_t)blockIdx.x * G;
-  if (i0 >= n) return;
-  const int ng = (int)min((int64_t)G, n - i0);
+  const int64_t nch = (n + G - 1) / G;
+  const XcdWalk wk = xcd_walk(nch);
+  if (wk.first >= wk.end) return;
   const int tid = threadIdx.x;
   for (int p = tid; p < RW; p += NT) fq[p] = freq[p];
-  // pass x: pencil (ry, rz) reads its L contiguous values; A[g][xi * L^2 + ry + L rz]
-  for (int w = tid; w < ng * L2; w += NT) {
-    const int g = w / L2, yz = w % L2;
-    const C2<R>* m = M + (int64_t)src[i0 + g] * L3 + yz * L;
-    C2<R> in[L], out[P];
+  C2<R> in_x[NX][L];
+  auto load_x = [&](int64_t ch) {
+    const int64_t i0 = ch * G;
+    const int ng = (int)min((int64_t)G, n - i0);
 #pragma unroll
-    for (int r = 0; r < L; ++r) in[r] = m[r];
-    dft_pencil<R, P, L, P, -1>(in, out);
+    for (int v = 0; v < NX; ++v) {
+      const int w = tid + v * NT;
+      if (w < ng * L2) {
+        const int g = w / L2, yz = w % L2;
+        const C2<R>* m = M + (int64_t)src[i0 + g] * L3 + yz * L;
 #pragma unroll
-    for (int k = 0; k < P; ++k) A[g][k * L2 + yz] = out[k];
-  }
-  __syncthreads();
-  // pass y: pencil (rz, xi); B[g][rz + L (xi + P yi)]
-  for (int w = tid; w < ng * P * L; w += NT) {
-    const int g = w / (P * L), q = w % (P * L), rz = q % L, xi = q / L;
-    C2<R> in[L], out[P];
-#pragma unroll
-    for (int r = 0; r < L; ++r) in[r] = A[g][xi * L2 + r + L * rz];
-    dft_pencil<R, P, L, P, -1>(in, out);
-#pragma unroll
-    for (int k = 0; k < P; ++k) B[g][rz + L * (xi + P * k)] = out[k];
-  }
-  __syncthreads();
-  // pass z: pencil (xi, yi) = xy; A[g][xy + P^2 zi]
-  for (int w = tid; w < ng * P * P; w += NT) {
-    const int g = w / (P * P), xy = w % (P * P);
-    C2<R> in[L], out[P];
-#pragma unroll
-    for (int r = 0; r < L; ++r) in[r] = B[g][r + L * xy];
-    dft_pencil<R, P, L, P, -1>(in, out);
-#pragma unroll
-    for (int k = 0; k < P; ++k) A[g][xy + P * P * k] = out[k];
-  }
-  __syncthreads();
-  // the G rows are contiguous; stored two entries (16 or 32 bytes) per thread
-  constexpr int RW2 = RW / 2, NV = (G * RW2 + NT - 1) / NT;
-#pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    const int w = tid + k * NT;
-    if (w < ng * RW2) {
-      const int g = w / RW2, p = 2 * (w % RW2);
-      const int f0 = fq[p], f1 = fq[p + 1];
-      C2x2<R> v;
-      v.a = f0 >= 0 ? A[g][f0] : C2<R>{(R)0, (R)0};
-      v.b = f1 >= 0 ? A[g][f1] : C2<R>{(R)0, (R)0};
-      reinterpret_cast<C2x2<R>*>(Mt + i0 * RW)[w] = v;
+        for (int r = 0; r < L; ++r) in_x[v][r] = m[r];
+      }
     }
+  };
+  load_x(wk.first);
+  for (int64_t ch = wk.first; ch < wk.end; ch += wk.step) {
+    const int64_t i0 = ch * G;
+    const int ng = (int)min((int64_t)G, n - i0);
+    // pass x: pencil (ry, rz) of L contiguous values; A[g][xi * L^2 + ry + L rz]
+#pragma unroll
+    for (int v = 0; v < NX; ++v) {
+      const int w = tid + v * NT;
+      if (w < ng * L2) {
+        const int g = w / L2, yz = w % L2;
+        C2<R> out[P];
+        dft_pencil<R, P, L, P, -1>(in_x[v], out);
+#pragma unroll
+        for (int k = 0; k < P; ++k) A[g][k * L2 + yz] = out[k];
+      }
+    }
+    if (ch + wk.step < wk.end) load_x(ch + wk.step);
+    __syncthreads();
+    // pass y: pencil (rz, xi); B[g][rz + L (xi + P yi)]
+    for (int w = tid; w < ng * P * L; w += NT) {
+      const int g = w / (P * L), q = w % (P * L), rz = q % L, xi = q / L;
+      C2<R> in[L], out[P];
+#pragma unroll
+      for (int r = 0; r < L; ++r) in[r] = A[g][xi * L2 + r + L * rz];
+      dft_pencil<R, P, L, P, -1>(in, out);
+#pragma unroll
+      for (int k = 0; k < P; ++k) B[g][rz + L * (xi + P * k)] = out[k];
+    }
+    __syncthreads();
+    // pass z: pencil (xi, yi) = xy; A[g][xy + P^2 zi]
+    for (int w = tid; w < ng * P * P; w += NT) {
+      const int g = w / (P * P), xy = w % (P * P);
+      C2<R> in[L], out[P];
+#pragma unroll
+      for (int r = 0; r < L; ++r) in[r] = B[g][r + L * xy];
+      dft_pencil<R, P, L, P, -1>(in, out);
+#pragma unroll
+      for (int k = 0; k < P; ++k) A[g][xy + P * P * k] = out[k];
+    }
+    __syncthreads();
+    // the G rows are contiguous; stored two entries (16 or 32 bytes) per thread
+    constexpr int RW2 = RW / 2, NV = (G * RW2 + NT - 1) / NT;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const int w = tid + k * NT;
+      if (w < ng * RW2) {
+        const int g = w / RW2, p = 2 * (w % RW2);
+        const int f0 = fq[p], f1 = fq[p + 1];
+        C2x2<R> v;
+        v.a = f0 >= 0 ? A[g][f0] : C2<R>{(R)0, (R)0};
+        v.b = f1 >= 0 ? A[g][f1] : C2<R>{(R)0, (R)0};
+        reinterpret_cast<C2x2<R>*>(Mt + i0 * RW)[w] = v;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -2132,8 +2176,8 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
     const int64_t rb = P.lvl_m2f[fr_lo[k]], nr = P.lvl_m2f[fr_hi[k]] - rb;
     if (nr == 0) continue;
     DEFMM_L_SWITCH(L, DEFMM_G_SWITCH(W.fourier_items, R, LL, hipLaunchKernelGGL((k_m2f<R, LL, GG>),
-                                     dim3((unsigned)((nr + GG - 1) / GG)), dim3(256), 0, s, nr, P.m2f_exp + rb,
-                                     P.freq, (const C2<R>*)M, Mt + rb * P3R)));
+                                     dim3(fourier_grid((nr + GG - 1) / GG, P.num_cu)), dim3(256), 0, s, nr,
+                                     P.m2f_exp + rb, P.freq, (const C2<R>*)M, Mt + rb * P3R)));
   }
   tm.end();
   if (fork_late) {
