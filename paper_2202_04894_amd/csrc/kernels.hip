@@ -1609,17 +1609,21 @@ __global__ __launch_bounds__(round64(L* L* L)) void k_l2l(int64_t n, const int32
 
 // ------------------------------------------------------------------ L2P
 // p(x) += sum_u exp(ik<x - a, u>) sum_h S_h(x) exp(-ik<x_h - a, u>) L^u(x_h).
-// One wave per work item (a leaf and <= 256 of its points, 64 at a time, one
-// point per lane).  The interpolation weights of a point are computed once;
-// the leaf's expansions are staged one by one in LDS with their node phases,
-// the next expansion's values being loaded while the current one is summed.
+// One wave per work item (a leaf and <= 256 of its points, 64 at a time).
+// Leaves hold 18 points on average, so a chunk of m points is replicated:
+// with m <= 16 the wave holds 4 replicas of 16 lanes, with m <= 32 two of 32,
+// else one; replica q serves expansions q, q + NR, ... of the leaf, one point
+// per lane, and the replicas' sums are added at the end.  The interpolation
+// weights of a point are computed once; each replica stages its expansion in
+// LDS with the node phases (its lanes loading the next one's values while the
+// current one is summed).
 template <typename R, int L>
 __global__ __launch_bounds__(64) void k_l2p(int64_t n, const int32_t* __restrict__ cell,
                                             const int32_t* __restrict__ pfirst, const int32_t* __restrict__ pcount,
                                             TreeView T, Geo g, const C2<R>* __restrict__ Lx,
                                             C2<R>* __restrict__ ps) {
-  constexpr int L3 = L * L * L, NV = (L3 + 63) / 64;
-  __shared__ C2<R> lp[L3];
+  constexpr int L3 = L * L * L, RMAX = 4, NV = (L3 + 64 / RMAX - 1) / (64 / RMAX);
+  __shared__ C2<R> lp[RMAX][L3];
   const int64_t item = blockIdx.x;
   if (item >= n) return;
   const int c = cell[item];
@@ -1627,19 +1631,14 @@ __global__ __launch_bounds__(64) void k_l2p(int64_t n, const int32_t* __restrict
   const double ax = g.ox + h * T.ijk[3 * c], ay = g.oy + h * T.ijk[3 * c + 1], az = g.oz + h * T.ijk[3 * c + 2];
   const int first = pfirst[item], cnt = pcount[item];
   const int lane = threadIdx.x;
-  const int e0 = T.exp_begin[c], e1 = T.exp_begin[c + 1];
+  const int e0 = T.exp_begin[c], ne = T.exp_begin[c + 1] - e0;
   const double kh = g.kappa * h / (double)(L - 1);
-  int kx_[NV], ky_[NV], kz_[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    const int i = min(lane + 64 * v, L3 - 1);
-    kx_[v] = i % L;
-    ky_[v] = (i / L) % L;
-    kz_[v] = i / (L * L);
-  }
   for (int base = 0; base < cnt; base += 64) {
-    const int j = base + lane;
-    const bool on = j < cnt;
+    const int m = min(64, cnt - base);
+    const int nr = m <= 16 ? 4 : m <= 32 ? 2 : 1;  // replicas (uniform)
+    const int lpr = 64 / nr, q = lane / lpr, x = lane - q * lpr;
+    const bool on = x < m;
+    const int j = base + x;
     double d0 = 0, d1 = 0, d2 = 0;
     if (on) {
       const int64_t pi = first + j;
@@ -1652,44 +1651,73 @@ __global__ __launch_bounds__(64) void k_l2p(int64_t n, const int32_t* __restrict
     lagrange<R, L>((R)(d1 / h), wy);
     lagrange<R, L>((R)(d2 / h), wz);
     C2<R> acc = {(R)0, (R)0};
+    // replica q stages nodes x + lpr v of its expansion
     C2<R> nxt[NV];
-    if (e0 < e1) {
+    double nu0 = 0, nu1 = 0, nu2 = 0;  // the next expansion's direction
+    if (q < ne) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v)
-        nxt[v] = lane + 64 * v < L3 ? Lx[(int64_t)e0 * L3 + lane + 64 * v] : C2<R>{(R)0, (R)0};
-    }
-    for (int e = e0; e < e1; ++e) {
-      const double ux = T.exp_u[3 * e], uy = T.exp_u[3 * e + 1], uz = T.exp_u[3 * e + 2];
-      __syncthreads();
-#pragma unroll
-      for (int v = 0; v < NV; ++v)
-        if (lane + 64 * v < L3)
-          lp[lane + 64 * v] = cmul(nxt[v], expi<R>(-kh * (ux * kx_[v] + uy * ky_[v] + uz * kz_[v])));
-      __syncthreads();
-      if (e + 1 < e1) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-          nxt[v] = lane + 64 * v < L3 ? Lx[(int64_t)(e + 1) * L3 + lane + 64 * v] : C2<R>{(R)0, (R)0};
+      for (int v = 0; v < NV; ++v) {
+        const int k = x + lpr * v;
+        if (v * lpr < L3 && k < L3) nxt[v] = Lx[(int64_t)(e0 + q) * L3 + k];
       }
-      C2<R> sz = {(R)0, (R)0};
+      nu0 = T.exp_u[3 * (e0 + q)];
+      nu1 = T.exp_u[3 * (e0 + q) + 1];
+      nu2 = T.exp_u[3 * (e0 + q) + 2];
+    }
+    for (int i = 0; i < ne; i += nr) {
+      const int e = e0 + i + q;
+      const bool has = i + q < ne;
+      const double ux = nu0, uy = nu1, uz = nu2;
+      __syncthreads();
+      if (has) {
 #pragma unroll
-      for (int kz = 0; kz < L; ++kz) {
-        C2<R> sy = {(R)0, (R)0};
-#pragma unroll
-        for (int ky = 0; ky < L; ++ky) {
-          C2<R> sx = {(R)0, (R)0};
-#pragma unroll
-          for (int kx = 0; kx < L; ++kx) cfma_r(sx, lp[kx + L * ky + L * L * kz], wx[kx]);
-          cfma_r(sy, sx, wy[ky]);
+        for (int v = 0; v < NV; ++v) {
+          const int k = x + lpr * v;
+          if (v * lpr < L3 && k < L3) {
+            const int kx = k % L, ky = (k / L) % L, kz = k / (L * L);
+            lp[q][k] = cmul(nxt[v], expi<R>(-kh * (ux * kx + uy * ky + uz * kz)));
+          }
         }
-        cfma_r(sz, sy, wz[kz]);
       }
-      cfma(acc, sz, expi<R>(g.kappa * (ux * d0 + uy * d1 + uz * d2)));
+      __syncthreads();
+      if (i + nr + q < ne) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const int k = x + lpr * v;
+          if (v * lpr < L3 && k < L3) nxt[v] = Lx[(int64_t)(e + nr) * L3 + k];
+        }
+        nu0 = T.exp_u[3 * (e + nr)];
+        nu1 = T.exp_u[3 * (e + nr) + 1];
+        nu2 = T.exp_u[3 * (e + nr) + 2];
+      }
+      if (on && has) {
+        const C2<R>* l = lp[q];
+        C2<R> sz = {(R)0, (R)0};
+#pragma unroll
+        for (int kz = 0; kz < L; ++kz) {
+          C2<R> sy = {(R)0, (R)0};
+#pragma unroll
+          for (int ky = 0; ky < L; ++ky) {
+            C2<R> sx = {(R)0, (R)0};
+#pragma unroll
+            for (int kx = 0; kx < L; ++kx) cfma_r(sx, l[kx + L * ky + L * L * kz], wx[kx]);
+            cfma_r(sy, sx, wy[ky]);
+          }
+          cfma_r(sz, sy, wz[kz]);
+        }
+        cfma(acc, sz, expi<R>(g.kappa * (ux * d0 + uy * d1 + uz * d2)));
+      }
     }
-    if (on) {
+    // the replicas' sums: lane x collects lanes x + lpr, x + 2 lpr, ...
+    for (int o = 32; o >= lpr; o >>= 1) {
+      acc.x += __shfl_down(acc.x, o);
+      acc.y += __shfl_down(acc.y, o);
+    }
+    if (on && q == 0) {
       C2<R> cur = ps[first + j];
       ps[first + j] = {cur.x + acc.x, cur.y + acc.y};
     }
+    __syncthreads();
   }
 }
 
