@@ -554,23 +554,38 @@ __global__ __launch_bounds__(64) void k_m2m_p(int64_t npair, const int32_t* __re
 #pragma unroll
   for (int l = 0; l < L; ++l) acc[l] = {(R)0, (R)0};
   C2<R>* stg = st[hf];
+  // the sons' indices and octants up front, each son's pencil one son ahead
+  int ce0s[8], ces[8], os[8];
+#pragma unroll
   for (int k = 0; k < 8; ++k) {
-    const int ce0 = child[(int64_t)item0 * 8 + k];
-    if (ce0 < 0) break;  // the same for both expansions of the wave
-    const int o = oct[(int64_t)item0 * 8 + k];
+    ce0s[k] = child[(int64_t)item0 * 8 + k];
+    ces[k] = child[(int64_t)it * 8 + k];
+    os[k] = oct[(int64_t)item0 * 8 + k];
+  }
+  C2<R> nv[L];
+  if (on && ces[0] >= 0) {
+#pragma unroll
+    for (int r = 0; r < L; ++r) nv[r] = M[(int64_t)ces[0] * L3 + p * L + r];
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (ce0s[k] < 0) break;  // the same for both expansions of the wave
+    const int o = os[k];
     const int bx = o & 1, by = (o >> 1) & 1, bz = (o >> 2) & 1;
-    const int ce = child[(int64_t)it * 8 + k];
     C2<R> in[L], out[L];
 #pragma unroll
     for (int r = 0; r < L; ++r) in[r] = {(R)0, (R)0};
     if (on) {
       // x-pencil (r_y, r_z) = (a0, a1) of the son, times exp(-i kappa <y'_r - a_s, v>)
-      const C2<R>* src = M + (int64_t)ce * L3 + p * L;
       const double t0 = -ks * (v0 * bx + v1 * (by + (double)a0 / (L - 1)) + v2 * (bz + (double)a1 / (L - 1)));
       C2<R> ph[L];
       phase_run<R, L>(t0, -ks * v0 / (L - 1), ph);
 #pragma unroll
-      for (int r = 0; r < L; ++r) in[r] = cmul(src[r], ph[r]);
+      for (int r = 0; r < L; ++r) in[r] = cmul(nv[r], ph[r]);
+      if (k + 1 < 8 && ces[k + 1 < 8 ? k + 1 : 7] >= 0) {
+#pragma unroll
+        for (int r = 0; r < L; ++r) nv[r] = M[(int64_t)ces[k + 1 < 8 ? k + 1 : 7] * L3 + p * L + r];
+      }
     }
     son_mode_b<R, L, false>(bx, in, out);
     __syncthreads();
