@@ -153,3 +153,21 @@ def test_graph_replay_in_the_executor_is_closed():
     from paper_2202_04894_amd import serving as S
     with pytest.raises(NotImplementedError):
         S.DeviceExecutor(graphs=True)
+
+
+def test_requests_carry_the_setting_of_their_order_and_kappa():
+    """Each serving request carries the knob setting measured within 1e-4 of
+    the direct sum for its order and kappa*D band (the finer setting for L = 4
+    at high kappa*D); the paper-literal mode gives every request (1, 2, 0)."""
+    from paper_2202_04894_amd import serving as S
+    reqs = S.config_requests(n_requests=64, n_geometries=16, seed=7)
+    seen = set()
+    for r in reqs:
+        kd = 2.0 * r.kappa
+        want = (S.ACCURATE_KNOBS_HIGH_KD if kd >= S.HIGH_KD else S.ACCURATE_KNOBS)[r.order_L]
+        assert r.knobs == want, (r.order_L, kd, r.knobs)
+        seen.add((r.order_L, kd >= S.HIGH_KD))
+    assert len(seen) >= 3  # both orders and both bands appear in the mix
+    assert S.accurate_knobs(4, 250.0) == (0.1, 0.75, 2) and S.accurate_knobs(4, 32.0) == (0.15, 0.75, 2)
+    lit = S.config_requests(n_requests=8, n_geometries=4, seed=7, accurate=False)
+    assert all(r.knobs == S.LITERAL_KNOBS for r in lit)
