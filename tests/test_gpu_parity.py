@@ -111,6 +111,27 @@ def test_c128_matches_oracle(geom, n, kappa, kw):
             assert np.abs(ex["values"] - ex_o[key]).max() <= 1e-11 * scale, (key, updown)
 
 
+def test_leaves_beyond_one_wave():
+    """Leaves of up to 150 points: L2P work items of several 64-point chunks
+    (the last one replicated across the wave when small), complex64 P2M over
+    several point chunks, near-field blocks split per leaf; both precisions
+    against the oracle element by element, with both up/down kernel families."""
+    defmm = _defmm()
+    X = W.sphere(20000, 141)
+    q = W.charges(20000, 142)
+    kw = dict(order_L=4, ncrit=150, eta=0.5, hf_threshold=1.0, dir_refine=1)
+    ref = oracle.FMM(X, None, 16.0, oracle_params(defmm.Params(**kw))).apply(q)
+    for prec, tol in ((defmm.C128, 1e-11), (defmm.C64, 2e-5)):
+        p, plan, ws = run_gpu(X, q, 16.0, defmm.Params(precision=prec, **kw))
+        tr = plan.tree(0)
+        assert tr["count"][tr["is_leaf"].astype(bool)].max() > 128
+        assert_close(p.astype(np.complex128), ref, tol, (prec, rel(p, ref)))
+        qt = torch.as_tensor(q, device="cuda").to(plan.cdtype)
+        ws.set_tuning(overlap=0, p2p_waves_per_cu=2, m2l_variant=2, dense_levels=0, updown_variant=0)
+        p0 = ws.matvec(qt).cpu().numpy().astype(np.complex128)
+        assert_close(p0, ref, tol, (prec, "updown 0", rel(p0, ref)))
+
+
 @pytest.mark.parametrize("geom,n,kappa,kw", FMM_CASES[:3])
 def test_c64_matches_oracle(geom, n, kappa, kw):
     defmm = _defmm()
