@@ -521,9 +521,12 @@ constexpr int pencil_epw() { return L * L <= 32 ? 2 : 1; }
 // sharing a wave).  A wave serves up to two expansions v of one father cell;
 // lane p < L^2 of a half holds pencil p.  For each son: the son's expansion
 // Father(v) as x-pencils (r_y, r_z), the son-node phases exp(-i kappa <y'_r -
-// a_s, v>) with FP64 arguments, three mode products with the son matrices
-// (x-, y- and z-pencils, exchanged through LDS), summed over sons in
-// z-pencils (l_x, l_y); then the father-node phases exp(i kappa <y_l - a_s, v>).
+// a_s, v>) with FP64 arguments, and three mode products with the son matrices
+// (x-, y- and z-pencils, exchanged through LDS), summed over sons; a mode
+// matrix depends only on the son's half along its axis, so the sum is taken
+// factor by factor (the x-mode results of sons differing only in x before
+// their common y-mode product, and so on: 14 mode products for 8 sons instead
+// of 24); then the father-node phases exp(i kappa <y_l - a_s, v>).
 // Along a pencil the phases are one FP64-reduced turn and its step rotated
 // L - 1 times (phase_run).
 // Both expansions of a wave share the father cell, so its sons and their
@@ -554,62 +557,115 @@ __global__ __launch_bounds__(64) void k_m2m_p(int64_t npair, const int32_t* __re
 #pragma unroll
   for (int l = 0; l < L; ++l) acc[l] = {(R)0, (R)0};
   C2<R>* stg = st[hf];
-  // the sons' indices and octants up front, each son's pencil one son ahead
-  int ce0s[8], ces[8], os[8];
+  // the sons by octant o = bx + 2 by + 4 bz: whether present (the same for
+  // both expansions of the wave) and this half's son expansion
+  bool pres[8];
+  int se[8];
+  {
+    int ce0s[8], ces[8], os[8];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    ce0s[k] = child[(int64_t)item0 * 8 + k];
-    ces[k] = child[(int64_t)it * 8 + k];
-    os[k] = oct[(int64_t)item0 * 8 + k];
+    for (int k = 0; k < 8; ++k) {
+      ce0s[k] = child[(int64_t)item0 * 8 + k];
+      ces[k] = child[(int64_t)it * 8 + k];
+      os[k] = oct[(int64_t)item0 * 8 + k];
+    }
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      pres[o] = false;
+      se[o] = -1;
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (ce0s[k] >= 0 && os[k] == o) {
+          pres[o] = true;
+          se[o] = ces[k];
+        }
+    }
   }
+  // each son's pencil is loaded one son ahead, sons in octant order
   C2<R> nv[L];
-  if (on && ces[0] >= 0) {
+  auto load_after = [&](int o0) {  // the pencil of the first present son at octant >= o0
+    int e = -1;
 #pragma unroll
-    for (int r = 0; r < L; ++r) nv[r] = M[(int64_t)ces[0] * L3 + p * L + r];
-  }
+    for (int o = 7; o >= 0; --o)
+      if (o >= o0 && pres[o]) e = se[o];
+    if (on && e >= 0) {
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    if (ce0s[k] < 0) break;  // the same for both expansions of the wave
-    const int o = os[k];
-    const int bx = o & 1, by = (o >> 1) & 1, bz = (o >> 2) & 1;
-    C2<R> in[L], out[L];
+      for (int r = 0; r < L; ++r) nv[r] = M[(int64_t)e * L3 + p * L + r];
+    }
+  };
+  load_after(0);
+  // Sum factorisation over the sons: the x-mode products of the two sons that
+  // differ only in bx are summed before their common y-mode product, and the
+  // y-mode results of the two halves by before their common z-mode product.
 #pragma unroll
-    for (int r = 0; r < L; ++r) in[r] = {(R)0, (R)0};
-    if (on) {
-      // x-pencil (r_y, r_z) = (a0, a1) of the son, times exp(-i kappa <y'_r - a_s, v>)
-      const double t0 = -ks * (v0 * bx + v1 * (by + (double)a0 / (L - 1)) + v2 * (bz + (double)a1 / (L - 1)));
-      C2<R> ph[L];
-      phase_run<R, L>(t0, -ks * v0 / (L - 1), ph);
+  for (int bz = 0; bz < 2; ++bz) {
+    if (!(pres[4 * bz] || pres[4 * bz + 1] || pres[4 * bz + 2] || pres[4 * bz + 3])) continue;
+    C2<R> ysum[L];
 #pragma unroll
-      for (int r = 0; r < L; ++r) in[r] = cmul(nv[r], ph[r]);
-      if (k + 1 < 8 && ces[k + 1 < 8 ? k + 1 : 7] >= 0) {
+    for (int l = 0; l < L; ++l) ysum[l] = {(R)0, (R)0};
 #pragma unroll
-        for (int r = 0; r < L; ++r) nv[r] = M[(int64_t)ces[k + 1 < 8 ? k + 1 : 7] * L3 + p * L + r];
+    for (int by = 0; by < 2; ++by) {
+      const int ob = 2 * by + 4 * bz;
+      if (!(pres[ob] || pres[ob + 1])) continue;
+      C2<R> xsum[L], in[L], out[L];
+#pragma unroll
+      for (int l = 0; l < L; ++l) xsum[l] = {(R)0, (R)0};
+#pragma unroll
+      for (int bx = 0; bx < 2; ++bx) {
+        const int o = ob + bx;
+        if (!pres[o]) continue;
+#pragma unroll
+        for (int r = 0; r < L; ++r) in[r] = {(R)0, (R)0};
+        if (on) {
+          // x-pencil (r_y, r_z) = (a0, a1) of the son, times exp(-i kappa <y'_r - a_s, v>)
+          const double t0 = -ks * (v0 * bx + v1 * (by + (double)a0 / (L - 1)) + v2 * (bz + (double)a1 / (L - 1)));
+          C2<R> ph[L];
+          phase_run<R, L>(t0, -ks * v0 / (L - 1), ph);
+#pragma unroll
+          for (int r = 0; r < L; ++r) in[r] = cmul(nv[r], ph[r]);
+        }
+        load_after(o + 1);
+        if (bx) son_mode<R, L, 1, false>(in, out);
+        else son_mode<R, L, 0, false>(in, out);
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+          xsum[l].x += out[l].x;
+          xsum[l].y += out[l].y;
+        }
+      }
+      __syncthreads();
+      if (on) {  // x-pencil (r_y, r_z) -> stage [l_x][r_z][r_y]
+#pragma unroll
+        for (int l = 0; l < L; ++l) stg[(l + L * a1) * L + a0] = xsum[l];
+      }
+      __syncthreads();
+      if (on) {  // y-pencil (l_x, r_z) = (a0, a1)
+#pragma unroll
+        for (int r = 0; r < L; ++r) in[r] = stg[p * L + r];
+      }
+      if (by) son_mode<R, L, 1, false>(in, out);
+      else son_mode<R, L, 0, false>(in, out);
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
+        ysum[l].x += out[l].x;
+        ysum[l].y += out[l].y;
       }
     }
-    son_mode_b<R, L, false>(bx, in, out);
-    __syncthreads();
-    if (on) {  // x-pencil (r_y, r_z) -> stage [l_x][r_z][r_y]
-#pragma unroll
-      for (int l = 0; l < L; ++l) stg[(l + L * a1) * L + a0] = out[l];
-    }
-    __syncthreads();
-    if (on) {  // y-pencil (l_x, r_z) = (a0, a1)
-#pragma unroll
-      for (int r = 0; r < L; ++r) in[r] = stg[p * L + r];
-    }
-    son_mode_b<R, L, false>(by, in, out);
+    C2<R> in[L], out[L];
     __syncthreads();
     if (on) {  // -> stage [l_x][l_y][r_z]
 #pragma unroll
-      for (int l = 0; l < L; ++l) stg[(a0 + L * l) * L + a1] = out[l];
+      for (int l = 0; l < L; ++l) stg[(a0 + L * l) * L + a1] = ysum[l];
     }
     __syncthreads();
+#pragma unroll
+    for (int r = 0; r < L; ++r) in[r] = {(R)0, (R)0};
     if (on) {  // z-pencil (l_x, l_y) = (a0, a1)
 #pragma unroll
       for (int r = 0; r < L; ++r) in[r] = stg[p * L + r];
     }
-    son_mode_b<R, L, false>(bz, in, out);
+    if (bz) son_mode<R, L, 1, false>(in, out);
+    else son_mode<R, L, 0, false>(in, out);
 #pragma unroll
     for (int l = 0; l < L; ++l) {
       acc[l].x += out[l].x;
