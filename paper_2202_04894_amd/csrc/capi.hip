@@ -11,6 +11,7 @@
 #include <new>
 #include <stdexcept>
 #include <string>
+#include <tuple>
 
 #include "../../include/defmm.h"
 #include "build_device.hpp"
@@ -86,6 +87,44 @@ size_t csize(const DevPlan& P) { return P.precision == 0 ? 16 : 8; }
 // Expansions per wave of the pencil M2M/L2L kernels (the device side's
 // pencil_epw): two when a half wave holds the L^2 pencils of one expansion.
 int pencil_epw_host(int L) { return L * L <= 32 ? 2 : 1; }
+
+// L2L families of son level l + 1: the son items (son expansion, CSR range of
+// its father expansions) of one father cell that the same father expansions
+// feed (one son direction, or the only expansion of a low-frequency son),
+// found by (father cell, first father expansion); at most one son per octant.
+// Families in father-cell order, kFamWords words each; fcell the father cell
+// of each.  False if a family would hold two sons of one octant (not built).
+bool l2l_families(const HostPlan& H, size_t l, std::vector<int32_t>& fam, std::vector<int32_t>& fcell) {
+  const auto& ch = H.l2l_ch[l];
+  const auto& bg = H.l2l_begin[l];
+  const auto& pa = H.l2l_par[l];
+  const auto& oc = H.l2l_oct[l];
+  const int64_t n = (int64_t)ch.size();
+  std::vector<std::tuple<int32_t, int32_t, int32_t>> key(n);  // (father cell, first father exp, item)
+  for (int64_t i = 0; i < n; ++i)
+    key[i] = {H.tx.parent[H.tx.exp_cell[ch[i]]], pa[bg[i]], (int32_t)i};
+  std::sort(key.begin(), key.end());
+  for (int64_t a = 0; a < n;) {
+    int64_t b = a;
+    const int32_t i0 = std::get<2>(key[a]);
+    int32_t rec[kFamWords];
+    for (int q = 0; q < kFamWords; ++q) rec[q] = q < 2 ? 0 : -1;
+    rec[0] = bg[i0];
+    rec[1] = bg[i0 + 1] - bg[i0];
+    while (b < n && std::get<0>(key[b]) == std::get<0>(key[a]) && std::get<1>(key[b]) == std::get<1>(key[a])) {
+      const int32_t i = std::get<2>(key[b]);
+      if (bg[i + 1] - bg[i] != rec[1]) return false;
+      const int o = oc[bg[i]];
+      if (o < 0 || o > 7 || rec[2 + o] >= 0) return false;
+      rec[2 + o] = ch[i];
+      ++b;
+    }
+    fam.insert(fam.end(), rec, rec + kFamWords);
+    fcell.push_back(std::get<0>(key[a]));
+    a = b;
+  }
+  return true;
+}
 
 // Work list of the pencil kernels from the cell of each item (items of a cell
 // consecutive): pairs of items of the same cell, (i, -1) for a lone one; with
@@ -426,6 +465,13 @@ defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int
       std::vector<int32_t> pr = pencil_pairs(cell, P.L);
       P.l2l[l].npair = (int64_t)pr.size() / pencil_epw_host(P.L);
       P.l2l[l].pair = upload(P, pr);
+      std::vector<int32_t> fam, fcell;
+      if (l2l_families(H, l, fam, fcell)) {
+        std::vector<int32_t> fp = pencil_pairs(fcell, P.L);
+        P.l2l[l].nfpair = (int64_t)fp.size() / pencil_epw_host(P.L);
+        P.l2l[l].fpair = upload(P, fp);
+        P.l2l[l].fam = upload(P, fam);
+      }
     }
     P.l2p_cell = upload(P, H.l2p_cell);
     P.l2p_first = upload(P, H.l2p_first);

@@ -62,7 +62,17 @@ struct LevelTable {  // per-level operator table on the device
   // wave holds an expansion (L^2 <= 32), else one at a time (-1 = no second)
   int32_t* pair = nullptr;
   int64_t npair = 0;
+  // L2L by families (complex64 pencil path): kFamWords words per family, the
+  // son expansions of one father cell fed by the same father expansions, and
+  // the families taken two at a time (same father cell) as `pair` is
+  int32_t* fam = nullptr;
+  int32_t* fpair = nullptr;
+  int64_t nfpair = 0;
 };
+
+// An L2L family record: [0] first of its father expansions in the level's
+// parent list, [1] their number, [2 + o] the son expansion at octant o or -1.
+constexpr int kFamWords = 16;
 
 struct DevPlan {
   HostPlan host;   // kept for introspection and stats

@@ -17,6 +17,7 @@
 #include <cmath>
 #include <algorithm>
 #include <cstdio>
+#include <type_traits>
 
 #include "device.hpp"
 
@@ -777,6 +778,149 @@ __global__ __launch_bounds__(64) void k_l2l_p(int64_t npair, const int32_t* __re
     for (int l = 0; l < L; ++l) {
       const C2<R> cur = add ? dst[L2 * l] : C2<R>{(R)0, (R)0};
       dst[L2 * l] = {cur.x + acc[l].x, cur.y + acc[l].y};
+    }
+  }
+}
+
+// L2L by families (the complex64 pencil path): a half wave serves one family,
+// the son expansions u_o (octant o) of one father cell that the same father
+// expansions v feed, and takes each v once for all of them.  Per v: the
+// father's values as x-pencils times the father-node phases, then the mode
+// products with the transposed son matrices shared between sons: one x-mode
+// product per half bx, one y-mode product per (bx, by), one z-mode product
+// per son (14 for 8 sons instead of 24), each son's result times its
+// son-node phases exp(i kappa <x'_h - a_t, v>) added to the son's sum in
+// registers.  Both families of a wave have the same father cell; the branches
+// over octants follow the union of their sons, so they are uniform.
+template <typename R, int L>
+__global__ __launch_bounds__(64) void k_l2l_f(int64_t npair, const int32_t* __restrict__ pairs,
+                                              const int32_t* __restrict__ fam, const int32_t* __restrict__ par,
+                                              const uint8_t* __restrict__ has_m2l, TreeView T, Geo g,
+                                              C2<R>* __restrict__ Lx) {
+  constexpr int L2 = L * L, L3 = L2 * L, EPW = pencil_epw<L>(), HW = 64 / EPW;
+  __shared__ C2<R> sx[EPW][2][L3];  // x-mode results by bx, [l_x][k_z][k_y]
+  __shared__ C2<R> sy[EPW][4][L3];  // y-mode results by bx + 2 by, [l_x][l_y][k_z]
+  const int64_t w = blockIdx.x;
+  if (w >= npair) return;
+  const int lane = threadIdx.x, hf = lane / HW, p = lane % HW;
+  const int item0 = pairs[EPW * w];
+  const int item1 = EPW == 2 ? pairs[EPW * w + 1] : -1;
+  int rec0[10], rec1[10];
+#pragma unroll
+  for (int q = 0; q < 10; ++q) {
+    rec0[q] = fam[(int64_t)item0 * kFamWords + q];
+    rec1[q] = item1 >= 0 ? fam[(int64_t)item1 * kFamWords + q] : (q < 2 ? 0 : -1);
+  }
+  const bool mine = hf == 0 || item1 >= 0;
+  const bool on = mine && p < L2;
+  const int vb = hf == 0 ? rec0[0] : rec1[0];
+  const int vn = mine ? (hf == 0 ? rec0[1] : rec1[1]) : 0;
+  const int nmax = rec0[1] > rec1[1] ? rec0[1] : rec1[1];
+  bool pres[8];
+  int se[8];
+#pragma unroll
+  for (int o = 0; o < 8; ++o) {
+    pres[o] = rec0[2 + o] >= 0 || rec1[2 + o] >= 0;
+    se[o] = mine ? (hf == 0 ? rec0[2 + o] : rec1[2 + o]) : -1;
+  }
+  bool need_y[4], need_x[2];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) need_y[q] = pres[q] || pres[q + 4];
+  need_x[0] = need_y[0] || need_y[2];
+  need_x[1] = need_y[1] || need_y[3];
+  // the father cell (of every v of both families) and the sons' level
+  const int cf = T.exp_cell[par[rec0[0]]];
+  const double hp = ldexp(g.D, -T.level[cf]), hcs = 0.5 * hp;
+  constexpr double inv2pi = 0.15915494309189533577;
+  const double kf = g.kappa * hp / (L - 1) * inv2pi, ks = g.kappa * hcs * inv2pi;
+  const int a0 = p % L, a1 = (p / L) % L;
+  C2<R> acc[8][L];
+#pragma unroll
+  for (int o = 0; o < 8; ++o)
+#pragma unroll
+    for (int l = 0; l < L; ++l) acc[o][l] = {(R)0, (R)0};
+  for (int k = 0; k < nmax; ++k) {
+    const bool act = on && k < vn;
+    const int pe = par[act ? vb + k : rec0[0]];
+    const double v0 = T.exp_u[3 * pe], v1 = T.exp_u[3 * pe + 1], v2 = T.exp_u[3 * pe + 2];
+    C2<R> in[L], out[L];
+#pragma unroll
+    for (int r = 0; r < L; ++r) in[r] = {(R)0, (R)0};
+    if (act) {
+      // x-pencil (k_y, k_z) of the father, times exp(-i kappa hp <k, v> / (L-1))
+      const C2<R>* src = Lx + (int64_t)pe * L3 + p * L;
+      C2<R> ph[L];
+      phase_run<R, L>(-kf * (v1 * a0 + v2 * a1), -kf * v0, ph);
+#pragma unroll
+      for (int r = 0; r < L; ++r) in[r] = cmul(src[r], ph[r]);
+    }
+#pragma unroll
+    for (int bx = 0; bx < 2; ++bx) {
+      if (!need_x[bx]) continue;
+      if (bx) son_mode<R, L, 1, true>(in, out);
+      else son_mode<R, L, 0, true>(in, out);
+      if (act) {
+#pragma unroll
+        for (int l = 0; l < L; ++l) sx[hf][bx][(l + L * a1) * L + a0] = out[l];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int bx = 0; bx < 2; ++bx) {
+      if (!need_x[bx]) continue;
+      if (act) {  // y-pencil (l_x, k_z) = (a0, a1)
+#pragma unroll
+        for (int r = 0; r < L; ++r) in[r] = sx[hf][bx][p * L + r];
+      }
+#pragma unroll
+      for (int by = 0; by < 2; ++by) {
+        if (!need_y[bx + 2 * by]) continue;
+        if (by) son_mode<R, L, 1, true>(in, out);
+        else son_mode<R, L, 0, true>(in, out);
+        if (act) {
+#pragma unroll
+          for (int l = 0; l < L; ++l) sy[hf][bx + 2 * by][(a0 + L * l) * L + a1] = out[l];
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (!need_y[q]) continue;
+      const int bx = q & 1, by = q >> 1;
+      if (act) {  // z-pencil (l_x, l_y) = (a0, a1)
+#pragma unroll
+        for (int r = 0; r < L; ++r) in[r] = sy[hf][q][p * L + r];
+      }
+#pragma unroll
+      for (int bz = 0; bz < 2; ++bz) {
+        const int o = q + 4 * bz;
+        if (!pres[o]) continue;
+        if (bz) son_mode<R, L, 1, true>(in, out);
+        else son_mode<R, L, 0, true>(in, out);
+        if (act && se[o] >= 0) {
+          // son-node phases exp(i kappa hc <b + h / (L-1), v>), z-pencil (h_x, h_y)
+          C2<R> ph[L];
+          phase_run<R, L>(ks * (v0 * (bx + (double)a0 / (L - 1)) + v1 * (by + (double)a1 / (L - 1)) + v2 * bz),
+                          ks * v2 / (L - 1), ph);
+#pragma unroll
+          for (int l = 0; l < L; ++l) cfma(acc[o][l], out[l], ph[l]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 0; o < 8; ++o) {
+    if (!pres[o]) continue;
+    if (on && se[o] >= 0) {
+      // added to what M2L wrote (an M2L target), else the son's only contribution
+      C2<R>* dst = Lx + (int64_t)se[o] * L3 + p;
+      const bool add = has_m2l[se[o]] != 0;
+#pragma unroll
+      for (int l = 0; l < L; ++l) {
+        const C2<R> cur = add ? dst[L2 * l] : C2<R>{(R)0, (R)0};
+        dst[L2 * l] = {cur.x + acc[o][l].x, cur.y + acc[o][l].y};
+      }
     }
   }
 }
@@ -2351,7 +2495,11 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
   for (size_t l = 0; l < P.l2l.size(); ++l) {
     const LevelTable& t = P.l2l[l];
     if (t.n == 0) continue;
-    if (W.pencil_updown) {
+    if (W.pencil_updown && std::is_same<R, float>::value && t.fam) {
+      DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_l2l_f<float, LL>), dim3((unsigned)t.nfpair), dim3(64), 0, s,
+                                            t.nfpair, t.fpair, t.fam, t.c, P.has_m2l, TX, g,
+                                            reinterpret_cast<C2<float>*>(Lx)));
+    } else if (W.pencil_updown) {
       DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_l2l_p<R, LL>), dim3((unsigned)t.npair), dim3(64), 0, s, t.npair,
                                             t.pair, t.a, t.b, t.c, t.oct, P.has_m2l, TX, g, Lx));
     } else {
