@@ -839,21 +839,45 @@ __global__ __launch_bounds__(64) void k_l2l_f(int64_t npair, const int32_t* __re
   for (int o = 0; o < 8; ++o)
 #pragma unroll
     for (int l = 0; l < L; ++l) acc[o][l] = {(R)0, (R)0};
+  // the father expansions one ahead (their indices two ahead)
+  auto pe_at = [&](int j) { return par[on && j < vn ? vb + j : rec0[0]]; };
+  int pe_n = pe_at(0);
+  double nv0 = 0, nv1 = 0, nv2 = 0;
+  C2<R> nraw[L];
+  auto fetch = [&](int pe, bool a) {
+    nv0 = T.exp_u[3 * pe];
+    nv1 = T.exp_u[3 * pe + 1];
+    nv2 = T.exp_u[3 * pe + 2];
+    if (a) {
+      const C2<R>* src = Lx + (int64_t)pe * L3 + p * L;
+#pragma unroll
+      for (int r = 0; r < L; ++r) nraw[r] = src[r];
+    }
+  };
+  fetch(pe_n, on && 0 < vn);
+  pe_n = pe_at(1);
   for (int k = 0; k < nmax; ++k) {
     const bool act = on && k < vn;
-    const int pe = par[act ? vb + k : rec0[0]];
-    const double v0 = T.exp_u[3 * pe], v1 = T.exp_u[3 * pe + 1], v2 = T.exp_u[3 * pe + 2];
+    const double v0 = nv0, v1 = nv1, v2 = nv2;
     C2<R> in[L], out[L];
 #pragma unroll
-    for (int r = 0; r < L; ++r) in[r] = {(R)0, (R)0};
+    for (int r = 0; r < L; ++r) in[r] = act ? nraw[r] : C2<R>{(R)0, (R)0};
+    if (k + 1 < nmax) {
+      fetch(pe_n, on && k + 1 < vn);
+      pe_n = pe_at(k + 2);
+    }
     if (act) {
       // x-pencil (k_y, k_z) of the father, times exp(-i kappa hp <k, v> / (L-1))
-      const C2<R>* src = Lx + (int64_t)pe * L3 + p * L;
       C2<R> ph[L];
       phase_run<R, L>(-kf * (v1 * a0 + v2 * a1), -kf * v0, ph);
 #pragma unroll
-      for (int r = 0; r < L; ++r) in[r] = cmul(src[r], ph[r]);
+      for (int r = 0; r < L; ++r) in[r] = cmul(in[r], ph[r]);
     }
+    // the son-node phases exp(i kappa hc <b + h / (L-1), v>) as
+    // exp(i kappa hc <h / (L-1), v>) (ph0, along the z-pencil) times
+    // exp(i kappa hc v_d) for each axis d whose half b_d is 1, the latter
+    // applied to the mode product of that axis (scalars commute with them)
+    const C2<R> cx = expi_turns<R>(ks * v0), cy = expi_turns<R>(ks * v1), cz = expi_turns<R>(ks * v2);
 #pragma unroll
     for (int bx = 0; bx < 2; ++bx) {
       if (!need_x[bx]) continue;
@@ -861,7 +885,7 @@ __global__ __launch_bounds__(64) void k_l2l_f(int64_t npair, const int32_t* __re
       else son_mode<R, L, 0, true>(in, out);
       if (act) {
 #pragma unroll
-        for (int l = 0; l < L; ++l) sx[hf][bx][(l + L * a1) * L + a0] = out[l];
+        for (int l = 0; l < L; ++l) sx[hf][bx][(l + L * a1) * L + a0] = bx ? cmul(out[l], cx) : out[l];
       }
     }
     __syncthreads();
@@ -879,15 +903,16 @@ __global__ __launch_bounds__(64) void k_l2l_f(int64_t npair, const int32_t* __re
         else son_mode<R, L, 0, true>(in, out);
         if (act) {
 #pragma unroll
-          for (int l = 0; l < L; ++l) sy[hf][bx + 2 * by][(a0 + L * l) * L + a1] = out[l];
+          for (int l = 0; l < L; ++l) sy[hf][bx + 2 * by][(a0 + L * l) * L + a1] = by ? cmul(out[l], cy) : out[l];
         }
       }
     }
     __syncthreads();
+    C2<R> ph0[L];
+    phase_run<R, L>(ks * (v0 * a0 + v1 * a1) / (L - 1), ks * v2 / (L - 1), ph0);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       if (!need_y[q]) continue;
-      const int bx = q & 1, by = q >> 1;
       if (act) {  // z-pencil (l_x, l_y) = (a0, a1)
 #pragma unroll
         for (int r = 0; r < L; ++r) in[r] = sy[hf][q][p * L + r];
@@ -899,12 +924,8 @@ __global__ __launch_bounds__(64) void k_l2l_f(int64_t npair, const int32_t* __re
         if (bz) son_mode<R, L, 1, true>(in, out);
         else son_mode<R, L, 0, true>(in, out);
         if (act && se[o] >= 0) {
-          // son-node phases exp(i kappa hc <b + h / (L-1), v>), z-pencil (h_x, h_y)
-          C2<R> ph[L];
-          phase_run<R, L>(ks * (v0 * (bx + (double)a0 / (L - 1)) + v1 * (by + (double)a1 / (L - 1)) + v2 * bz),
-                          ks * v2 / (L - 1), ph);
 #pragma unroll
-          for (int l = 0; l < L; ++l) cfma(acc[o][l], out[l], ph[l]);
+          for (int l = 0; l < L; ++l) cfma(acc[o][l], bz ? cmul(out[l], cz) : out[l], ph0[l]);
         }
       }
     }
