@@ -466,7 +466,7 @@ defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int
       P.l2l[l].npair = (int64_t)pr.size() / pencil_epw_host(P.L);
       P.l2l[l].pair = upload(P, pr);
       std::vector<int32_t> fam, fcell;
-      if (l2l_families(H, l, fam, fcell)) {
+      if (P.L <= kL2LFamilyMaxL && l2l_families(H, l, fam, fcell)) {
         std::vector<int32_t> fp = pencil_pairs(fcell, P.L);
         P.l2l[l].nfpair = (int64_t)fp.size() / pencil_epw_host(P.L);
         P.l2l[l].fpair = upload(P, fp);
