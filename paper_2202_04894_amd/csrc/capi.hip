@@ -1093,11 +1093,23 @@ defmm_status defmm_workspace_pass_work(const defmm_workspace* ws, double* bytes,
   for (int32_t e : H.p2m_exp) npts += H.ty->count[H.ty->exp_cell[e]];
   b[kPassP2M] = npts * (24 + cs) + (double)P.n_p2m * cs * L3;
   f[kPassP2M] = npts * L3 * 8;
-  double nm2m = 0, nm2m_child = 0;
-  for (const auto& v : H.m2m_par) nm2m += (double)v.size();
-  for (const auto& v : H.m2m_child)
-    for (int32_t c : v) nm2m_child += c >= 0;
-  b[kPassM2M] = (nm2m + nm2m_child) * cs * L3;
+  // M2M: each son expansion that feeds a father read once (one feeds every
+  // father direction it serves), each father written once
+  double nm2m = 0, nm2m_child = 0, nm2m_son = 0;
+  {
+    std::vector<uint8_t> seen((size_t)std::max<int64_t>(H.ty->nexp(), 1), 0);
+    for (const auto& v : H.m2m_par) nm2m += (double)v.size();
+    for (const auto& v : H.m2m_child)
+      for (int32_t c : v)
+        if (c >= 0) {
+          nm2m_child += 1;
+          if (!seen[c]) {
+            seen[c] = 1;
+            nm2m_son += 1;
+          }
+        }
+  }
+  b[kPassM2M] = (nm2m + nm2m_son) * cs * L3;
   f[kPassM2M] = nm2m_child * 8 * (3 * L3 * L + 2 * L3);
   const double f2l_per_tgt = 8 * (Pp * Pp * L * Pp + Pp * L * L * Pp + L3 * Pp);
   const double m2f_per_row = 8 * (Pp * L * L * L + Pp * Pp * L * L + P3 * L);
@@ -1132,11 +1144,23 @@ defmm_status defmm_workspace_pass_work(const defmm_workspace* ws, double* bytes,
       f[kPassF2L] += n_tgt * f2l_per_tgt;
     }
   }
-  double nl2l = 0;
-  for (const auto& v : H.l2l_par) nl2l += (double)v.size();
+  // L2L: each father expansion that feeds a son read once, each son read and
+  // written once
+  double nl2l = 0, nl2l_par = 0;
+  {
+    std::vector<uint8_t> seen((size_t)std::max<int64_t>(H.tx.nexp(), 1), 0);
+    for (const auto& v : H.l2l_par) {
+      nl2l += (double)v.size();
+      for (int32_t e : v)
+        if (!seen[e]) {
+          seen[e] = 1;
+          nl2l_par += 1;
+        }
+    }
+  }
   double nl2l_ch = 0;
   for (const auto& v : H.l2l_ch) nl2l_ch += (double)v.size();
-  b[kPassL2L] = (nl2l + 2 * nl2l_ch) * cs * L3;
+  b[kPassL2L] = (nl2l_par + 2 * nl2l_ch) * cs * L3;
   f[kPassL2L] = nl2l * 8 * (3 * L3 * L + 3 * L3);
   // per pair: 3 differences, 5 for r^2, rsqrt, r, kappa r, then sin, cos, 2 scalings
   // and a complex multiply-add (8), or, screened, exp, 1 scaling and a real-by-
