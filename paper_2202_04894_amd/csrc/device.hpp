@@ -73,9 +73,9 @@ struct LevelTable {  // per-level operator table on the device
 // An L2L family record: [0] first of its father expansions in the level's
 // parent list, [1] their number, [2 + o] the son expansion at octant o or -1.
 constexpr int kFamWords = 16;
-// Largest order the family L2L serves: its eight sons' sums stay in registers
-// (166 VGPRs at L = 5, three waves per SIMD; at L = 6, 180 VGPRs and two
-// waves per SIMD made it slower than the kernel per son expansion).
+// Largest order the family L2L serves: four sons' sums stay in registers at
+// a time (128 VGPRs at L = 5, four waves per SIMD; at L = 6 the kernel per
+// son expansion was faster).
 constexpr int kL2LFamilyMaxL = 5;
 
 struct DevPlan {

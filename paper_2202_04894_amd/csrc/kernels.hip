@@ -784,22 +784,23 @@ __global__ __launch_bounds__(64) void k_l2l_p(int64_t npair, const int32_t* __re
 
 // L2L by families (the complex64 pencil path): a half wave serves one family,
 // the son expansions u_o (octant o) of one father cell that the same father
-// expansions v feed, and takes each v once for all of them.  Per v: the
-// father's values as x-pencils times the father-node phases, then the mode
-// products with the transposed son matrices shared between sons: one x-mode
-// product per half bx, one y-mode product per (bx, by), one z-mode product
-// per son (14 for 8 sons instead of 24), each son's result times its
-// son-node phases exp(i kappa <x'_h - a_t, v>) added to the son's sum in
-// registers.  Both families of a wave have the same father cell; the branches
-// over octants follow the union of their sons, so they are uniform.
+// expansions v feed, and takes each v once for all of them in each of two
+// passes (one per son half bx, whose four sons' sums stay in registers).  Per
+// v and pass: the father's values as x-pencils times the father-node phases,
+// then the mode products with the transposed son matrices shared between
+// sons: the x-mode product of the half, one y-mode product per by, one z-mode
+// product per son (14 for 8 sons instead of 24), each son's result times its
+// son-node phases exp(i kappa <x'_h - a_t, v>) added to the son's sum.  Both
+// families of a wave have the same father cell; the branches over octants
+// follow the union of their sons, so they are uniform.
 template <typename R, int L>
 __global__ __launch_bounds__(64) void k_l2l_f(int64_t npair, const int32_t* __restrict__ pairs,
                                               const int32_t* __restrict__ fam, const int32_t* __restrict__ par,
                                               const uint8_t* __restrict__ has_m2l, TreeView T, Geo g,
                                               C2<R>* __restrict__ Lx) {
   constexpr int L2 = L * L, L3 = L2 * L, EPW = pencil_epw<L>(), HW = 64 / EPW;
-  __shared__ C2<R> sx[EPW][2][L3];  // x-mode results by bx, [l_x][k_z][k_y]
-  __shared__ C2<R> sy[EPW][4][L3];  // y-mode results by bx + 2 by, [l_x][l_y][k_z]
+  __shared__ C2<R> sx[EPW][L3];     // the x-mode result, [l_x][k_z][k_y]
+  __shared__ C2<R> sy[EPW][2][L3];  // y-mode results by by, [l_x][l_y][k_z]
   const int64_t w = blockIdx.x;
   if (w >= npair) return;
   const int lane = threadIdx.x, hf = lane / HW, p = lane % HW;
@@ -834,67 +835,66 @@ __global__ __launch_bounds__(64) void k_l2l_f(int64_t npair, const int32_t* __re
   constexpr double inv2pi = 0.15915494309189533577;
   const double kf = g.kappa * hp / (L - 1) * inv2pi, ks = g.kappa * hcs * inv2pi;
   const int a0 = p % L, a1 = (p / L) % L;
-  C2<R> acc[8][L];
+  // the sons in two passes over the fathers, one per half bx: a pass holds
+  // the sums of its four sons in registers
 #pragma unroll
-  for (int o = 0; o < 8; ++o)
+  for (int bx = 0; bx < 2; ++bx) {
+    if (!need_x[bx]) continue;
+    C2<R> acc[4][L];  // son bx + 2 q, q = by + 2 bz
 #pragma unroll
-    for (int l = 0; l < L; ++l) acc[o][l] = {(R)0, (R)0};
-  // the father expansions one ahead (their indices two ahead)
-  auto pe_at = [&](int j) { return par[on && j < vn ? vb + j : rec0[0]]; };
-  int pe_n = pe_at(0);
-  double nv0 = 0, nv1 = 0, nv2 = 0;
-  C2<R> nraw[L];
-  auto fetch = [&](int pe, bool a) {
-    nv0 = T.exp_u[3 * pe];
-    nv1 = T.exp_u[3 * pe + 1];
-    nv2 = T.exp_u[3 * pe + 2];
-    if (a) {
-      const C2<R>* src = Lx + (int64_t)pe * L3 + p * L;
+    for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int r = 0; r < L; ++r) nraw[r] = src[r];
-    }
-  };
-  fetch(pe_n, on && 0 < vn);
-  pe_n = pe_at(1);
-  for (int k = 0; k < nmax; ++k) {
-    const bool act = on && k < vn;
-    const double v0 = nv0, v1 = nv1, v2 = nv2;
-    C2<R> in[L], out[L];
+      for (int l = 0; l < L; ++l) acc[q][l] = {(R)0, (R)0};
+    // the father expansions one ahead (their indices two ahead)
+    auto pe_at = [&](int j) { return par[on && j < vn ? vb + j : rec0[0]]; };
+    int pe_n = pe_at(0);
+    double nv0 = 0, nv1 = 0, nv2 = 0;
+    C2<R> nraw[L];
+    auto fetch = [&](int pe, bool a) {
+      nv0 = T.exp_u[3 * pe];
+      nv1 = T.exp_u[3 * pe + 1];
+      nv2 = T.exp_u[3 * pe + 2];
+      if (a) {
+        const C2<R>* src = Lx + (int64_t)pe * L3 + p * L;
 #pragma unroll
-    for (int r = 0; r < L; ++r) in[r] = act ? nraw[r] : C2<R>{(R)0, (R)0};
-    if (k + 1 < nmax) {
-      fetch(pe_n, on && k + 1 < vn);
-      pe_n = pe_at(k + 2);
-    }
-    if (act) {
-      // x-pencil (k_y, k_z) of the father, times exp(-i kappa hp <k, v> / (L-1))
-      C2<R> ph[L];
-      phase_run<R, L>(-kf * (v1 * a0 + v2 * a1), -kf * v0, ph);
+        for (int r = 0; r < L; ++r) nraw[r] = src[r];
+      }
+    };
+    fetch(pe_n, on && 0 < vn);
+    pe_n = pe_at(1);
+    for (int k = 0; k < nmax; ++k) {
+      const bool act = on && k < vn;
+      const double v0 = nv0, v1 = nv1, v2 = nv2;
+      C2<R> in[L], out[L];
 #pragma unroll
-      for (int r = 0; r < L; ++r) in[r] = cmul(in[r], ph[r]);
-    }
-    // the son-node phases exp(i kappa hc <b + h / (L-1), v>) as
-    // exp(i kappa hc <h / (L-1), v>) (ph0, along the z-pencil) times
-    // exp(i kappa hc v_d) for each axis d whose half b_d is 1, the latter
-    // applied to the mode product of that axis (scalars commute with them)
-    const C2<R> cx = expi_turns<R>(ks * v0), cy = expi_turns<R>(ks * v1), cz = expi_turns<R>(ks * v2);
+      for (int r = 0; r < L; ++r) in[r] = act ? nraw[r] : C2<R>{(R)0, (R)0};
+      if (k + 1 < nmax) {
+        fetch(pe_n, on && k + 1 < vn);
+        pe_n = pe_at(k + 2);
+      }
+      if (act) {
+        // x-pencil (k_y, k_z) of the father, times exp(-i kappa hp <k, v> / (L-1))
+        C2<R> ph[L];
+        phase_run<R, L>(-kf * (v1 * a0 + v2 * a1), -kf * v0, ph);
 #pragma unroll
-    for (int bx = 0; bx < 2; ++bx) {
-      if (!need_x[bx]) continue;
+        for (int r = 0; r < L; ++r) in[r] = cmul(in[r], ph[r]);
+      }
+      // the son-node phases exp(i kappa hc <b + h / (L-1), v>) as
+      // exp(i kappa hc <h / (L-1), v>) (ph0, along the z-pencil) times
+      // exp(i kappa hc v_d) for each axis d whose half b_d is 1, the latter
+      // applied to the mode product of that axis (scalars commute with them)
+      const C2<R> cx = expi_turns<R>(ks * v0), cy = expi_turns<R>(ks * v1), cz = expi_turns<R>(ks * v2);
       if (bx) son_mode<R, L, 1, true>(in, out);
       else son_mode<R, L, 0, true>(in, out);
+      __syncthreads();
       if (act) {
 #pragma unroll
-        for (int l = 0; l < L; ++l) sx[hf][bx][(l + L * a1) * L + a0] = bx ? cmul(out[l], cx) : out[l];
+        for (int l = 0; l < L; ++l) sx[hf][(l + L * a1) * L + a0] = bx ? cmul(out[l], cx) : out[l];
       }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int bx = 0; bx < 2; ++bx) {
-      if (!need_x[bx]) continue;
+      __syncthreads();
       if (act) {  // y-pencil (l_x, k_z) = (a0, a1)
 #pragma unroll
-        for (int r = 0; r < L; ++r) in[r] = sx[hf][bx][p * L + r];
+        for (int r = 0; r < L; ++r) in[r] = sx[hf][p * L + r];
       }
 #pragma unroll
       for (int by = 0; by < 2; ++by) {
@@ -903,44 +903,45 @@ __global__ __launch_bounds__(64) void k_l2l_f(int64_t npair, const int32_t* __re
         else son_mode<R, L, 0, true>(in, out);
         if (act) {
 #pragma unroll
-          for (int l = 0; l < L; ++l) sy[hf][bx + 2 * by][(a0 + L * l) * L + a1] = by ? cmul(out[l], cy) : out[l];
+          for (int l = 0; l < L; ++l) sy[hf][by][(a0 + L * l) * L + a1] = by ? cmul(out[l], cy) : out[l];
+        }
+      }
+      __syncthreads();
+      C2<R> ph0[L];
+      phase_run<R, L>(ks * (v0 * a0 + v1 * a1) / (L - 1), ks * v2 / (L - 1), ph0);
+#pragma unroll
+      for (int by = 0; by < 2; ++by) {
+        if (!need_y[bx + 2 * by]) continue;
+        if (act) {  // z-pencil (l_x, l_y) = (a0, a1)
+#pragma unroll
+          for (int r = 0; r < L; ++r) in[r] = sy[hf][by][p * L + r];
+        }
+#pragma unroll
+        for (int bz = 0; bz < 2; ++bz) {
+          const int o = bx + 2 * by + 4 * bz;
+          if (!pres[o]) continue;
+          if (bz) son_mode<R, L, 1, true>(in, out);
+          else son_mode<R, L, 0, true>(in, out);
+          if (act && se[o] >= 0) {
+#pragma unroll
+            for (int l = 0; l < L; ++l) cfma(acc[by + 2 * bz][l], bz ? cmul(out[l], cz) : out[l], ph0[l]);
+          }
         }
       }
     }
-    __syncthreads();
-    C2<R> ph0[L];
-    phase_run<R, L>(ks * (v0 * a0 + v1 * a1) / (L - 1), ks * v2 / (L - 1), ph0);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      if (!need_y[q]) continue;
-      if (act) {  // z-pencil (l_x, l_y) = (a0, a1)
+      const int o = bx + 2 * q;
+      if (!pres[o]) continue;
+      if (on && se[o] >= 0) {
+        // added to what M2L wrote (an M2L target), else the son's only contribution
+        C2<R>* dst = Lx + (int64_t)se[o] * L3 + p;
+        const bool add = has_m2l[se[o]] != 0;
 #pragma unroll
-        for (int r = 0; r < L; ++r) in[r] = sy[hf][q][p * L + r];
-      }
-#pragma unroll
-      for (int bz = 0; bz < 2; ++bz) {
-        const int o = q + 4 * bz;
-        if (!pres[o]) continue;
-        if (bz) son_mode<R, L, 1, true>(in, out);
-        else son_mode<R, L, 0, true>(in, out);
-        if (act && se[o] >= 0) {
-#pragma unroll
-          for (int l = 0; l < L; ++l) cfma(acc[o][l], bz ? cmul(out[l], cz) : out[l], ph0[l]);
+        for (int l = 0; l < L; ++l) {
+          const C2<R> cur = add ? dst[L2 * l] : C2<R>{(R)0, (R)0};
+          dst[L2 * l] = {cur.x + acc[q][l].x, cur.y + acc[q][l].y};
         }
-      }
-    }
-  }
-#pragma unroll
-  for (int o = 0; o < 8; ++o) {
-    if (!pres[o]) continue;
-    if (on && se[o] >= 0) {
-      // added to what M2L wrote (an M2L target), else the son's only contribution
-      C2<R>* dst = Lx + (int64_t)se[o] * L3 + p;
-      const bool add = has_m2l[se[o]] != 0;
-#pragma unroll
-      for (int l = 0; l < L; ++l) {
-        const C2<R> cur = add ? dst[L2 * l] : C2<R>{(R)0, (R)0};
-        dst[L2 * l] = {cur.x + acc[o][l].x, cur.y + acc[o][l].y};
       }
     }
   }
