@@ -73,10 +73,10 @@ struct LevelTable {  // per-level operator table on the device
 // An L2L family record: [0] first of its father expansions in the level's
 // parent list, [1] their number, [2 + o] the son expansion at octant o or -1.
 constexpr int kFamWords = 16;
-// Largest order the family L2L serves: four sons' sums stay in registers at
-// a time (128 VGPRs at L = 5, four waves per SIMD; at L = 6 the kernel per
-// son expansion was faster).
-constexpr int kL2LFamilyMaxL = 5;
+// Largest order the family L2L serves (measured faster than the kernel per
+// son expansion at L = 5 and 6; four sons' sums in registers at a time: 128
+// VGPRs at L = 5, four waves per SIMD, 140 at L = 6, three).
+constexpr int kL2LFamilyMaxL = 6;
 
 struct DevPlan {
   HostPlan host;   // kept for introspection and stats

@@ -132,8 +132,11 @@ def test_leaves_beyond_one_wave():
         assert_close(p0, ref, tol, (prec, "updown 0", rel(p0, ref)))
 
 
-@pytest.mark.parametrize("geom,n,kappa,kw", FMM_CASES[:3])
+@pytest.mark.parametrize("geom,n,kappa,kw", FMM_CASES)
 def test_c64_matches_oracle(geom, n, kappa, kw):
+    """complex64 against the oracle at every order of the cases (the family
+    L2L serves complex64 up to L = 6, the per-son kernel beyond), potentials
+    and every expansion element by element."""
     defmm = _defmm()
     X = W.GENERATORS[geom](n, 101)
     q = W.charges(n, 102)
