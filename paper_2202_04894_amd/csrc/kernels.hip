@@ -241,11 +241,18 @@ __global__ void k_zero(int64_t n, C2<R>* __restrict__ a) {
   if (i < n) a[i] = {(R)0, (R)0};
 }
 
-// Clears rows of `len` values: row rows[i] of a, for i < n.
-template <typename R>
-__global__ void k_zero_rows(int64_t n, int len, const int32_t* __restrict__ rows, C2<R>* __restrict__ a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n * len) a[(int64_t)rows[i / len] * len + i % len] = {(R)0, (R)0};
+// Clears rows of LEN values: row rows[i] of a, for i < n.  A workgroup clears
+// kZeroRowsPerBlock consecutive rows of the list, consecutive threads on
+// consecutive values (a row's index divides by a compile-time length).
+constexpr int kZeroRowsPerBlock = 8;
+template <typename R, int LEN>
+__global__ __launch_bounds__(256) void k_zero_rows(int64_t n, const int32_t* __restrict__ rows,
+                                                   C2<R>* __restrict__ a) {
+  const int64_t r0 = (int64_t)blockIdx.x * kZeroRowsPerBlock;
+  for (int k = threadIdx.x; k < kZeroRowsPerBlock * LEN; k += 256) {
+    const int q = k / LEN, c = k - q * LEN;
+    if (r0 + q < n) a[(int64_t)rows[r0 + q] * LEN + c] = {(R)0, (R)0};
+  }
 }
 
 // ------------------------------------------------------------------ spectra
@@ -2346,8 +2353,9 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
   if (P.tx.nexp > 0 && !W.pencil_updown)
     hipLaunchKernelGGL((k_zero<R>), dim3(blocks_for(P.tx.nexp * L3, 256)), dim3(256), 0, s, P.tx.nexp * L3, Lx);
   else if (P.n_zero_exp > 0)
-    hipLaunchKernelGGL((k_zero_rows<R>), dim3(blocks_for(P.n_zero_exp * L3, 256)), dim3(256), 0, s, P.n_zero_exp,
-                       L3, P.zero_exp, Lx);
+    DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_zero_rows<R, LL * LL * LL>),
+                                          dim3(blocks_for(P.n_zero_exp, kZeroRowsPerBlock)), dim3(256), 0, s,
+                                          P.n_zero_exp, P.zero_exp, Lx));
   tm.end();
 
   // Near field on the workspace's side stream, concurrently with the far
