@@ -1490,8 +1490,9 @@ template <typename R, int L, int NSL, bool SYM>
 __global__ __launch_bounds__(64) void k_m2l_runs(int64_t ngrp, const int32_t* __restrict__ grp_tfirst,
                                                  const int32_t* __restrict__ grp_tcount,
                                                  const int32_t* __restrict__ run_begin, const int32_t* __restrict__ runs,
-                                                 const uint8_t* __restrict__ perm, const C2<R>* __restrict__ Mt,
-                                                 const C2<R>* __restrict__ S, C2<R>* __restrict__ Lt) {
+                                                 const uint8_t* __restrict__ perm, const int32_t* __restrict__ freq,
+                                                 const C2<R>* __restrict__ Mt, const C2<R>* __restrict__ S,
+                                                 C2<R>* __restrict__ Lt) {
   constexpr int P3R = fourier_row(L), SL = P3R / NSL, NP = SL / 2, G = 8, RS = kRunWords;
   static_assert(SL % 2 == 0 && NP <= 64, "a slice holds at most 64 frequency pairs");
   constexpr int U = m2l_run_batch<R>();  // runs per batch
@@ -1502,10 +1503,13 @@ __global__ __launch_bounds__(64) void k_m2l_runs(int64_t ngrp, const int32_t* __
   if (!slice_item(NSL, ngrp, slice, g)) return;
   const int lane = threadIdx.x;
   const uint8_t* pt = SYM ? load_slice_perm(perm, slice, ptab) : nullptr;
-  const bool ok = lane < NP;
   const int s0 = slice * SL;
-  const int fl = ok ? s0 + 2 * lane : s0;
-  const uint32_t lb = (uint32_t)fl * sizeof(C2<R>), sb = (uint32_t)s0 * sizeof(C2<R>);
+  const int fl = lane < NP ? s0 + 2 * lane : s0;
+  // a pair of padding entries (the row's tail) is neither read nor written:
+  // its lane offset lies past every row, where buffer loads return zeros
+  // without a memory access
+  const bool ok = lane < NP && (freq[fl] >= 0 || freq[fl + 1] >= 0);
+  const uint32_t lb = ok ? (uint32_t)fl * sizeof(C2<R>) : RB, sb = (uint32_t)s0 * sizeof(C2<R>);
   C2x2<R> acc[G];
 #pragma unroll
   for (int t = 0; t < G; ++t) acc[t] = C2x2<R>{{(R)0, (R)0}, {(R)0, (R)0}};
@@ -2488,12 +2492,12 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
         DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_runs<R, LL, m2l_slices(LL), true>),
                                              dim3(xcd_grid(m2l_slices(LL) * ng)), dim3(64), 0, s, ng,
                                              P.grp_tfirst + gb, P.grp_tcount + gb, P.grp_run_begin + gb, P.runs,
-                                             P.perm, (const C2<R>*)Mt, S, Lt));
+                                             P.perm, P.freq, (const C2<R>*)Mt, S, Lt));
       } else {
         DEFMM_L_SWITCH(L, hipLaunchKernelGGL((k_m2l_runs<R, LL, m2l_slices(LL), false>),
                                              dim3(xcd_grid(m2l_slices(LL) * ng)), dim3(64), 0, s, ng,
                                              P.grp_tfirst + gb, P.grp_tcount + gb, P.grp_run_begin + gb, P.runs,
-                                             P.perm, (const C2<R>*)Mt, S, Lt));
+                                             P.perm, P.freq, (const C2<R>*)Mt, S, Lt));
       }
     } else {
       if (P.sym) {
