@@ -493,6 +493,9 @@ defmm_status defmm_plan_create(const double* X, int64_t nx, const double* Y, int
       FourierLayout F = make_fourier_layout(P.L, m2l_slices(P.L), fourier_cap(P.L));
       if (F.row != fourier_row(P.L)) throw std::logic_error("fourier layout: row length mismatch");
       P.freq = upload(P, F.freq);
+      P.live_pairs = 0;
+      for (size_t i = 0; i < F.freq.size(); ++i)
+        if (F.freq[i] >= 0) P.live_pairs = (int32_t)(i / 2 + 1);
       P.perm = upload(P, F.perm);
     }
     P.sym = H.compressed;

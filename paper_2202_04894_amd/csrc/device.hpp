@@ -133,6 +133,7 @@ struct DevPlan {
   int64_t n_spec = 0;
   bool sym = false;
   int32_t* freq = nullptr;  // Fourier layout: frequency at each row position (-1 = padding)
+  int32_t live_pairs = 0;   // entry pairs of a row up to the last one holding a frequency
   uint8_t* perm = nullptr;  // Fourier layout: [slices][48][64] pair permutation per symmetry code
   std::vector<void*> allocs;
   size_t resident_bytes = 0;

@@ -1583,8 +1583,8 @@ __global__ __launch_bounds__(64) void k_m2l_runs(int64_t ngrp, const int32_t* __
 // Targets in XCD-aware order, G per workgroup.
 template <typename R, int L, int G>
 __global__ __launch_bounds__(256) void k_f2l(int64_t ntgt, const int32_t* __restrict__ tgt,
-                                             const int32_t* __restrict__ freq, const C2<R>* __restrict__ Lt,
-                                             C2<R>* __restrict__ Lx) {
+                                             const int32_t* __restrict__ freq, int live_pairs,
+                                             const C2<R>* __restrict__ Lt, C2<R>* __restrict__ Lx) {
   constexpr int P = 2 * L - 1, P3 = P * P * P, L2 = L * L, L3 = L2 * L, NT = 256;
   constexpr int RW = fourier_row(L);
   constexpr int SA = P3 > P * L2 ? P3 : P * L2;  // the full grid, then the y-stage output
@@ -1599,20 +1599,21 @@ __global__ __launch_bounds__(256) void k_f2l(int64_t ntgt, const int32_t* __rest
   const int ng = (int)min((int64_t)G, ntgt - i0);
   const int tid = threadIdx.x;
   // the G rows are contiguous: every load (two entries per thread) is issued
-  // before the first LDS write
+  // before the first LDS write; the pairs of the row's padding tail (past
+  // live_pairs) are not loaded
   constexpr int RW2 = RW / 2, NV = (G * RW2 + NT - 1) / NT;
   C2x2<R> v[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     const int w = tid + k * NT;
-    if (w < ng * RW2) v[k] = reinterpret_cast<const C2x2<R>*>(Lt + i0 * RW)[w];
+    if (w < ng * RW2 && w % RW2 < live_pairs) v[k] = reinterpret_cast<const C2x2<R>*>(Lt + i0 * RW)[w];
   }
   for (int p = tid; p < RW; p += NT) fq[p] = freq[p];
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
     const int w = tid + k * NT;
-    if (w < ng * RW2) {
+    if (w < ng * RW2 && w % RW2 < live_pairs) {
       const int g = w / RW2, p = 2 * (w % RW2);
       const int f0 = fq[p], f1 = fq[p + 1];
       if (f0 >= 0) A[g][f0] = v[k].a;
@@ -2521,7 +2522,7 @@ static hipError_t matvec_impl(DevPlan& P, Workspace& W, const void* q, void* p, 
       if (nt == 0) continue;
       DEFMM_L_SWITCH(L, DEFMM_G_SWITCH(W.fourier_items, R, LL, hipLaunchKernelGGL((k_f2l<R, LL, GG>),
                                        dim3(xcd_grid((nt + GG - 1) / GG)), dim3(256), 0, s, nt, P.m2l_tgt + tb,
-                                       P.freq, (const C2<R>*)(Lt + tb * P3R), Lx)));
+                                       P.freq, P.live_pairs, (const C2<R>*)(Lt + tb * P3R), Lx)));
     }
   tm.end();
 
